@@ -1,0 +1,208 @@
+/*
+ * bdg.h -- C-ABI of the MI355X (gfx950) dense BdG eigensolver library.
+ *
+ * The library diagonalises the quasiparticle Hamiltonian of the static
+ * SLDA/BdG problem (Wlazlowski et al., arXiv:2310.03341, eq. stHpsi with the
+ * block form of eq. TDSLDA):
+ *
+ *     H = [[ h, Delta ], [ Delta^*, -h^* ]],   h = -(1/2) nabla^2 + U(r) - mu,
+ *
+ * on a periodic Nx x Ny x Nz grid with unit spacing and hbar = m = 1, the
+ * kinetic term being the spectral operator F^-1 (k^2/2) F over the momenta
+ * k = 2 pi n / N, n = -N/2 .. N/2-1 ("Numerical setup and implementation").
+ * The matrix has order n = 2 Nx Ny Nz; a quasiparticle wavefunction is the
+ * vector [u; v] with the site index r = x + Nx (y + Ny z) (x fastest).
+ *
+ * The eigensolver is the two-stage direct method that the paper's ELPA runs
+ * use ("Performance of the Matrix Diagonalization Algorithm"): dense ->
+ * Hermitian band (blocked Householder), band -> real tridiagonal (bulge
+ * chasing), tridiagonal divide and conquer, and the two back-transformations
+ * of the eigenvectors.  Only eigenpairs inside a closed energy window
+ * [emin, emax] are returned (the densities of eq. densities2 sum over the
+ * window 0 < E_n < E_c with E_c = pi^2/2, "Methods").
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers owned by the caller; the library
+ *     never frees them and never keeps them after the call returns.
+ *   - Complex arrays are complex128 (or complex64 where stated) interleaved
+ *     (re, im); matrices are column-major with a leading dimension >= rows.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = legacy default
+ *     stream) and is asynchronous unless stated otherwise.
+ *   - Return value: BDG_OK (0) or a status below; a negative value -i means
+ *     argument i (1-based) is invalid.  bdg_last_error() gives a message.
+ *   - Thread-compatible: concurrent calls need distinct streams and distinct
+ *     workspaces.
+ */
+#ifndef BDG_H
+#define BDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+#define BDG_OK 0
+#define BDG_ERR_NOCONV 1          /* secular-equation / iteration failure       */
+#define BDG_ERR_REFINE_TOL 2      /* refinement missed refine_tol (result valid) */
+#define BDG_ERR_HIP 3             /* HIP runtime error                          */
+#define BDG_ERR_WORKSPACE 4       /* workspace or output capacity too small     */
+#define BDG_ERR_NOT_IMPLEMENTED 5 /* option not supported                       */
+#define BDG_ERR_NONFINITE 6       /* NaN/Inf found in the input matrix          */
+
+typedef void *bdg_stream_t; /* hipStream_t */
+
+/* Periodic lattice; dims[d] for d < ndim, unit spacing, x fastest. */
+typedef struct {
+    int32_t ndim;    /* 1, 2 or 3 */
+    int32_t dims[3]; /* each even and >= 2 */
+} bdg_lattice;
+
+/* Arithmetic of the reduction stages. */
+#define BDG_FP64 0         /* all stages in FP64                                  */
+#define BDG_FP32_REFINED 1 /* band reduction + back-transforms in FP32 on MFMA,
+                              tridiagonal solve in FP64, then FP64 refinement     */
+
+typedef struct {
+    int32_t precision;       /* BDG_FP64 or BDG_FP32_REFINED                     */
+    int32_t band;            /* half-bandwidth of stage 1 (0 = default 64)      */
+    int32_t refine_max_iter; /* refinement sweeps for BDG_FP32_REFINED (0 = 3)  */
+    double refine_tol;       /* residual target, relative to ||H||_2 (0=1e-13)  */
+    int32_t dc_leaf;         /* divide-and-conquer leaf size (0 = default 32)   */
+    int32_t ph_mirror;       /* 1: back-transform only E >= 0 vectors and build
+                                the E < 0 ones as (-v^*, u^*) (particle-hole
+                                symmetry of a BdG matrix with real h and local
+                                Delta); 0: back-transform every vector          */
+} bdg_opts;
+
+/* Per-call accuracy and timing report (filled when non-NULL). */
+typedef struct {
+    double max_resid;     /* max_j ||H z_j - w_j z_j||_2 / max|w| (when checked) */
+    double gram_defect;   /* max_ij |(Z^H Z - I)_ij|              (when checked) */
+    double eig_shift_max; /* largest eigenvalue change made by refinement        */
+    int32_t refine_iters; /* refinement sweeps performed                         */
+    int32_t pad;
+    double stage_ms[8];   /* he2hb, hb2st, stedc, bt2, bt1, refine, select, total */
+} bdg_err_report;
+
+/*
+ * bdg_assemble -- dense BdG matrix H of eq. (stHpsi) on the lattice `lat`.
+ *   U     [nsites] real potential U(r) (device, f64).
+ *   Delta [nsites] complex pairing field Delta(r) (device, complex128).
+ *   mu    chemical potential (enters h as -mu, "Methods", mean-field h).
+ *   H     [ldh x n] output (device, complex128), n = 2*nsites; both triangles
+ *         are written.  ldh >= n.
+ * The kinetic block uses the closed form of F^-1 (k^2/2) F on the paper's
+ * momentum grid; the v-block is -conj(h) and the off-diagonal blocks are
+ * diag(Delta) (upper right) and diag(conj Delta) (lower left).
+ */
+int bdg_assemble(const bdg_lattice *lat, const double *U, const double *Delta, double mu,
+                 double *H, int64_t ldh, bdg_stream_t stream);
+
+/*
+ * bdg_eigh_workspace -- device workspace (bytes) that bdg_eigh needs for order n.
+ */
+int bdg_eigh_workspace(int64_t n, const bdg_opts *opts, size_t *bytes);
+
+/*
+ * bdg_eigh -- eigenpairs of the Hermitian matrix A with eigenvalues in the
+ * closed window [emin, emax] (use -INFINITY/INFINITY for the full spectrum).
+ *   n         order of A (>= 1).
+ *   A         [lda x n] complex128 Hermitian; only the lower triangle is read.
+ *             DESTROYED (holds the stage-1 reflectors on exit).
+ *   W         [n] f64 output; W[0..m) are the selected eigenvalues, ascending.
+ *             W[m..n) is scratch.
+ *   Z         [ldz x zcols] complex128 output; Z[:, 0..m) the eigenvectors.
+ *   zcols     column capacity of Z; if m > zcols, BDG_ERR_WORKSPACE is
+ *             returned and *m holds the count.
+ *   m         output: number of eigenpairs in the window (host pointer).
+ *   opts      options (NULL = defaults, FP64).
+ *   work      device workspace of work_bytes >= bdg_eigh_workspace(n, opts).
+ *   report    optional host pointer for accuracy/timing information.
+ * Synchronises `stream` once to read the window count m back to the host.
+ * Returns BDG_ERR_NONFINITE (and does not modify W, Z) if A holds NaN/Inf.
+ */
+int bdg_eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
+             double *Z, int64_t ldz, int64_t zcols, int64_t *m, const bdg_opts *opts,
+             void *work, size_t work_bytes, bdg_err_report *report, bdg_stream_t stream);
+
+/*
+ * bdg_check -- FP64 accuracy of m eigenpairs (W, Z) of the Hermitian H.
+ *   H [ldh x n] complex128 (full storage, both triangles read).
+ *   max_resid   = max_j ||H z_j - w_j z_j||_2 / max_j |w_j| (host output)
+ *   gram_defect = max_ij |(Z^H Z - I)_ij|                     (host output)
+ *   work        device scratch of at least 16*(n*m + m*m) bytes.
+ * Synchronises `stream`.
+ */
+int bdg_check(int64_t n, const double *H, int64_t ldh, int64_t m, const double *W,
+              const double *Z, int64_t ldz, double *max_resid, double *gram_defect,
+              void *work, size_t work_bytes, bdg_stream_t stream);
+
+/* Text of the last error recorded by this thread (never NULL). */
+const char *bdg_last_error(void);
+
+/* Library version string. */
+const char *bdg_version(void);
+
+/* ------------------------------------------------------------------------
+ * Stage-level entry points.  They expose the individual steps of the
+ * two-stage method so that each can be tested and timed on its own; bdg_eigh
+ * chains the same kernels.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * bdg_zgemm -- C = alpha op(A) op(B) + beta C, complex128, column-major,
+ * op = 'N' (none) or 'C' (conjugate transpose).  alpha/beta are host
+ * complex scalars given as (re, im) pairs.  The MFMA tile kernel shared by
+ * stage 1 and the back-transformations.
+ */
+int bdg_zgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, const double *alpha,
+              const double *A, int64_t lda, const double *B, int64_t ldb, const double *beta,
+              double *C, int64_t ldc, bdg_stream_t stream);
+
+/* bdg_cgemm -- same for complex64 (FP32 MFMA, FP32 accumulation). */
+int bdg_cgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, const float *alpha,
+              const float *A, int64_t lda, const float *B, int64_t ldb, const float *beta,
+              float *C, int64_t ldc, bdg_stream_t stream);
+
+/* bdg_dgemm -- same for real f64 (used by the divide-and-conquer merges). */
+int bdg_dgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, double alpha,
+              const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+              double *C, int64_t ldc, bdg_stream_t stream);
+
+/*
+ * Stage hooks (same kernels as bdg_eigh; for tests and per-stage timing).
+ * Workspace sizes come from bdg_stage_workspace(stage, n, band):
+ * stage 1 = he2hb, 2 = hb2st (none), 3 = stedc, 4 = bt2, 5 = bt1 (per column: m).
+ *
+ * bdg_stage_he2hb: A (lower triangle read, overwritten by the reflectors) ->
+ *   AB lower band storage (ldab >= 2 band + 2, AB[(i-j) + j ldab] = B(i, j)),
+ *   T1 [panels x band x band] block-reflector factors.
+ * bdg_stage_hb2st: AB (destroyed) -> d [n] real diagonal, e [n-1] complex
+ *   sub-diagonal; reflectors in V2/tau2 with device offsets voff [n] that the
+ *   call fills.  V2 needs band*(bdg_stage_nrefl(n, band)+1) complex entries.
+ * bdg_stage_stedc: real symmetric tridiagonal (d, e) -> W ascending and Q
+ *   (n x n, ld n, real).
+ * bdg_stage_bt2: Z [n x m] complex = Q2 diag(ph) Y[:, i0:i0+m] with ph from e.
+ * bdg_stage_bt1: Z <- Q1 Z with the stage-1 reflectors left in A.
+ */
+int bdg_stage_workspace(int stage, int64_t n, int band, int64_t m, size_t *bytes);
+int64_t bdg_stage_nrefl(int64_t n, int band);
+int bdg_stage_he2hb(int64_t n, double *A, int64_t lda, int band, double *AB, int64_t ldab,
+                    double *T1, void *work, size_t work_bytes, bdg_stream_t stream);
+int bdg_stage_hb2st(int64_t n, int band, double *AB, int64_t ldab, double *d, double *e,
+                    double *V2, double *tau2, int64_t *voff, bdg_stream_t stream);
+int bdg_stage_stedc(int64_t n, const double *d, const double *e, double *W, double *Q, int leaf,
+                    void *work, size_t work_bytes, bdg_stream_t stream);
+int bdg_stage_bt2(int64_t n, int band, int64_t m, const double *e, const double *Y, int64_t i0,
+                  const double *V2, const double *tau2, const int64_t *voff, double *Z,
+                  int64_t ldz, void *work, size_t work_bytes, bdg_stream_t stream);
+int bdg_stage_bt1(int64_t n, int64_t m, const double *A, int64_t lda, int band, const double *T1,
+                  double *Z, int64_t ldz, void *work, size_t work_bytes, bdg_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BDG_H */

@@ -176,3 +176,38 @@ def eigh(H: np.ndarray, emin: float = -np.inf, emax: float = np.inf, method: str
     W, Z = eigh_jacobi(H) if method == "jacobi" else eigh_hqr(H)
     sel = (W >= emin) & (W <= emax)
     return W[sel], Z[:, sel]
+
+
+def assemble_entries(dims, U, Delta, mu, rows, cols) -> np.ndarray:
+    """Selected entries H[rows[k], cols[k]] of the BdG matrix, from the same
+    definition as ``assemble`` (direct Fourier sum for each axis), for sizes
+    where the full matrix is too large for the CPU."""
+    dims = [int(v) for v in dims]
+    T = [kinetic_1d(N) for N in dims]
+    ns = int(np.prod(dims))
+    U = np.asarray(U, dtype=np.float64)
+    D = np.asarray(Delta, dtype=np.complex128)
+
+    def site(r):
+        c = []
+        for N in dims:
+            c.append(r % N)
+            r //= N
+        return c
+
+    out = np.zeros(len(rows), dtype=np.complex128)
+    for k, (i, j) in enumerate(zip(rows, cols)):
+        bi, bj = i >= ns, j >= ns
+        si, sj = i - ns * bi, j - ns * bj
+        if bi == bj:
+            ci, cj = site(si), site(sj)
+            h = 0.0
+            for d in range(len(dims)):
+                if all(ci[e] == cj[e] for e in range(len(dims)) if e != d):
+                    h += T[d][ci[d], cj[d]]
+            if si == sj:
+                h += U[si] - mu
+            out[k] = -h if bi else h
+        elif si == sj:
+            out[k] = np.conj(D[si]) if bi else D[si]
+    return out

@@ -1,0 +1,298 @@
+"""Thin Python binding of libbdg.so: argument marshalling only.
+
+Every computation runs in the HIP library; this module only passes device
+pointers (from torch tensors), sizes and the current HIP stream across the
+C-ABI declared in include/bdg.h.  If the library is not built, or there is no
+GPU, the calls raise -- there is no CPU fallback.
+
+Matrices are column-major.  A column-major n x n torch view is created as
+``torch.empty((n, ld), dtype).T[:n]`` so that ``M[i, j]`` is element (i, j)
+and ``M.stride(1)`` is the leading dimension.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbdg.so")
+_lib = None
+
+BDG_FP64 = 0
+BDG_FP32_REFINED = 1
+
+
+class BdgError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__("%s failed with status %d: %s" % (fn, code, msg))
+        self.code = code
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dims", ctypes.c_int32 * 3)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("band", ctypes.c_int32),
+                ("refine_max_iter", ctypes.c_int32), ("refine_tol", ctypes.c_double),
+                ("dc_leaf", ctypes.c_int32), ("ph_mirror", ctypes.c_int32)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("max_resid", ctypes.c_double), ("gram_defect", ctypes.c_double),
+                ("eig_shift_max", ctypes.c_double), ("refine_iters", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("stage_ms", ctypes.c_double * 8)]
+
+
+def lib():
+    """Load libbdg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libbdg.so is not built: run `python -m paper_2310_03341_amd.build` "
+                               "(expected at %s)" % LIB_PATH)
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, D, S = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+        L.bdg_last_error.restype = ctypes.c_char_p
+        L.bdg_version.restype = ctypes.c_char_p
+        L.bdg_assemble.argtypes = [ctypes.POINTER(Lattice), P, P, D, P, I64, S]
+        L.bdg_eigh_workspace.argtypes = [I64, ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_size_t)]
+        L.bdg_eigh.argtypes = [I64, P, I64, D, D, P, P, I64, I64, ctypes.POINTER(I64),
+                               ctypes.POINTER(Opts), P, ctypes.c_size_t, ctypes.POINTER(Report), S]
+        L.bdg_check.argtypes = [I64, P, I64, I64, P, P, I64, ctypes.POINTER(D), ctypes.POINTER(D),
+                                P, ctypes.c_size_t, S]
+        L.bdg_zgemm.argtypes = [ctypes.c_char, ctypes.c_char, I64, I64, I64, P, P, I64, P, I64,
+                                P, P, I64, S]
+        L.bdg_cgemm.argtypes = L.bdg_zgemm.argtypes
+        L.bdg_dgemm.argtypes = [ctypes.c_char, ctypes.c_char, I64, I64, I64, D, P, I64, P, I64,
+                                D, P, I64, S]
+        _lib = L
+    return _lib
+
+
+def _call(name: str, *args) -> int:
+    rc = getattr(lib(), name)(*args)
+    if rc != 0:
+        raise BdgError(name, rc, lib().bdg_last_error().decode())
+    return rc
+
+
+def _stream(dev=None) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
+def _dev(t: torch.Tensor):
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    return t.data_ptr()
+
+
+def colmajor(n: int, m: int, dtype, device="cuda", ld: Optional[int] = None) -> torch.Tensor:
+    """Uninitialised column-major n x m tensor (M[i, j] = element (i, j))."""
+    ld = ld or max(n, 1)
+    return torch.empty((m, ld), dtype=dtype, device=device).T[:n]
+
+
+def to_colmajor(M: torch.Tensor) -> torch.Tensor:
+    out = colmajor(M.shape[0], M.shape[1], M.dtype, M.device)
+    out.copy_(M)
+    return out
+
+
+def _ld(M: torch.Tensor) -> int:
+    if M.dim() != 2 or M.stride(0) != 1:
+        raise ValueError("expected a column-major matrix view (stride(0) == 1)")
+    return max(M.stride(1), M.shape[0], 1)
+
+
+def version() -> str:
+    return lib().bdg_version().decode()
+
+
+def assemble(dims: Sequence[int], U: torch.Tensor, Delta: torch.Tensor, mu: float,
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Dense BdG matrix (complex128, column-major) of eq. (stHpsi)."""
+    lat = Lattice()
+    lat.ndim = len(dims)
+    for d, v in enumerate(dims):
+        lat.dims[d] = int(v)
+    n = 2 * int(math.prod(dims))
+    H = out if out is not None else colmajor(n, n, torch.complex128, U.device)
+    _call("bdg_assemble", ctypes.byref(lat), _dev(U), _dev(Delta), float(mu), _dev(H), _ld(H),
+          _stream(U.device))
+    return H
+
+
+def make_opts(precision: int = BDG_FP64, band: int = 0, refine_max_iter: int = 0,
+              refine_tol: float = 0.0, dc_leaf: int = 0, ph_mirror: int = 0) -> Opts:
+    o = Opts()
+    o.precision, o.band, o.refine_max_iter = precision, band, refine_max_iter
+    o.refine_tol, o.dc_leaf, o.ph_mirror = refine_tol, dc_leaf, ph_mirror
+    return o
+
+
+def eigh_workspace(n: int, opts: Optional[Opts] = None) -> int:
+    nb = ctypes.c_size_t(0)
+    _call("bdg_eigh_workspace", int(n), ctypes.byref(opts) if opts else None, ctypes.byref(nb))
+    return int(nb.value)
+
+
+class Solver:
+    """Holds the device workspace of bdg_eigh for one matrix order."""
+
+    def __init__(self, n: int, opts: Optional[Opts] = None, device="cuda"):
+        self.n = int(n)
+        self.opts = opts or make_opts()
+        self.bytes = eigh_workspace(self.n, self.opts)
+        self.work = torch.empty(max(self.bytes, 1), dtype=torch.uint8, device=device)
+        self.report = Report()
+
+    def __call__(self, A: torch.Tensor, emin: float = -math.inf, emax: float = math.inf,
+                 W: Optional[torch.Tensor] = None, Z: Optional[torch.Tensor] = None):
+        n = self.n
+        if A.shape != (n, n):
+            raise ValueError("A must be %d x %d" % (n, n))
+        W = W if W is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+        Z = Z if Z is not None else colmajor(n, n, torch.complex128, A.device)
+        m = ctypes.c_int64(0)
+        _call("bdg_eigh", n, _dev(A), _ld(A), float(emin), float(emax), _dev(W), _dev(Z),
+              _ld(Z), Z.shape[1], ctypes.byref(m), ctypes.byref(self.opts), _dev(self.work),
+              self.bytes, ctypes.byref(self.report), _stream(A.device))
+        k = int(m.value)
+        return W[:k], Z[:, :k]
+
+
+def eigh(A: torch.Tensor, emin: float = -math.inf, emax: float = math.inf,
+         opts: Optional[Opts] = None):
+    """Eigenpairs of the Hermitian A (destroyed) with eigenvalues in [emin, emax]."""
+    return Solver(A.shape[0], opts, A.device)(A, emin, emax)
+
+
+def check(H: torch.Tensor, W: torch.Tensor, Z: torch.Tensor):
+    """(max residual / ||H||_2, max |Z^H Z - I|) computed on the GPU in FP64."""
+    n, m = Z.shape
+    work = torch.empty(16 * (n * m + m * m) + 64, dtype=torch.uint8, device=H.device)
+    r, g = ctypes.c_double(0), ctypes.c_double(0)
+    _call("bdg_check", n, _dev(H), _ld(H), m, _dev(W), _dev(Z) if m else None, _ld(Z) if m else n,
+          ctypes.byref(r), ctypes.byref(g), _dev(work), work.numel(), _stream(H.device))
+    return r.value, g.value
+
+
+def _gemm(fn: str, opA: str, opB: str, A, B, C, alpha, beta, real=False):
+    M, N = C.shape
+    K = A.shape[1] if opA == "N" else A.shape[0]
+    if real:
+        _call(fn, opA.encode(), opB.encode(), M, N, K, float(alpha), _dev(A), _ld(A), _dev(B),
+              _ld(B), float(beta), _dev(C), _ld(C), _stream(C.device))
+        return C
+    ctype = ctypes.c_double if fn == "bdg_zgemm" else ctypes.c_float
+    al = (ctype * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctype * 2)(complex(beta).real, complex(beta).imag)
+    _call(fn, opA.encode(), opB.encode(), M, N, K, ctypes.cast(al, ctypes.c_void_p), _dev(A), _ld(A),
+          _dev(B), _ld(B), ctypes.cast(be, ctypes.c_void_p), _dev(C), _ld(C), _stream(C.device))
+    return C
+
+
+def zgemm(opA, opB, A, B, C, alpha=1.0, beta=0.0):
+    return _gemm("bdg_zgemm", opA, opB, A, B, C, alpha, beta)
+
+
+def cgemm(opA, opB, A, B, C, alpha=1.0, beta=0.0):
+    return _gemm("bdg_cgemm", opA, opB, A, B, C, alpha, beta)
+
+
+def dgemm(opA, opB, A, B, C, alpha=1.0, beta=0.0):
+    return _gemm("bdg_dgemm", opA, opB, A, B, C, alpha, beta, real=True)
+
+
+# ---------------------------------------------------------------- stage hooks
+def _stage_sigs(L):
+    P, I64, S = ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p
+    L.bdg_stage_workspace.argtypes = [ctypes.c_int, I64, ctypes.c_int, I64,
+                                      ctypes.POINTER(ctypes.c_size_t)]
+    L.bdg_stage_nrefl.argtypes = [I64, ctypes.c_int]
+    L.bdg_stage_nrefl.restype = I64
+    L.bdg_stage_he2hb.argtypes = [I64, P, I64, ctypes.c_int, P, I64, P, P, ctypes.c_size_t, S]
+    L.bdg_stage_hb2st.argtypes = [I64, ctypes.c_int, P, I64, P, P, P, P, P, S]
+    L.bdg_stage_stedc.argtypes = [I64, P, P, P, P, ctypes.c_int, P, ctypes.c_size_t, S]
+    L.bdg_stage_bt2.argtypes = [I64, ctypes.c_int, I64, P, P, I64, P, P, P, P, I64, P,
+                                ctypes.c_size_t, S]
+    L.bdg_stage_bt1.argtypes = [I64, I64, P, I64, ctypes.c_int, P, P, I64, P, ctypes.c_size_t, S]
+
+
+def stage_workspace(stage: int, n: int, band: int = 64, m: int = 0, device="cuda"):
+    L = lib()
+    _stage_sigs(L)
+    nb = ctypes.c_size_t(0)
+    _call("bdg_stage_workspace", stage, n, band, m, ctypes.byref(nb))
+    return torch.empty(max(int(nb.value), 1), dtype=torch.uint8, device=device)
+
+
+def stage_he2hb(A: torch.Tensor, band: int = 64):
+    """Stage 1 on A (destroyed): returns (AB, T1) device tensors."""
+    L = lib()
+    _stage_sigs(L)
+    n = A.shape[0]
+    ldab = 2 * band + 2
+    AB = torch.zeros((n, ldab), dtype=torch.complex128, device=A.device)  # AB[j, d]
+    np_ = max(1, sum(1 for k in range(0, n, band) if k + band + 1 < n))
+    T1 = torch.zeros(np_ * band * band, dtype=torch.complex128, device=A.device)
+    work = stage_workspace(1, n, band, 0, A.device)
+    _call("bdg_stage_he2hb", n, _dev(A), _ld(A), band, _dev(AB), ldab, _dev(T1), _dev(work),
+          work.numel(), _stream(A.device))
+    return AB, T1
+
+
+def stage_hb2st(AB: torch.Tensor, band: int = 64):
+    """Stage 2 on AB (destroyed): returns (d, e_complex, V2, tau2, voff)."""
+    L = lib()
+    _stage_sigs(L)
+    n, ldab = AB.shape
+    nrefl = int(L.bdg_stage_nrefl(n, band))
+    dev = AB.device
+    d = torch.zeros(n, dtype=torch.float64, device=dev)
+    e = torch.zeros(max(n, 1), dtype=torch.complex128, device=dev)
+    V2 = torch.zeros((nrefl + 1) * band, dtype=torch.complex128, device=dev)
+    tau2 = torch.zeros(nrefl + 1, dtype=torch.float64, device=dev)
+    voff = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    _call("bdg_stage_hb2st", n, band, _dev(AB), ldab, _dev(d), _dev(e), _dev(V2), _dev(tau2),
+          _dev(voff), _stream(dev))
+    return d, e, V2, tau2, voff
+
+
+def stage_stedc(d: torch.Tensor, e: torch.Tensor, leaf: int = 0):
+    L = lib()
+    _stage_sigs(L)
+    n = d.numel()
+    W = torch.zeros(n, dtype=torch.float64, device=d.device)
+    Q = colmajor(n, n, torch.float64, d.device)
+    work = stage_workspace(3, n, 64, 0, d.device)
+    ee = e if e.numel() > 0 else torch.zeros(1, dtype=torch.float64, device=d.device)
+    _call("bdg_stage_stedc", n, _dev(d), _dev(ee), _dev(W), _dev(Q), leaf, _dev(work),
+          work.numel(), _stream(d.device))
+    return W, Q
+
+
+def stage_bt2(e_cplx, Y, i0, m, V2, tau2, voff, band: int = 64):
+    L = lib()
+    _stage_sigs(L)
+    n = Y.shape[0]
+    Z = colmajor(n, max(m, 1), torch.complex128, Y.device)
+    work = stage_workspace(4, n, band, m, Y.device)
+    _call("bdg_stage_bt2", n, band, m, _dev(e_cplx), _dev(Y), i0, _dev(V2), _dev(tau2), _dev(voff),
+          _dev(Z), _ld(Z), _dev(work), work.numel(), _stream(Y.device))
+    return Z[:, :m]
+
+
+def stage_bt1(A, T1, Z, band: int = 64):
+    L = lib()
+    _stage_sigs(L)
+    n, m = Z.shape
+    work = stage_workspace(5, n, band, m, Z.device)
+    _call("bdg_stage_bt1", n, m, _dev(A), _ld(A), band, _dev(T1), _dev(Z), _ld(Z), _dev(work),
+          work.numel(), _stream(Z.device))
+    return Z

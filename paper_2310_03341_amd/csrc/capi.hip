@@ -1,0 +1,223 @@
+// C-ABI entry points of libbdg.so (declared in include/bdg.h).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "common.h"
+#include "gemm.h"
+#include "solver.h"
+
+namespace bdg {
+
+static thread_local char g_err[512] = "no error";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+int hip_fail(hipError_t e, const char *what, const char *file, int line) {
+    set_error("HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), what, file, line);
+    return BDG_ERR_HIP;
+}
+
+}  // namespace bdg
+
+using namespace bdg;
+
+extern "C" {
+
+const char *bdg_last_error(void) { return bdg::g_err; }
+
+const char *bdg_version(void) { return "bdg-mi355x 0.1 (gfx950)"; }
+
+int bdg_assemble(const bdg_lattice *lat, const double *U, const double *Delta, double mu,
+                 double *H, int64_t ldh, bdg_stream_t stream) {
+    if (!lat || lat->ndim < 1 || lat->ndim > 3) {
+        set_error("bdg_assemble: lattice must have ndim in 1..3");
+        return -1;
+    }
+    int64_t ns = 1;
+    for (int d = 0; d < lat->ndim; ++d) {
+        const int N = lat->dims[d];
+        if (N < 2 || (N & 1) || N > 64) {
+            set_error("bdg_assemble: dims[%d]=%d must be even and in [2, 64]", d, N);
+            return -1;
+        }
+        ns *= N;
+    }
+    if (!U) { set_error("bdg_assemble: U is NULL"); return -2; }
+    if (!Delta) { set_error("bdg_assemble: Delta is NULL"); return -3; }
+    if (!H) { set_error("bdg_assemble: H is NULL"); return -5; }
+    if (ldh < 2 * ns) { set_error("bdg_assemble: ldh=%lld < n=%lld", (long long)ldh, (long long)(2 * ns)); return -6; }
+    return bdg::assemble(lat, U, Delta, mu, H, ldh, (hipStream_t)stream);
+}
+
+static int check_gemm_args(char opA, char opB, int64_t M, int64_t N, int64_t K, const void *A,
+                           int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc) {
+    auto okop = [](char o) { return o == 'N' || o == 'n' || o == 'C' || o == 'c' || o == 'T' || o == 't'; };
+    if (!okop(opA)) { set_error("gemm: bad opA"); return -1; }
+    if (!okop(opB)) { set_error("gemm: bad opB"); return -2; }
+    if (M < 0) return -3;
+    if (N < 0) return -4;
+    if (K < 0) return -5;
+    const bool na = (opA == 'N' || opA == 'n'), nb = (opB == 'N' || opB == 'n');
+    if (M && N && K && !A) return -7;
+    if (lda < (na ? (M > 0 ? M : 1) : (K > 0 ? K : 1))) { set_error("gemm: lda too small"); return -8; }
+    if (M && N && K && !B) return -9;
+    if (ldb < (nb ? (K > 0 ? K : 1) : (N > 0 ? N : 1))) { set_error("gemm: ldb too small"); return -10; }
+    if (M && N && !C) return -12;
+    if (ldc < (M > 0 ? M : 1)) { set_error("gemm: ldc too small"); return -13; }
+    return 0;
+}
+
+int bdg_zgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, const double *alpha,
+              const double *A, int64_t lda, const double *B, int64_t ldb, const double *beta,
+              double *C, int64_t ldc, bdg_stream_t stream) {
+    BDG_TRY(check_gemm_args(opA, opB, M, N, K, A, lda, B, ldb, C, ldc));
+    GemmArgs g{M, N, K, alpha[0], alpha[1], beta[0], beta[1], A, lda, B, ldb, C, ldc, GEMM_FULL, 1, nullptr};
+    return gemm<double, true>(opA, opB, g, (hipStream_t)stream);
+}
+
+int bdg_cgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, const float *alpha,
+              const float *A, int64_t lda, const float *B, int64_t ldb, const float *beta,
+              float *C, int64_t ldc, bdg_stream_t stream) {
+    BDG_TRY(check_gemm_args(opA, opB, M, N, K, A, lda, B, ldb, C, ldc));
+    GemmArgs g{M, N, K, alpha[0], alpha[1], beta[0], beta[1], A, lda, B, ldb, C, ldc, GEMM_FULL, 1, nullptr};
+    return gemm<float, true>(opA, opB, g, (hipStream_t)stream);
+}
+
+int bdg_dgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, double alpha,
+              const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
+              double *C, int64_t ldc, bdg_stream_t stream) {
+    BDG_TRY(check_gemm_args(opA, opB, M, N, K, A, lda, B, ldb, C, ldc));
+    GemmArgs g{M, N, K, alpha, 0.0, beta, 0.0, A, lda, B, ldb, C, ldc, GEMM_FULL, 1, nullptr};
+    return gemm<double, false>(opA, opB, g, (hipStream_t)stream);
+}
+
+int bdg_check(int64_t n, const double *H, int64_t ldh, int64_t m, const double *W,
+              const double *Z, int64_t ldz, double *max_resid, double *gram_defect, void *work,
+              size_t work_bytes, bdg_stream_t stream) {
+    if (n < 1) return -1;
+    if (!H) return -2;
+    if (ldh < n) return -3;
+    if (m < 0 || m > n) return -4;
+    if (m > 0 && !W) return -5;
+    if (m > 0 && !Z) return -6;
+    if (ldz < n) return -7;
+    if (!max_resid) return -8;
+    if (!gram_defect) return -9;
+    const size_t need = 16 * ((size_t)n * m + (size_t)m * m) + 64;
+    if (work_bytes < need || !work) {
+        set_error("bdg_check: workspace %zu < %zu bytes", work_bytes, need);
+        return BDG_ERR_WORKSPACE;
+    }
+    return bdg::check_pairs(n, H, ldh, m, W, Z, ldz, max_resid, gram_defect, work, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int bdg_eigh_workspace(int64_t n, const bdg_opts *opts, size_t *bytes) {
+    if (n < 1) { set_error("bdg_eigh_workspace: n must be >= 1"); return -1; }
+    if (!bytes) return -3;
+    return bdg::eigh_workspace(n, opts, bytes);
+}
+
+int bdg_eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W, double *Z,
+             int64_t ldz, int64_t zcols, int64_t *m, const bdg_opts *opts, void *work,
+             size_t work_bytes, bdg_err_report *report, bdg_stream_t stream) {
+    if (n < 1) { set_error("bdg_eigh: n must be >= 1"); return -1; }
+    if (!A) return -2;
+    if (lda < n) { set_error("bdg_eigh: lda < n"); return -3; }
+    if (!(emin <= emax)) { set_error("bdg_eigh: emin > emax or NaN"); return -4; }
+    if (!W) return -6;
+    if (!Z) return -7;
+    if (ldz < n) { set_error("bdg_eigh: ldz < n"); return -8; }
+    if (zcols < 0) return -9;
+    if (!m) return -10;
+    size_t need = 0;
+    BDG_TRY(bdg::eigh_workspace(n, opts, &need));
+    if (!work || work_bytes < need) {
+        set_error("bdg_eigh: workspace %zu < %zu bytes", work_bytes, need);
+        return BDG_ERR_WORKSPACE;
+    }
+    return bdg::eigh(n, A, lda, emin, emax, W, Z, ldz, zcols, m, opts, work, work_bytes, report,
+                     (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- stage hooks
+#include <vector>
+#include "stages.h"
+
+extern "C" {
+
+int bdg_stage_workspace(int stage, int64_t n, int band, int64_t m, size_t *bytes) {
+    if (!bytes) return -5;
+    switch (stage) {
+        case 1: *bytes = bdg::he2hb_workspace(n, band); return 0;
+        case 2: *bytes = 0; return 0;
+        case 3: *bytes = bdg::stedc_workspace(n); return 0;
+        case 4: *bytes = bdg::bt2_workspace(n, band) + 16 * (size_t)n + 8 * (size_t)n + 512; return 0;
+        case 5: *bytes = bdg::bt1_workspace(m, band); return 0;
+        default: set_error("bdg_stage_workspace: unknown stage %d", stage); return -1;
+    }
+}
+
+int64_t bdg_stage_nrefl(int64_t n, int band) { return bdg::hb2st_nrefl(n, band); }
+
+int bdg_stage_he2hb(int64_t n, double *A, int64_t lda, int band, double *AB, int64_t ldab,
+                    double *T1, void *work, size_t work_bytes, bdg_stream_t stream) {
+    if (n < 1) return -1;
+    if (work_bytes < bdg::he2hb_workspace(n, band)) return BDG_ERR_WORKSPACE;
+    return bdg::he2hb(n, A, lda, band, AB, ldab, T1, work, (hipStream_t)stream);
+}
+
+int bdg_stage_hb2st(int64_t n, int band, double *AB, int64_t ldab, double *d, double *e,
+                    double *V2, double *tau2, int64_t *voff, bdg_stream_t stream) {
+    if (n < 1) return -1;
+    hipStream_t s = (hipStream_t)stream;
+    if (n >= 3) {
+        std::vector<int64_t> vh((size_t)(n - 2));
+        bdg::hb2st_offsets(n, band, vh.data());
+        BDG_HIP(hipMemcpyAsync(voff, vh.data(), 8 * (size_t)(n - 2), hipMemcpyHostToDevice, s));
+        BDG_HIP(hipStreamSynchronize(s));
+    }
+    return bdg::hb2st(n, band, AB, ldab, V2, tau2, voff, d, e, s);
+}
+
+int bdg_stage_stedc(int64_t n, const double *d, const double *e, double *W, double *Q, int leaf,
+                    void *work, size_t work_bytes, bdg_stream_t stream) {
+    if (n < 1) return -1;
+    if (work_bytes < bdg::stedc_workspace(n)) return BDG_ERR_WORKSPACE;
+    return bdg::stedc(n, d, e, W, Q, n, work, (hipStream_t)stream, leaf);
+}
+
+int bdg_stage_bt2(int64_t n, int band, int64_t m, const double *e, const double *Y, int64_t i0,
+                  const double *V2, const double *tau2, const int64_t *voff, double *Z,
+                  int64_t ldz, void *work, size_t work_bytes, bdg_stream_t stream) {
+    size_t need = 0;
+    bdg_stage_workspace(4, n, band, m, &need);
+    if (work_bytes < need) return BDG_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)work;
+    double *ph = (double *)w;
+    double *ea = (double *)(w + 16 * (size_t)n + 256);
+    void *rest = w + 16 * (size_t)n + 8 * (size_t)n + 512;
+    BDG_TRY(bdg::phases(n, e, ph, ea, s));
+    BDG_TRY(bdg::phase_scale(n, m, Y, i0, ph, Z, ldz, s));
+    return bdg::bt2(n, band, m, V2, tau2, voff, Z, ldz, rest, s);
+}
+
+int bdg_stage_bt1(int64_t n, int64_t m, const double *A, int64_t lda, int band, const double *T1,
+                  double *Z, int64_t ldz, void *work, size_t work_bytes, bdg_stream_t stream) {
+    if (work_bytes < bdg::bt1_workspace(m, band)) return BDG_ERR_WORKSPACE;
+    return bdg::bt1(n, m, A, lda, band, T1, Z, ldz, work, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Shared device/host helpers of the BdG eigensolver library (gfx950 only).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/bdg.h"
+
+namespace bdg {
+
+typedef double __attribute__((ext_vector_type(4))) d4;
+typedef float __attribute__((ext_vector_type(4))) f4;
+
+// Interleaved complex scalar used on both host and device.
+template <typename T>
+struct cx {
+    T re, im;
+};
+typedef cx<double> zd;
+typedef cx<float> cf;
+
+template <typename T>
+__host__ __device__ inline cx<T> mk(T r, T i) { cx<T> z; z.re = r; z.im = i; return z; }
+template <typename T>
+__host__ __device__ inline cx<T> cadd(cx<T> a, cx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename T>
+__host__ __device__ inline cx<T> csub(cx<T> a, cx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename T>
+__host__ __device__ inline cx<T> cmul(cx<T> a, cx<T> b) { return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re); }
+// conj(a) * b
+template <typename T>
+__host__ __device__ inline cx<T> cjmul(cx<T> a, cx<T> b) { return mk(a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re); }
+template <typename T>
+__host__ __device__ inline cx<T> cconj(cx<T> a) { return mk(a.re, -a.im); }
+template <typename T>
+__host__ __device__ inline cx<T> cscale(cx<T> a, T s) { return mk(a.re * s, a.im * s); }
+template <typename T>
+__host__ __device__ inline T cabs2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// MFMA 16x16x4 (one block).  Operand lane layout: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16].  Accumulator element r of lane l holds D[row][l%16] with
+// row = (l/16) + 4 r for the f64 instruction and row = 4 (l/16) + r for the
+// f32 one (measured on gfx950; see mfma_row).
+__device__ inline d4 mfma16(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma16(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline int mfma_row(double, int lane, int r) { return (lane >> 4) + 4 * r; }
+__device__ inline int mfma_row(float, int lane, int r) { return 4 * (lane >> 4) + r; }
+template <typename T> struct acc4;
+template <> struct acc4<double> { typedef d4 type; };
+template <> struct acc4<float> { typedef f4 type; };
+
+// Wave-level reductions (64 lanes).
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-level sum over blockDim.x threads (multiple of 64), result to all.
+template <typename T>
+__device__ inline T block_sum(T v, T* red /* >= blockDim.x/64 */) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    T s = 0;
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) s += red[i];
+    __syncthreads();
+    return s;
+}
+
+}  // namespace bdg
+
+// ---- host-side error plumbing -------------------------------------------------
+namespace bdg {
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what, const char* file, int line);
+}  // namespace bdg
+
+#define BDG_HIP(call)                                                               \
+    do {                                                                            \
+        hipError_t _e = (call);                                                     \
+        if (_e != hipSuccess) return bdg::hip_fail(_e, #call, __FILE__, __LINE__);  \
+    } while (0)
+
+#define BDG_CHECK_LAUNCH() BDG_HIP(hipGetLastError())
+
+#define BDG_TRY(call)                 \
+    do {                              \
+        int _rc = (call);             \
+        if (_rc != 0) return _rc;     \
+    } while (0)

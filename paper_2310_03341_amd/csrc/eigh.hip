@@ -1,0 +1,197 @@
+// bdg_eigh driver: dense Hermitian -> band -> real tridiagonal -> divide and
+// conquer -> window selection -> back-transformations (the 2-stage solver of
+// the paper's diagonalisation section, with the energy window of the density
+// sums, "Methods").
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "solver.h"
+#include "stages.h"
+
+namespace bdg {
+namespace {
+
+constexpr int DEFAULT_BAND = 64;
+
+struct Layout {
+    int b;
+    int64_t ldab, np, nrefl;
+    size_t off_AB, off_T1, off_V2, off_tau2, off_voff, off_d, off_ec, off_ea, off_ph, off_Y, off_W2,
+        off_flag, off_scratch, scratch, total;
+};
+
+size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+Layout layout(int64_t n, const bdg_opts *o) {
+    Layout L;
+    L.b = (o && o->band > 0) ? o->band : DEFAULT_BAND;
+    if (L.b > 64) L.b = 64;
+    if (n <= 2) L.b = 1;
+    L.ldab = 2 * L.b + 2;
+    L.np = he2hb_panels(n, L.b);
+    L.nrefl = hb2st_nrefl(n, L.b);
+    size_t o_ = 0;
+    auto put = [&](size_t bytes) { size_t r = o_; o_ += al(bytes); return r; };
+    L.off_AB = put(16 * (size_t)L.ldab * n);
+    L.off_T1 = put(16 * (size_t)(L.np + 1) * L.b * L.b);
+    L.off_V2 = put(16 * (size_t)(L.nrefl + 1) * L.b);
+    L.off_tau2 = put(8 * (size_t)(L.nrefl + 1));
+    L.off_voff = put(8 * (size_t)(n + 1));
+    L.off_d = put(8 * (size_t)n);
+    L.off_ec = put(16 * (size_t)n);
+    L.off_ea = put(8 * (size_t)n);
+    L.off_ph = put(16 * (size_t)n);
+    L.off_Y = put(8 * (size_t)n * n);
+    L.off_W2 = put(8 * (size_t)n);
+    L.off_flag = put(256);
+    // scratch shared by the stages (they run one after another)
+    size_t sc = he2hb_workspace(n, L.b);
+    sc = std::max(sc, stedc_workspace(n));
+    sc = std::max(sc, bt2_workspace(n, L.b));
+    sc = std::max(sc, bt1_workspace(n, L.b));
+    L.off_scratch = put(sc);
+    L.scratch = sc;
+    L.total = o_ + 256;
+    return L;
+}
+
+__global__ void nonfinite_lower(int64_t n, const double *__restrict__ A, int64_t lda, int *flag) {
+    const int64_t j = blockIdx.x;
+    int bad = 0;
+    for (int64_t i = j + threadIdx.x; i < n; i += blockDim.x) {
+        const double re = A[2 * (i + j * lda)], im = A[2 * (i + j * lda) + 1];
+        if (!isfinite(re) || !isfinite(im)) bad = 1;
+    }
+    if (bad) atomicOr(flag, 1);
+}
+
+struct Timer {
+    hipStream_t s;
+    hipEvent_t ev[9];
+    int k = 0;
+    bool ok = false;
+    explicit Timer(hipStream_t st) : s(st) {
+        ok = true;
+        for (int i = 0; i < 9; ++i)
+            if (hipEventCreate(&ev[i]) != hipSuccess) ok = false;
+    }
+    ~Timer() {
+        for (int i = 0; i < 9; ++i) (void)hipEventDestroy(ev[i]);
+    }
+    void mark(int i) {
+        if (ok) (void)hipEventRecord(ev[i], s);
+    }
+    double ms(int a, int b) {
+        float t = 0.f;
+        if (!ok || hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) return 0.0;
+        return (double)t;
+    }
+};
+
+}  // namespace
+
+int eigh_workspace(int64_t n, const bdg_opts *opts, size_t *bytes) {
+    if (opts && opts->precision != BDG_FP64) {
+        set_error("bdg_eigh: only BDG_FP64 is available in this build");
+        return BDG_ERR_NOT_IMPLEMENTED;
+    }
+    *bytes = layout(n, opts).total;
+    return 0;
+}
+
+int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W, double *Z,
+         int64_t ldz, int64_t zcols, int64_t *m_out, const bdg_opts *opts, void *work,
+         size_t work_bytes, bdg_err_report *report, hipStream_t s) {
+    (void)work_bytes;
+    if (opts && opts->precision != BDG_FP64) {
+        set_error("bdg_eigh: only BDG_FP64 is available in this build");
+        return BDG_ERR_NOT_IMPLEMENTED;
+    }
+    const Layout L = layout(n, opts);
+    const int b = L.b;
+    char *base = (char *)work;
+    double *AB = (double *)(base + L.off_AB);
+    double *T1 = (double *)(base + L.off_T1);
+    double *V2 = (double *)(base + L.off_V2);
+    double *tau2 = (double *)(base + L.off_tau2);
+    int64_t *voff = (int64_t *)(base + L.off_voff);
+    double *d = (double *)(base + L.off_d);
+    double *ec = (double *)(base + L.off_ec);
+    double *ea = (double *)(base + L.off_ea);
+    double *ph = (double *)(base + L.off_ph);
+    double *Y = (double *)(base + L.off_Y);
+    double *W2 = (double *)(base + L.off_W2);
+    int *flag = (int *)(base + L.off_flag);
+    void *scratch = base + L.off_scratch;
+    const int leaf = (opts && opts->dc_leaf > 0) ? opts->dc_leaf : 32;
+
+    Timer tm(s);
+    tm.mark(0);
+    // reject NaN/Inf before touching anything
+    BDG_HIP(hipMemsetAsync(flag, 0, 4, s));
+    hipLaunchKernelGGL(nonfinite_lower, dim3((unsigned)n), dim3(256), 0, s, n, A, lda, flag);
+    BDG_CHECK_LAUNCH();
+    int hflag = 0;
+    BDG_HIP(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+    BDG_HIP(hipStreamSynchronize(s));
+    if (hflag) {
+        set_error("bdg_eigh: the input matrix holds NaN or Inf");
+        return BDG_ERR_NONFINITE;
+    }
+    tm.mark(1);
+    // ---- stage 1: dense -> band
+    BDG_TRY(he2hb(n, A, lda, b, AB, L.ldab, T1, scratch, s));
+    tm.mark(2);
+    // ---- stage 2: band -> tridiagonal
+    if (n >= 3) {
+        std::vector<int64_t> vh((size_t)(n - 2));
+        hb2st_offsets(n, b, vh.data());
+        BDG_HIP(hipMemcpyAsync(voff, vh.data(), 8 * (size_t)(n - 2), hipMemcpyHostToDevice, s));
+        BDG_HIP(hipStreamSynchronize(s));  // vh goes out of scope
+    }
+    BDG_TRY(hb2st(n, b, AB, L.ldab, V2, tau2, voff, d, ec, s));
+    BDG_TRY(phases(n, ec, ph, ea, s));
+    tm.mark(3);
+    // ---- tridiagonal divide and conquer
+    BDG_TRY(stedc(n, d, ea, W2, Y, n, scratch, s, leaf));
+    tm.mark(4);
+    // ---- window
+    std::vector<double> wh((size_t)n);
+    BDG_HIP(hipMemcpyAsync(wh.data(), W2, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+    BDG_HIP(hipStreamSynchronize(s));
+    const int64_t i0 = std::lower_bound(wh.begin(), wh.end(), emin) - wh.begin();
+    const int64_t i1 = std::upper_bound(wh.begin(), wh.end(), emax) - wh.begin();
+    const int64_t m = i1 > i0 ? i1 - i0 : 0;
+    *m_out = m;
+    if (m > zcols) {
+        set_error("bdg_eigh: %lld eigenpairs in the window exceed zcols=%lld", (long long)m,
+                  (long long)zcols);
+        return BDG_ERR_WORKSPACE;
+    }
+    BDG_HIP(hipMemcpyAsync(W, W2 + i0, 8 * (size_t)m, hipMemcpyDeviceToDevice, s));
+    BDG_TRY(phase_scale(n, m, Y, i0, ph, Z, ldz, s));
+    tm.mark(5);
+    // ---- back-transformation 2 (band <- tridiagonal), then 1 (dense <- band)
+    BDG_TRY(bt2(n, b, m, V2, tau2, voff, Z, ldz, scratch, s));
+    tm.mark(6);
+    BDG_TRY(bt1(n, m, A, lda, b, T1, Z, ldz, scratch, s));
+    tm.mark(7);
+    BDG_HIP(hipStreamSynchronize(s));
+    if (report) {
+        memset(report, 0, sizeof(*report));
+        report->stage_ms[0] = tm.ms(1, 2);
+        report->stage_ms[1] = tm.ms(2, 3);
+        report->stage_ms[2] = tm.ms(3, 4);
+        report->stage_ms[3] = tm.ms(5, 6);
+        report->stage_ms[4] = tm.ms(6, 7);
+        report->stage_ms[5] = 0.0;
+        report->stage_ms[6] = tm.ms(4, 5);
+        report->stage_ms[7] = tm.ms(0, 7);
+    }
+    return 0;
+}
+
+}  // namespace bdg

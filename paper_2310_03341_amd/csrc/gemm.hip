@@ -1,0 +1,385 @@
+// MFMA tile GEMM kernels (see gemm.h for the layout and modes).
+#include "gemm.h"
+
+#include <math.h>
+
+namespace bdg {
+namespace {
+
+constexpr int BM = 64;
+constexpr int BN = 64;
+constexpr int NT = 256;
+
+template <typename T, bool CPLX>
+struct Cfg {
+    static constexpr int EW = CPLX ? 2 : 1;       // scalars per element
+    static constexpr int BK = CPLX ? 16 : 32;     // k-depth of one LDS tile
+    static constexpr int LDS_LD = BM + 1;         // elements per k-row in LDS
+    static constexpr int TILE_ELEMS = BK * BM;    // elements of one operand tile
+    static constexpr int PER_THREAD = TILE_ELEMS / NT;
+};
+
+// Load one operand tile (MN x BK elements) from global memory into registers.
+//   KFAST = false: element (i, k) at P[(r0 + i) + (k0 + k) * ld]  (contiguous in i)
+//   KFAST = true : element (i, k) at P[(k0 + k) + (r0 + i) * ld]  (contiguous in k)
+// Out-of-range elements are zero.  HEMM_DIAG: lower-Hermitian select for the
+// diagonal tile (i-fast layout only).
+template <typename T, bool CPLX, bool KFAST, bool CONJ>
+__device__ inline void load_tile(const T *__restrict__ P, int64_t ld, int64_t r0, int64_t k0,
+                                 int64_t MN, int64_t K, T (&reg)[Cfg<T, CPLX>::PER_THREAD][2],
+                                 bool hemm_diag, const int *__restrict__ kmap = nullptr) {
+    typedef Cfg<T, CPLX> C;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < C::PER_THREAD; ++j) {
+        int i, k;
+        if (KFAST) {
+            k = t % C::BK;
+            i = t / C::BK + (NT / C::BK) * j;
+        } else {
+            i = t % BM;
+            k = t / BM + (NT / BM) * j;
+        }
+        const int64_t gi = r0 + i, gk = k0 + k;
+        T re = 0, im = 0;
+        if (gi < MN && gk < K) {
+            int64_t off;
+            bool cj = CONJ;
+            if (KFAST) {
+                off = gk + gi * ld;
+            } else if (hemm_diag && gk > gi) {
+                off = gk + gi * ld;  // upper element of a Hermitian tile: conj of lower
+                cj = true;
+            } else {
+                off = gi + (kmap ? (int64_t)kmap[gk] : gk) * ld;
+            }
+            if (CPLX) {
+                re = P[2 * off];
+                im = P[2 * off + 1];
+                if (cj) im = -im;
+            } else {
+                re = P[off];
+            }
+        }
+        reg[j][0] = re;
+        reg[j][1] = im;
+    }
+}
+
+template <typename T, bool CPLX, bool KFAST>
+__device__ inline void store_tile(T *__restrict__ S, const T (&reg)[Cfg<T, CPLX>::PER_THREAD][2]) {
+    typedef Cfg<T, CPLX> C;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < C::PER_THREAD; ++j) {
+        int i, k;
+        if (KFAST) {
+            k = t % C::BK;
+            i = t / C::BK + (NT / C::BK) * j;
+        } else {
+            i = t % BM;
+            k = t / BM + (NT / BM) * j;
+        }
+        const int idx = k * C::LDS_LD + i;
+        if (CPLX) {
+            S[2 * idx] = reg[j][0];
+            S[2 * idx + 1] = reg[j][1];
+        } else {
+            S[idx] = reg[j][0];
+        }
+    }
+}
+
+// opA: false = 'N', true = 'C'.  opB likewise.
+template <typename T, bool CPLX, bool CA, bool CB, int MODE>
+__global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs g, int64_t kchunk) {
+    typedef Cfg<T, CPLX> C;
+    typedef typename acc4<T>::type A4;
+    constexpr int EW = C::EW;
+    __shared__ T As[2][C::BK * C::LDS_LD * EW];
+    __shared__ T Bs[2][C::BK * C::LDS_LD * EW];
+
+    const T *__restrict__ A = (const T *)g.A;
+    const T *__restrict__ B = (const T *)g.B;
+    T *__restrict__ Cm = (T *)g.C;
+
+    int64_t tI, tJ;
+    if (MODE == GEMM_LOWER) {
+        const int64_t L = blockIdx.x;
+        int64_t I = (int64_t)((sqrt(8.0 * (double)L + 1.0) - 1.0) * 0.5);
+        while (I * (I + 1) / 2 > L) --I;
+        while ((I + 1) * (I + 2) / 2 <= L) ++I;
+        tI = I;
+        tJ = L - I * (I + 1) / 2;
+    } else {
+        tI = blockIdx.x;
+        tJ = blockIdx.y;
+    }
+    const int64_t m0 = tI * BM, n0 = tJ * BN;
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = min(g.K, kbeg + kchunk);
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+
+    A4 accR[2][2], accI[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            accR[a][b] = A4{0, 0, 0, 0};
+            accI[a][b] = A4{0, 0, 0, 0};
+        }
+
+    T ra[C::PER_THREAD][2], rb[C::PER_THREAD][2];
+
+    // A operand: 'N' -> i-fast, 'C' -> k-fast.  HEMM_L: per tile choice.
+    auto loadA = [&](int64_t k0) {
+        if (MODE == GEMM_HEMM_L) {
+            // block column of A holding k0 (tiles aligned to BM)
+            if (k0 + C::BK <= m0) {
+                load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, false);
+            } else if (k0 >= m0 + BM) {
+                load_tile<T, CPLX, true, true>(A, g.lda, m0, k0, g.M, kend, ra, false);
+            } else {
+                load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, true);
+            }
+        } else if (CA) {
+            load_tile<T, CPLX, true, true>(A, g.lda, m0, k0, g.M, kend, ra, false);
+        } else {
+            load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, false, g.acol);
+        }
+    };
+    auto storeA = [&](int buf, int64_t k0) {
+        bool kf;
+        if (MODE == GEMM_HEMM_L) kf = (k0 >= m0 + BM);
+        else kf = CA;
+        if (kf) store_tile<T, CPLX, true>(As[buf], ra);
+        else store_tile<T, CPLX, false>(As[buf], ra);
+    };
+    // B operand: 'N' -> k-fast (B stored K x N), 'C' -> i-fast (B stored N x K).
+    auto loadB = [&](int64_t k0) {
+        if (CB) load_tile<T, CPLX, false, true>(B, g.ldb, n0, k0, g.N, kend, rb, false);
+        else load_tile<T, CPLX, true, false>(B, g.ldb, n0, k0, g.N, kend, rb, false);
+    };
+    auto storeB = [&](int buf) {
+        if (CB) store_tile<T, CPLX, false>(Bs[buf], rb);
+        else store_tile<T, CPLX, true>(Bs[buf], rb);
+    };
+
+    if (kbeg < kend) {
+        loadA(kbeg);
+        loadB(kbeg);
+        storeA(0, kbeg);
+        storeB(0);
+        __syncthreads();
+        int buf = 0;
+        for (int64_t k0 = kbeg; k0 < kend; k0 += C::BK) {
+            const int64_t kn = k0 + C::BK;
+            const bool more = kn < kend;
+            if (more) {
+                loadA(kn);
+                loadB(kn);
+            }
+            const T *as = As[buf];
+            const T *bs = Bs[buf];
+#pragma unroll
+            for (int kk = 0; kk < C::BK; kk += 4) {
+                const int kr = kk + (lane >> 4);
+                T are[2], aim[2], bre[2], bim[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int idx = kr * C::LDS_LD + wm * 32 + a * 16 + (lane & 15);
+                    if (CPLX) {
+                        are[a] = as[2 * idx];
+                        aim[a] = as[2 * idx + 1];
+                    } else {
+                        are[a] = as[idx];
+                        aim[a] = 0;
+                    }
+                }
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int idx = kr * C::LDS_LD + wn * 32 + b * 16 + (lane & 15);
+                    if (CPLX) {
+                        bre[b] = bs[2 * idx];
+                        bim[b] = bs[2 * idx + 1];
+                    } else {
+                        bre[b] = bs[idx];
+                        bim[b] = 0;
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) accR[a][b] = mfma16(are[a], bre[b], accR[a][b]);
+                if (CPLX) {
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b) accI[a][b] = mfma16(are[a], bim[b], accI[a][b]);
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b) accR[a][b] = mfma16(-aim[a], bim[b], accR[a][b]);
+#pragma unroll
+                    for (int a = 0; a < 2; ++a)
+#pragma unroll
+                        for (int b = 0; b < 2; ++b) accI[a][b] = mfma16(aim[a], bre[b], accI[a][b]);
+                }
+            }
+            if (more) {
+                storeA(buf ^ 1, kn);
+                storeB(buf ^ 1);
+            }
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+
+    // epilogue
+    const bool to_part = g.splitk > 1;
+    T *__restrict__ P = (T *)g.part;
+    const T ar = (T)g.alpha_re, ai = (T)g.alpha_im, br = (T)g.beta_re, bi = (T)g.beta_im;
+    const bool beta0 = (br == (T)0 && bi == (T)0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int64_t col = n0 + wn * 32 + b * 16 + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t row = m0 + wm * 32 + a * 16 + mfma_row((T)0, lane, q);
+                if (row >= g.M || col >= g.N) continue;
+                const T vr = accR[a][b][q], vi = CPLX ? accI[a][b][q] : (T)0;
+                if (to_part) {
+                    const int64_t off = (int64_t)blockIdx.z * g.M * g.N + row + col * g.M;
+                    if (CPLX) {
+                        P[2 * off] = vr;
+                        P[2 * off + 1] = vi;
+                    } else {
+                        P[off] = vr;
+                    }
+                    continue;
+                }
+                const int64_t off = row + (g.ccol ? (int64_t)g.ccol[col] : col) * g.ldc;
+                if (CPLX) {
+                    T cr = ar * vr - ai * vi, ci = ar * vi + ai * vr;
+                    if (!beta0) {
+                        const T orr = Cm[2 * off], oi = Cm[2 * off + 1];
+                        cr += br * orr - bi * oi;
+                        ci += br * oi + bi * orr;
+                    }
+                    Cm[2 * off] = cr;
+                    Cm[2 * off + 1] = ci;
+                } else {
+                    T cr = ar * vr;
+                    if (!beta0) cr += br * Cm[off];
+                    Cm[off] = cr;
+                }
+            }
+        }
+}
+
+template <typename T, bool CPLX>
+__global__ void splitk_reduce(GemmArgs g) {
+    const int64_t total = g.M * g.N;
+    const T *__restrict__ P = (const T *)g.part;
+    T *__restrict__ Cm = (T *)g.C;
+    const T ar = (T)g.alpha_re, ai = (T)g.alpha_im, br = (T)g.beta_re, bi = (T)g.beta_im;
+    const bool beta0 = (br == (T)0 && bi == (T)0);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = e % g.M, col = e / g.M;
+        T vr = 0, vi = 0;
+        for (int z = 0; z < g.splitk; ++z) {
+            const int64_t off = (int64_t)z * total + e;
+            if (CPLX) {
+                vr += P[2 * off];
+                vi += P[2 * off + 1];
+            } else {
+                vr += P[off];
+            }
+        }
+        const int64_t off = row + (g.ccol ? (int64_t)g.ccol[col] : col) * g.ldc;
+        if (CPLX) {
+            T cr = ar * vr - ai * vi, ci = ar * vi + ai * vr;
+            if (!beta0) {
+                const T orr = Cm[2 * off], oi = Cm[2 * off + 1];
+                cr += br * orr - bi * oi;
+                ci += br * oi + bi * orr;
+            }
+            Cm[2 * off] = cr;
+            Cm[2 * off + 1] = ci;
+        } else {
+            T cr = ar * vr;
+            if (!beta0) cr += br * Cm[off];
+            Cm[off] = cr;
+        }
+    }
+}
+
+template <typename T, bool CPLX, bool CA, bool CB, int MODE>
+int launch(const GemmArgs &g, hipStream_t s) {
+    typedef Cfg<T, CPLX> C;
+    const int64_t tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+    int splitk = g.splitk > 1 ? g.splitk : 1;
+    int64_t kchunk = g.K;
+    if (splitk > 1) {
+        kchunk = (g.K + splitk - 1) / splitk;
+        kchunk = (kchunk + C::BK - 1) / C::BK * C::BK;
+        splitk = (int)((g.K + kchunk - 1) / kchunk);
+    }
+    if (kchunk <= 0) kchunk = C::BK;
+    GemmArgs h = g;
+    h.splitk = splitk;
+    dim3 grid;
+    if (MODE == GEMM_LOWER) {
+        grid = dim3((unsigned)(tm * (tm + 1) / 2), 1, splitk);
+    } else {
+        grid = dim3((unsigned)tm, (unsigned)tn, splitk);
+    }
+    if (tm <= 0 || tn <= 0) return 0;
+    hipLaunchKernelGGL((gemm_kernel<T, CPLX, CA, CB, MODE>), grid, dim3(NT), 0, s, h, kchunk);
+    BDG_CHECK_LAUNCH();
+    if (splitk > 1) {
+        const int64_t total = g.M * g.N;
+        int64_t blocks = (total + 255) / 256;
+        if (blocks > 4096) blocks = 4096;
+        hipLaunchKernelGGL((splitk_reduce<T, CPLX>), dim3((unsigned)blocks), dim3(256), 0, s, h);
+        BDG_CHECK_LAUNCH();
+    }
+    return 0;
+}
+
+}  // namespace
+
+template <typename T, bool CPLX>
+int gemm(char opA, char opB, const GemmArgs &g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0) return 0;
+    const bool ca = (opA == 'C' || opA == 'c' || opA == 'T' || opA == 't');
+    const bool cb = (opB == 'C' || opB == 'c' || opB == 'T' || opB == 't');
+    if (g.mode == GEMM_HEMM_L) {
+        if (cb) return launch<T, CPLX, false, true, GEMM_HEMM_L>(g, s);
+        return launch<T, CPLX, false, false, GEMM_HEMM_L>(g, s);
+    }
+    if (g.mode == GEMM_LOWER) {
+        if (!ca && cb) return launch<T, CPLX, false, true, GEMM_LOWER>(g, s);
+        if (!ca && !cb) return launch<T, CPLX, false, false, GEMM_LOWER>(g, s);
+        set_error("gemm: lower mode supports opA='N' only");
+        return BDG_ERR_NOT_IMPLEMENTED;
+    }
+    if (ca) {
+        if (cb) return launch<T, CPLX, true, true, GEMM_FULL>(g, s);
+        return launch<T, CPLX, true, false, GEMM_FULL>(g, s);
+    }
+    if (cb) return launch<T, CPLX, false, true, GEMM_FULL>(g, s);
+    return launch<T, CPLX, false, false, GEMM_FULL>(g, s);
+}
+
+template int gemm<double, true>(char, char, const GemmArgs &, hipStream_t);
+template int gemm<float, true>(char, char, const GemmArgs &, hipStream_t);
+template int gemm<double, false>(char, char, const GemmArgs &, hipStream_t);
+template int gemm<float, false>(char, char, const GemmArgs &, hipStream_t);
+
+}  // namespace bdg

@@ -1,0 +1,323 @@
+// Stage 2 of the two-stage reduction: Hermitian band -> real tridiagonal.
+//
+// Second step of the 2-stage solver ("then transforming the banded matrix
+// into a tridiagonal form", paper sec. "Performance of the Matrix
+// Diagonalization Algorithm"), by bulge chasing.  Sweep s removes column s
+// below the sub-diagonal; its task t works on the index range
+//   C = [r0 - b, r0), R = [r0, min(n, r0 + b)),  r0 = s + 1 + t b:
+//   t = 0 : reflector H_0 on rows s+1.. zeroes A[s+2:s+1+b, s]; two-sided on A[R, R].
+//   t >= 1: A[R, C] <- A[R, C] H_{t-1} (creates the bulge); reflector H_t zeroes
+//           A[r0+1:, r0-b] (first bulge column); A[R, C] <- H_t^H A[R, C];
+//           two-sided on A[R, R].
+// Consecutive sweeps lag by three tasks: task t of sweep s+1 only needs tasks
+// <= t+2 of sweep s, and task t+3 of sweep s touches indices disjoint from
+// task t of sweep s+1.  One launch executes every (s, t) with t = g - 3 s, so
+// the kernel boundary orders dependent tasks and needs no in-kernel waits.
+//
+// The band lives in lower band storage AB[(i - j) + j ldab] (ldab >= 2b + 2
+// holds the bulge).  Reflector (s, t) is stored with v_0 = 1 (length b, zero
+// padded) at V2 + b * (voff[s] + t), its scale at tau2[voff[s] + t].  On exit
+// d = real diag, e = complex sub-diagonal (phase scaled later).
+#include "stages.h"
+
+namespace bdg {
+namespace {
+
+constexpr int BMAX = 64;
+constexpr int LDS = BMAX + 1;
+
+__device__ inline double2 ld2(const double *p) { return *(const double2 *)p; }
+__device__ inline void st2(double *p, double2 v) { *(double2 *)p = v; }
+
+__global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, double *__restrict__ AB,
+                                                  int64_t ldab, double *__restrict__ V2,
+                                                  double *__restrict__ tau2,
+                                                  const int64_t *__restrict__ voff, int64_t g,
+                                                  int64_t s_lo) {
+    __shared__ double2 Bs[BMAX * LDS];
+    __shared__ double2 Ds[BMAX * LDS];
+    __shared__ double2 vp[BMAX], vn[BMAX], yv[BMAX], wv[BMAX];
+    __shared__ double red[4][2];
+    __shared__ double sc[8];
+    const int64_t s = s_lo + blockIdx.x;
+    const int64_t t = g - 3 * s;
+    if (s > n - 3 || t < 0) return;
+    const int64_t Ts = (n - 2 - s) / b + 1;
+    if (t >= Ts) return;
+    const int tid = threadIdx.x;
+    const int64_t r0 = s + 1 + t * b;
+    const int Lr = (int)min((int64_t)b, n - r0);
+    const int64_t ridx = voff[s] + t;
+
+    // ---- load x (t == 0) or B = A[R, C] and apply previous reflector from the right
+    if (t == 0) {
+        for (int r = tid; r < Lr; r += blockDim.x) vn[r] = ld2(AB + 2 * ((1 + r) + s * ldab));
+    } else {
+        const int64_t c0 = r0 - b;
+        for (int e = tid; e < Lr * b; e += blockDim.x) {
+            const int r = e % Lr, c = e / Lr;
+            Bs[r + c * LDS] = ld2(AB + 2 * ((b + r - c) + (c0 + c) * ldab));
+        }
+        for (int c = tid; c < b; c += blockDim.x) vp[c] = ld2(V2 + 2 * ((ridx - 1) * b + c));
+        const double tp = tau2[ridx - 1];
+        __syncthreads();
+        if (tp != 0.0) {
+            // y = B v (row sums): 4 threads per row
+            for (int base = 0; base < Lr * 4; base += blockDim.x) {
+                const int e = base + tid;
+                const int r = e >> 2, q = e & 3;
+                double yr = 0.0, yi = 0.0;
+                if (r < Lr) {
+                    for (int c = q; c < b; c += 4) {
+                        const double2 a = Bs[r + c * LDS], v = vp[c];
+                        yr += a.x * v.x - a.y * v.y;
+                        yi += a.x * v.y + a.y * v.x;
+                    }
+                }
+                yr += __shfl_xor(yr, 1, 64); yi += __shfl_xor(yi, 1, 64);
+                yr += __shfl_xor(yr, 2, 64); yi += __shfl_xor(yi, 2, 64);
+                if (r < Lr && q == 0) yv[r] = make_double2(tp * yr, tp * yi);
+            }
+            __syncthreads();
+            // B -= (tau y) v^H
+            for (int e = tid; e < Lr * b; e += blockDim.x) {
+                const int r = e % Lr, c = e / Lr;
+                const double2 y = yv[r], v = vp[c];
+                double2 a = Bs[r + c * LDS];
+                a.x -= y.x * v.x + y.y * v.y;
+                a.y -= y.y * v.x - y.x * v.y;
+                Bs[r + c * LDS] = a;
+            }
+            __syncthreads();
+        }
+        for (int r = tid; r < Lr; r += blockDim.x) vn[r] = Bs[r];
+    }
+    __syncthreads();
+
+    // ---- reflector from x = vn[0..Lr)
+    {
+        const int w = tid >> 6, l = tid & 63;
+        double t2 = 0.0;
+        for (int r = 1 + tid; r < Lr; r += blockDim.x) t2 += vn[r].x * vn[r].x + vn[r].y * vn[r].y;
+        t2 = wave_sum(t2);
+        if (l == 0) red[w][0] = t2;
+        __syncthreads();
+        if (tid == 0) {
+            const double tail2 = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+            const double ar = vn[0].x, ai = vn[0].y;
+            const double aa = sqrt(ar * ar + ai * ai);
+            if (tail2 == 0.0) {
+                sc[0] = 0.0; sc[1] = 0.0; sc[2] = 0.0; sc[3] = ar; sc[4] = ai;
+            } else {
+                const double xn = sqrt(aa * aa + tail2);
+                double sr = 1.0, si = 0.0;
+                if (aa > 0.0) { sr = ar / aa; si = ai / aa; }
+                const double den = aa + xn;
+                sc[0] = sr / den;     // 1/u0 = conj(sgn)/(|a| + |x|)
+                sc[1] = -si / den;
+                sc[2] = den / xn;     // tau
+                sc[3] = -sr * xn;     // beta
+                sc[4] = -si * xn;
+            }
+        }
+        __syncthreads();
+    }
+    const double tj = sc[2];
+    const double ur = sc[0], ui = sc[1];
+    const double2 beta = make_double2(sc[3], sc[4]);
+    // v: v_0 = 1, v_r = x_r / u0 ; stored (zero padded to b)
+    __syncthreads();
+    for (int r = tid; r < b; r += blockDim.x) {
+        double2 v;
+        if (r == 0) v = make_double2(1.0, 0.0);
+        else if (r < Lr && tj != 0.0) {
+            const double2 x = vn[r];
+            v = make_double2(x.x * ur - x.y * ui, x.x * ui + x.y * ur);
+        } else v = make_double2(0.0, 0.0);
+        wv[r] = v;  // wv temporarily holds v
+        st2(V2 + 2 * (ridx * b + r), v);
+    }
+    if (tid == 0) tau2[ridx] = tj;
+    __syncthreads();
+    for (int r = tid; r < b; r += blockDim.x) vn[r] = wv[r];
+    __syncthreads();
+
+    // ---- left application to B (t >= 1): column 0 -> beta e_0, others B -= tau v (v^H B)
+    if (t > 0) {
+        if (tj != 0.0) {
+            for (int base = 0; base < b * 4; base += blockDim.x) {
+                const int e = base + tid;
+                const int c = e >> 2, q = e & 3;
+                double sr = 0.0, si = 0.0;
+                if (c < b && c > 0) {
+                    for (int r = q; r < Lr; r += 4) {
+                        const double2 v = vn[r], a = Bs[r + c * LDS];
+                        sr += v.x * a.x + v.y * a.y;   // conj(v) a
+                        si += v.x * a.y - v.y * a.x;
+                    }
+                }
+                sr += __shfl_xor(sr, 1, 64); si += __shfl_xor(si, 1, 64);
+                sr += __shfl_xor(sr, 2, 64); si += __shfl_xor(si, 2, 64);
+                if (c < b && q == 0) wv[c] = make_double2(tj * sr, tj * si);
+            }
+            __syncthreads();
+            for (int e = tid; e < Lr * b; e += blockDim.x) {
+                const int r = e % Lr, c = e / Lr;
+                double2 a = Bs[r + c * LDS];
+                if (c == 0) {
+                    a = (r == 0) ? beta : make_double2(0.0, 0.0);
+                } else {
+                    const double2 v = vn[r], w = wv[c];
+                    a.x -= v.x * w.x - v.y * w.y;
+                    a.y -= v.x * w.y + v.y * w.x;
+                }
+                Bs[r + c * LDS] = a;
+            }
+            __syncthreads();
+        }
+        // write B back
+        const int64_t c0 = r0 - b;
+        for (int e = tid; e < Lr * b; e += blockDim.x) {
+            const int r = e % Lr, c = e / Lr;
+            st2(AB + 2 * ((b + r - c) + (c0 + c) * ldab), Bs[r + c * LDS]);
+        }
+    } else {
+        // t == 0: column s -> beta on the sub-diagonal, zeros below
+        for (int r = tid; r < Lr; r += blockDim.x) {
+            const double2 a = (tj == 0.0) ? ld2(AB + 2 * ((1 + r) + s * ldab))
+                                          : (r == 0 ? beta : make_double2(0.0, 0.0));
+            st2(AB + 2 * ((1 + r) + s * ldab), a);
+        }
+    }
+
+    // ---- two-sided application to D = A[R, R]
+    if (tj != 0.0) {
+        for (int e = tid; e < Lr * Lr; e += blockDim.x) {
+            const int r = e % Lr, c = e / Lr;
+            double2 a;
+            if (r >= c) a = ld2(AB + 2 * ((r - c) + (r0 + c) * ldab));
+            else {
+                a = ld2(AB + 2 * ((c - r) + (r0 + r) * ldab));
+                a.y = -a.y;
+            }
+            Ds[r + c * LDS] = a;
+        }
+        __syncthreads();
+        // p = tau D v
+        for (int base = 0; base < Lr * 4; base += blockDim.x) {
+            const int e = base + tid;
+            const int r = e >> 2, q = e & 3;
+            double pr = 0.0, pi = 0.0;
+            if (r < Lr) {
+                for (int c = q; c < Lr; c += 4) {
+                    const double2 a = Ds[r + c * LDS], v = vn[c];
+                    pr += a.x * v.x - a.y * v.y;
+                    pi += a.x * v.y + a.y * v.x;
+                }
+            }
+            pr += __shfl_xor(pr, 1, 64); pi += __shfl_xor(pi, 1, 64);
+            pr += __shfl_xor(pr, 2, 64); pi += __shfl_xor(pi, 2, 64);
+            if (r < Lr && q == 0) yv[r] = make_double2(tj * pr, tj * pi);
+        }
+        __syncthreads();
+        // K = (tau/2) v^H p
+        {
+            const int w = tid >> 6, l = tid & 63;
+            double kr = 0.0, ki = 0.0;
+            for (int r = tid; r < Lr; r += blockDim.x) {
+                const double2 v = vn[r], p = yv[r];
+                kr += v.x * p.x + v.y * p.y;
+                ki += v.x * p.y - v.y * p.x;
+            }
+            kr = wave_sum(kr);
+            ki = wave_sum(ki);
+            if (l == 0) { red[w][0] = kr; red[w][1] = ki; }
+            __syncthreads();
+            if (tid == 0) {
+                sc[5] = 0.5 * tj * (red[0][0] + red[1][0] + red[2][0] + red[3][0]);
+                sc[6] = 0.5 * tj * (red[0][1] + red[1][1] + red[2][1] + red[3][1]);
+            }
+            __syncthreads();
+        }
+        // w = p - K v
+        {
+            const double Kr = sc[5], Ki = sc[6];
+            for (int r = tid; r < Lr; r += blockDim.x) {
+                const double2 v = vn[r], p = yv[r];
+                wv[r] = make_double2(p.x - (Kr * v.x - Ki * v.y), p.y - (Kr * v.y + Ki * v.x));
+            }
+        }
+        __syncthreads();
+        // D -= v w^H + w v^H  (lower part written back)
+        for (int e = tid; e < Lr * Lr; e += blockDim.x) {
+            const int r = e % Lr, c = e / Lr;
+            if (r < c) continue;
+            const double2 vr = vn[r], vc = vn[c], wr = wv[r], wc = wv[c];
+            double2 a = Ds[r + c * LDS];
+            // v_r conj(w_c) + w_r conj(v_c)
+            a.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
+            a.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
+            if (r == c) a.y = 0.0;
+            st2(AB + 2 * ((r - c) + (r0 + c) * ldab), a);
+        }
+    }
+}
+
+__global__ void hb2st_extract(int64_t n, const double *__restrict__ AB, int64_t ldab,
+                              double *__restrict__ d, double *__restrict__ e_cplx) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        d[i] = AB[2 * (i * ldab)];
+        if (i + 1 < n) {
+            e_cplx[2 * i] = AB[2 * (1 + i * ldab)];
+            e_cplx[2 * i + 1] = AB[2 * (1 + i * ldab) + 1];
+        }
+    }
+}
+
+}  // namespace
+
+int64_t hb2st_nrefl(int64_t n, int b) {
+    int64_t tot = 0;
+    for (int64_t s = 0; s <= n - 3; ++s) tot += (n - 2 - s) / b + 1;
+    return tot;
+}
+
+void hb2st_offsets(int64_t n, int b, int64_t *voff_host) {
+    int64_t tot = 0;
+    for (int64_t s = 0; s <= n - 3; ++s) {
+        voff_host[s] = tot;
+        tot += (n - 2 - s) / b + 1;
+    }
+}
+
+int hb2st(int64_t n, int b, double *AB, int64_t ldab, double *V2, double *tau2,
+          const int64_t *voff_dev, double *d, double *e_cplx, hipStream_t s) {
+    if (b > BMAX) {
+        set_error("hb2st: band %d > %d", b, BMAX);
+        return BDG_ERR_NOT_IMPLEMENTED;
+    }
+    if (n >= 3) {
+        const int64_t nsw = n - 2;  // sweeps 0 .. n-3
+        const int64_t T0 = (n - 2) / b + 1;
+        const int64_t gmax = 3 * (nsw - 1) + T0;  // last step index + 1 upper bound
+        int64_t s_lo = 0;
+        for (int64_t g = 0; g < gmax; ++g) {
+            // smallest sweep still active at step g: g - 3 s < T_s
+            while (s_lo < nsw && g - 3 * s_lo >= (n - 2 - s_lo) / b + 1) ++s_lo;
+            if (s_lo >= nsw) break;
+            int64_t s_hi = g / 3;
+            if (s_hi > nsw - 1) s_hi = nsw - 1;
+            if (s_hi < s_lo) continue;
+            hipLaunchKernelGGL(hb2st_step, dim3((unsigned)(s_hi - s_lo + 1)), dim3(256), 0, s, n, b,
+                               AB, ldab, V2, tau2, voff_dev, g, s_lo);
+        }
+        BDG_CHECK_LAUNCH();
+    }
+    hipLaunchKernelGGL(hb2st_extract, dim3((unsigned)((n + 255) / 256 > 1024 ? 1024 : (n + 255) / 256)),
+                       dim3(256), 0, s, n, AB, ldab, d, e_cplx);
+    BDG_CHECK_LAUNCH();
+    return 0;
+}
+
+}  // namespace bdg

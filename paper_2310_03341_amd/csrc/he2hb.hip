@@ -1,0 +1,464 @@
+// Stage 1 of the two-stage reduction: Hermitian dense -> Hermitian band.
+//
+// First step of the 2-stage solver ("first transforming the dense matrix in a
+// banded matrix", paper sec. "Performance of the Matrix Diagonalization
+// Algorithm").  For each panel of b columns starting at k:
+//   P = A[k+b:n, k:k+b] = Q R          (Householder QR, Q = I - V T V^H)
+//   A22 = A[k+b:n, k+b:n] <- Q^H A22 Q = A22 - V W^H - W V^H,
+//   with X = A22 V T, W = X - 1/2 V (T^H V^H X).
+// R lands on the b-th sub-diagonal band; V (unit lower trapezoidal, stored
+// explicitly with its zeros and ones) stays in A's panel for the
+// back-transformation; T is kept per panel.
+//
+// The panel QR runs one column per launch over many workgroups (each owns a
+// chunk of rows); a launch applies reflector j and, in the same pass, forms
+// the partial norms and inner products that define reflector j+1.  All the
+// O(n^3) work (HEMM, HER2K and small GEMMs) goes through the MFMA tile kernel.
+#include "gemm.h"
+#include "stages.h"
+
+namespace bdg {
+namespace {
+
+constexpr int PQ_ROWS = 256;  // rows per workgroup in the panel kernels
+constexpr int MAXB = 64;      // largest supported band
+
+// Partials layout per workgroup: [0..nb) complex s_c, [nb] (tail2, 0).
+__device__ inline void reduce_partials(const double *__restrict__ part, int G, int nb,
+                                       double *__restrict__ s_sh /* 2*(nb+1) */) {
+    // 4 threads per column (256 threads)
+    __shared__ double tmp[4][2 * (MAXB + 1)];
+    const int t = threadIdx.x;
+    for (int col = t & 63; col <= nb; col += 64) {
+        const int g0 = t >> 6;
+        double re = 0.0, im = 0.0;
+        for (int g = g0; g < G; g += 4) {
+            const double *p = part + (size_t)g * 2 * (nb + 1) + 2 * col;
+            re += p[0];
+            im += p[1];
+        }
+        tmp[g0][2 * col] = re;
+        tmp[g0][2 * col + 1] = im;
+    }
+    __syncthreads();
+    for (int col = t; col <= nb; col += blockDim.x) {
+        double re = 0.0, im = 0.0;
+        for (int g = 0; g < 4; ++g) {
+            re += tmp[g][2 * col];
+            im += tmp[g][2 * col + 1];
+        }
+        s_sh[2 * col] = re;
+        s_sh[2 * col + 1] = im;
+    }
+    __syncthreads();
+}
+
+// One column step of the panel QR.
+//   j >= 0: apply reflector j (from partials in part_in / row_in) to the panel.
+//   j+1 < ncol: write partials for column j+1 to part_out / row_out.
+__global__ __launch_bounds__(256) void panel_step(double *__restrict__ P, int64_t ld, int64_t mr,
+                                                  int nb, int j, int ncol,
+                                                  const double *__restrict__ part_in,
+                                                  const double *__restrict__ row_in,
+                                                  double *__restrict__ part_out,
+                                                  double *__restrict__ row_out,
+                                                  double *__restrict__ tau, int G) {
+    __shared__ double s_sh[2 * (MAXB + 1)];
+    __shared__ double wc[2 * MAXB];
+    __shared__ double red[4][2 * (MAXB + 1)];
+    __shared__ double sc[6];  // u0inv (re, im), tau, beta (re, im), active
+    const int t = threadIdx.x;
+    const int64_t r = (int64_t)blockIdx.x * PQ_ROWS + t;  // panel row of this thread
+    const bool have = r < mr;
+
+    if (j >= 0) {
+        reduce_partials(part_in, G, nb, s_sh);
+        if (t == 0) {
+            const double ar = row_in[2 * j], ai = row_in[2 * j + 1];
+            const double tail2 = s_sh[2 * nb];
+            const double aa = sqrt(ar * ar + ai * ai);
+            if (tail2 == 0.0) {
+                sc[0] = 0.0; sc[1] = 0.0; sc[2] = 0.0; sc[3] = ar; sc[4] = ai; sc[5] = 0.0;
+            } else {
+                const double xn = sqrt(aa * aa + tail2);
+                double sr = 1.0, si = 0.0;
+                if (aa > 0.0) { sr = ar / aa; si = ai / aa; }
+                const double br = -sr * xn, bi = -si * xn;
+                // u0 = alpha - beta = sgn (|alpha| + xn); 1/u0 = conj(sgn) / (|alpha| + xn)
+                const double den = aa + xn;
+                sc[0] = sr / den;
+                sc[1] = -si / den;
+                sc[2] = den / xn;  // tau
+                sc[3] = br;
+                sc[4] = bi;
+                sc[5] = 1.0;
+            }
+        }
+        __syncthreads();
+        const double tj = sc[2];
+        const double ur = sc[0], ui = sc[1];
+        const bool active = sc[5] != 0.0;
+        if (blockIdx.x == 0 && t == 0) tau[j] = tj;
+        if (active) {
+            // w_c = (s_c - conj(beta) P[j,c]) / conj(u0), scaled by tau: tw_c = tau * w_c
+            const double br = sc[3], bi = sc[4];
+            for (int c = j + 1 + t; c < nb; c += blockDim.x) {
+                const double sr = s_sh[2 * c], si = s_sh[2 * c + 1];
+                const double pr = row_in[2 * c], pi = row_in[2 * c + 1];
+                // s - conj(beta) * p
+                const double nr = sr - (br * pr + bi * pi);
+                const double ni = si - (br * pi - bi * pr);
+                // / conj(u0) == * conj(1/u0)   (1/conj(u0) = conj(1/u0))
+                const double cr = ur, ci = -ui;
+                wc[2 * c] = tj * (nr * cr - ni * ci);
+                wc[2 * c + 1] = tj * (nr * ci + ni * cr);
+            }
+            __syncthreads();
+            if (have && r >= j) {
+                // v_r: 1 at r == j, x_r / u0 below
+                double vr, vi;
+                double *pj = P + 2 * (r + (int64_t)j * ld);
+                if (r == j) {
+                    vr = 1.0; vi = 0.0;
+                    pj[0] = sc[3];
+                    pj[1] = sc[4];
+                } else {
+                    const double xr = pj[0], xi = pj[1];
+                    vr = xr * ur - xi * ui;
+                    vi = xr * ui + xi * ur;
+                    pj[0] = vr;
+                    pj[1] = vi;
+                }
+                for (int c = j + 1; c < nb; ++c) {
+                    double *pc = P + 2 * (r + (int64_t)c * ld);
+                    const double wr = wc[2 * c], wi = wc[2 * c + 1];
+                    pc[0] -= vr * wr - vi * wi;
+                    pc[1] -= vr * wi + vi * wr;
+                }
+            }
+        } else if (have && r == j) {
+            // no reflector: R diagonal keeps alpha (already in place)
+        }
+        __syncthreads();
+    }
+
+    const int jn = j + 1;
+    if (jn < ncol) {
+        // partials for column jn over rows r >= jn
+        double xr = 0.0, xi = 0.0;
+        const bool in = have && r >= jn;
+        if (in) {
+            const double *px = P + 2 * (r + (int64_t)jn * ld);
+            xr = px[0];
+            xi = px[1];
+        }
+        const int w = t >> 6, l = t & 63;
+        // tail2 over r > jn
+        double t2 = (in && r > jn) ? xr * xr + xi * xi : 0.0;
+        t2 = wave_sum(t2);
+        if (l == 0) { red[w][2 * nb] = t2; red[w][2 * nb + 1] = 0.0; }
+        for (int c = jn + 1; c < nb; ++c) {
+            double pr = 0.0, pi = 0.0;
+            if (in) {
+                const double *pc = P + 2 * (r + (int64_t)c * ld);
+                pr = pc[0];
+                pi = pc[1];
+            }
+            // conj(x) * p
+            double sr = xr * pr + xi * pi, si = xr * pi - xi * pr;
+            sr = wave_sum(sr);
+            si = wave_sum(si);
+            if (l == 0) { red[w][2 * c] = sr; red[w][2 * c + 1] = si; }
+        }
+        __syncthreads();
+        for (int c = t; c <= nb; c += blockDim.x) {
+            double sr = 0.0, si = 0.0;
+            if (c > jn) {
+                for (int q = 0; q < 4; ++q) { sr += red[q][2 * c]; si += red[q][2 * c + 1]; }
+            }
+            part_out[(size_t)blockIdx.x * 2 * (nb + 1) + 2 * c] = sr;
+            part_out[(size_t)blockIdx.x * 2 * (nb + 1) + 2 * c + 1] = si;
+        }
+        if (have && r == jn) {
+            for (int c = 0; c < nb; ++c) {
+                row_out[2 * c] = P[2 * (r + (int64_t)c * ld)];
+                row_out[2 * c + 1] = P[2 * (r + (int64_t)c * ld) + 1];
+            }
+        }
+    }
+}
+
+// Copy the finished band columns [k, k+nb) into lower band storage AB: the
+// diagonal block (rows < k+b) and R (rows k+b .. k+b+c of column k+c).
+__global__ void panel_band(const double *__restrict__ A, int64_t lda, int64_t n, int64_t k, int b,
+                           double *__restrict__ AB, int64_t ldab) {
+    const int c = blockIdx.y;
+    const int64_t j = k + c;
+    for (int64_t d = threadIdx.x; d < ldab; d += blockDim.x) {
+        const int64_t i = j + d;
+        double re = 0.0, im = 0.0;
+        if (i < n && (i < k + b || i - (k + b) <= c)) {
+            re = A[2 * (i + j * lda)];
+            im = A[2 * (i + j * lda) + 1];
+        }
+        AB[2 * (d + j * ldab)] = re;
+        AB[2 * (d + j * ldab) + 1] = im;
+    }
+}
+
+// Write V explicitly (zeros above, ones on the diagonal) into the panel, into
+// VW[:, 0:nb] and into WV[:, nb:2nb].
+__global__ void panel_explicit_v(double *__restrict__ A, int64_t lda, int64_t k, int b, int nb,
+                                 int64_t mr, double *__restrict__ VW, double *__restrict__ WV,
+                                 int64_t ldw) {
+    const int c = blockIdx.y;
+    const int64_t j = k + c;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < mr;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        double *p = A + 2 * ((k + b + r) + j * lda);
+        double vr, vi;
+        if (r < c) { vr = 0.0; vi = 0.0; }
+        else if (r == c) { vr = 1.0; vi = 0.0; }
+        else { vr = p[0]; vi = p[1]; }
+        p[0] = vr;
+        p[1] = vi;
+        VW[2 * (r + (int64_t)c * ldw)] = vr;
+        VW[2 * (r + (int64_t)c * ldw) + 1] = vi;
+        WV[2 * (r + (int64_t)(nb + c) * ldw)] = vr;
+        WV[2 * (r + (int64_t)(nb + c) * ldw) + 1] = vi;
+    }
+}
+
+// Band columns that need no reduction: copy lower band of A.
+__global__ void band_copy_tail(const double *__restrict__ A, int64_t lda, int64_t n, int64_t j0,
+                               double *__restrict__ AB, int64_t ldab) {
+    const int64_t j = j0 + blockIdx.y;
+    for (int64_t d = threadIdx.x; d < ldab; d += blockDim.x) {
+        const int64_t i = j + d;
+        double re = 0.0, im = 0.0;
+        if (i < n) {
+            re = A[2 * (i + j * lda)];
+            im = A[2 * (i + j * lda) + 1];
+        }
+        AB[2 * (d + j * ldab)] = re;
+        AB[2 * (d + j * ldab) + 1] = im;
+    }
+}
+
+// T from G = V^H V and tau: T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j,0:j] G[0:j, j].
+// One workgroup; T upper triangular nb x nb (ld nb), zeros below.
+__global__ void tfactor(int nb, const double *__restrict__ G, const double *__restrict__ tau,
+                        double *__restrict__ T) {
+    __shared__ double Ts[2 * MAXB * MAXB];
+    const int t = threadIdx.x;
+    for (int e = t; e < nb * nb; e += blockDim.x) { Ts[2 * e] = 0.0; Ts[2 * e + 1] = 0.0; }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        const double tj = tau[j];
+        if (t < j) {
+            double sr = 0.0, si = 0.0;
+            for (int l = t; l < j; ++l) {
+                const double ar = Ts[2 * (t + l * nb)], ai = Ts[2 * (t + l * nb) + 1];
+                const double gr = G[2 * (l + j * nb)], gi = G[2 * (l + j * nb) + 1];
+                sr += ar * gr - ai * gi;
+                si += ar * gi + ai * gr;
+            }
+            Ts[2 * (t + j * nb)] = -tj * sr;
+            Ts[2 * (t + j * nb) + 1] = -tj * si;
+        }
+        if (t == j) { Ts[2 * (j + j * nb)] = tj; Ts[2 * (j + j * nb) + 1] = 0.0; }
+        __syncthreads();
+    }
+    for (int e = t; e < nb * nb; e += blockDim.x) { T[2 * e] = Ts[2 * e]; T[2 * e + 1] = Ts[2 * e + 1]; }
+}
+
+__global__ void copy_cols(const double *__restrict__ src, int64_t lds, double *__restrict__ dst,
+                          int64_t ldd, int64_t rows) {
+    const int c = blockIdx.y;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        dst[2 * (r + c * ldd)] = src[2 * (r + c * lds)];
+        dst[2 * (r + c * ldd) + 1] = src[2 * (r + c * lds) + 1];
+    }
+}
+
+int splitk_for(int64_t tiles, int64_t K) {
+    // aim for >= 512 workgroups, chunks of at least 512 along K
+    int64_t s = (512 + tiles - 1) / tiles;
+    const int64_t kmax = (K + 511) / 512;
+    if (s > kmax) s = kmax;
+    if (s < 1) s = 1;
+    if (s > 64) s = 64;
+    return (int)s;
+}
+
+}  // namespace
+
+size_t he2hb_workspace(int64_t n, int b) {
+    const size_t z = 16;
+    size_t w = 0;
+    w += z * (size_t)n * 2 * b * 2;              // VW, WV
+    w += z * (size_t)n * b;                       // Y
+    w += z * (size_t)b * b * 3;                   // G, S, M
+    w += z * 64 * (size_t)n * b;                  // split-K partials (upper bound)
+    w += z * 2 * ((size_t)(n / PQ_ROWS + 2) * (b + 1) + b) * 2;  // panel partials + rows
+    w += 8 * (size_t)b;                           // tau
+    w += 4096;
+    return w;
+}
+
+int he2hb(int64_t n, double *A, int64_t lda, int b, double *AB, int64_t ldab, double *T1,
+          void *work, hipStream_t s) {
+    if (b < 1 || b > MAXB) {
+        set_error("he2hb: band %d outside [1, %d]", b, MAXB);
+        return BDG_ERR_NOT_IMPLEMENTED;
+    }
+    if (ldab < 2 * b + 2) {
+        set_error("he2hb: ldab %lld < 2b+2", (long long)ldab);
+        return BDG_ERR_WORKSPACE;
+    }
+    char *wp = (char *)work;
+    auto take = [&](size_t bytes) {
+        char *p = wp;
+        wp += (bytes + 255) / 256 * 256;
+        return (double *)p;
+    };
+    const int64_t ldw = n;
+    double *VW = take(16 * (size_t)n * 2 * b);
+    double *WV = take(16 * (size_t)n * 2 * b);
+    double *Y = take(16 * (size_t)n * b);
+    double *Gm = take(16 * (size_t)b * b);
+    double *Sm = take(16 * (size_t)b * b);
+    double *Mm = take(16 * (size_t)b * b);
+    double *part = take(16 * 64 * (size_t)n * b);
+    const int64_t Gmax = n / PQ_ROWS + 2;
+    double *ppart[2], *prow[2];
+    ppart[0] = take(16 * (size_t)Gmax * (b + 1));
+    ppart[1] = take(16 * (size_t)Gmax * (b + 1));
+    prow[0] = take(16 * (size_t)b);
+    prow[1] = take(16 * (size_t)b);
+    double *tau = take(8 * (size_t)b);
+
+    int64_t k = 0;
+    int p = 0;
+    for (; k + b + 1 < n; k += b, ++p) {
+        const int nb = b;
+        const int64_t mr = n - k - b;
+        double *P = A + 2 * ((k + b) + k * lda);
+        const int ncol = (int)(mr < nb ? mr : nb);
+        const int G = (int)((mr + PQ_ROWS - 1) / PQ_ROWS);
+        BDG_HIP(hipMemsetAsync(tau, 0, 8 * (size_t)nb, s));
+        for (int j = -1; j < ncol; ++j) {
+            const int ib = (j + 2) & 1;   // buffer read by step j
+            const int ob = (j + 3) & 1;   // buffer written for column j+1
+            hipLaunchKernelGGL(panel_step, dim3(G), dim3(256), 0, s, P, lda, mr, nb, j, ncol,
+                               ppart[ib], prow[ib], ppart[ob], prow[ob], tau, G);
+            BDG_CHECK_LAUNCH();
+        }
+        // band columns, then explicit V (overwrites R in A)
+        hipLaunchKernelGGL(panel_band, dim3(1, nb), dim3(256), 0, s, A, lda, n, k, b, AB, ldab);
+        BDG_CHECK_LAUNCH();
+        {
+            int64_t gx = (mr + 255) / 256;
+            if (gx > 16) gx = 16;
+            hipLaunchKernelGGL(panel_explicit_v, dim3((unsigned)gx, nb), dim3(256), 0, s, A, lda,
+                               k, b, nb, mr, VW, WV, ldw);
+            BDG_CHECK_LAUNCH();
+        }
+        double *T = T1 + 2 * (size_t)p * b * b;
+        // G = V^H V
+        {
+            GemmArgs g{nb, nb, mr, 1.0, 0.0, 0.0, 0.0, VW, ldw, VW, ldw, Gm, nb, GEMM_FULL,
+                       splitk_for(1, mr), part};
+            BDG_TRY((gemm<double, true>('C', 'N', g, s)));
+        }
+        hipLaunchKernelGGL(tfactor, dim3(1), dim3(256), 0, s, nb, Gm, tau, T);
+        BDG_CHECK_LAUNCH();
+        // Y = A22 V  (A22 Hermitian, lower triangle valid)
+        double *A22 = A + 2 * ((k + b) + (k + b) * lda);
+        {
+            const int64_t tiles = (mr + 63) / 64;
+            GemmArgs g{mr, nb, mr, 1.0, 0.0, 0.0, 0.0, A22, lda, VW, ldw, Y, ldw, GEMM_HEMM_L,
+                       splitk_for(tiles, mr), part};
+            BDG_TRY((gemm<double, true>('N', 'N', g, s)));
+        }
+        // X = Y T  -> VW[:, nb:2nb]
+        double *X = VW + 2 * (size_t)nb * ldw;
+        {
+            GemmArgs g{mr, nb, nb, 1.0, 0.0, 0.0, 0.0, Y, ldw, T, nb, X, ldw, GEMM_FULL, 1, nullptr};
+            BDG_TRY((gemm<double, true>('N', 'N', g, s)));
+        }
+        // S = V^H X
+        {
+            GemmArgs g{nb, nb, mr, 1.0, 0.0, 0.0, 0.0, VW, ldw, X, ldw, Sm, nb, GEMM_FULL,
+                       splitk_for(1, mr), part};
+            BDG_TRY((gemm<double, true>('C', 'N', g, s)));
+        }
+        // M = T^H S
+        {
+            GemmArgs g{nb, nb, nb, 1.0, 0.0, 0.0, 0.0, T, nb, Sm, nb, Mm, nb, GEMM_FULL, 1, nullptr};
+            BDG_TRY((gemm<double, true>('C', 'N', g, s)));
+        }
+        // W = X - 1/2 V M  (in place in X)
+        {
+            GemmArgs g{mr, nb, nb, -0.5, 0.0, 1.0, 0.0, VW, ldw, Mm, nb, X, ldw, GEMM_FULL, 1, nullptr};
+            BDG_TRY((gemm<double, true>('N', 'N', g, s)));
+        }
+        // WV[:, 0:nb] = W
+        {
+            dim3 grid((unsigned)(((mr + 255) / 256) > 16 ? 16 : (mr + 255) / 256), nb);
+            hipLaunchKernelGGL(copy_cols, grid, dim3(256), 0, s, X, ldw, WV, ldw, mr);
+            BDG_CHECK_LAUNCH();
+        }
+        // A22 -= [V W] [W V]^H   (lower tiles)
+        {
+            GemmArgs g{mr, mr, 2 * (int64_t)nb, -1.0, 0.0, 1.0, 0.0, VW, ldw, WV, ldw, A22, lda,
+                       GEMM_LOWER, 1, nullptr};
+            BDG_TRY((gemm<double, true>('N', 'C', g, s)));
+        }
+    }
+    // remaining columns are already inside the band
+    if (k < n) {
+        dim3 grid(1, (unsigned)(n - k));
+        hipLaunchKernelGGL(band_copy_tail, grid, dim3(256), 0, s, A, lda, n, k, AB, ldab);
+        BDG_CHECK_LAUNCH();
+    }
+    return 0;
+}
+
+int he2hb_panels(int64_t n, int b) {
+    int p = 0;
+    for (int64_t k = 0; k + b + 1 < n; k += b) ++p;
+    return p;
+}
+
+}  // namespace bdg
+
+namespace bdg {
+
+// Back-transformation 1: Z <- Q1 Z = Q_0 Q_1 ... Q_last Z, Q_p = I - V_p T_p V_p^H
+// acting on rows k_p + b .. n-1; V_p explicit in A's panel p.
+int bt1(int64_t n, int64_t m, const double *A, int64_t lda, int b, const double *T1, double *Z,
+        int64_t ldz, void *work, hipStream_t s) {
+    const int np = he2hb_panels(n, b);
+    double *W1 = (double *)work;                 // b x m
+    double *W2 = W1 + 2 * (size_t)b * m;         // b x m
+    for (int p = np - 1; p >= 0; --p) {
+        const int64_t k = (int64_t)p * b;
+        const int64_t mr = n - k - b;
+        const double *V = A + 2 * ((k + b) + k * lda);
+        const double *T = T1 + 2 * (size_t)p * b * b;
+        double *Zs = Z + 2 * (k + b);
+        GemmArgs g1{b, m, mr, 1.0, 0.0, 0.0, 0.0, V, lda, Zs, ldz, W1, b, GEMM_FULL, 1, nullptr};
+        BDG_TRY((gemm<double, true>('C', 'N', g1, s)));
+        GemmArgs g2{b, m, b, 1.0, 0.0, 0.0, 0.0, T, b, W1, b, W2, b, GEMM_FULL, 1, nullptr};
+        BDG_TRY((gemm<double, true>('N', 'N', g2, s)));
+        GemmArgs g3{mr, m, b, -1.0, 0.0, 1.0, 0.0, V, lda, W2, b, Zs, ldz, GEMM_FULL, 1, nullptr};
+        BDG_TRY((gemm<double, true>('N', 'N', g3, s)));
+    }
+    return 0;
+}
+
+size_t bt1_workspace(int64_t m, int b) { return 2 * 16 * (size_t)b * (size_t)m + 256; }
+
+}  // namespace bdg

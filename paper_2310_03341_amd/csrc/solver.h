@@ -1,0 +1,23 @@
+// Internal interfaces between the C-ABI layer and the solver stages.
+#pragma once
+#include "common.h"
+
+namespace bdg {
+
+int assemble(const bdg_lattice *lat, const double *U, const double *Delta, double mu, double *H,
+             int64_t ldh, hipStream_t s);
+
+int check_pairs(int64_t n, const double *H, int64_t ldh, int64_t m, const double *W,
+                const double *Z, int64_t ldz, double *max_resid, double *gram_defect, void *work,
+                hipStream_t s);
+
+}  // namespace bdg
+
+namespace bdg {
+
+int eigh_workspace(int64_t n, const bdg_opts *opts, size_t *bytes);
+int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W, double *Z,
+         int64_t ldz, int64_t zcols, int64_t *m, const bdg_opts *opts, void *work,
+         size_t work_bytes, bdg_err_report *report, hipStream_t s);
+
+}  // namespace bdg
