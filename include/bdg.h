@@ -129,6 +129,40 @@ int bdg_eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double
              void *work, size_t work_bytes, bdg_err_report *report, bdg_stream_t stream);
 
 /*
+ * Constants of one self-consistency step (the SLDA loop of "Methods").
+ *   U' = Vext + B eps_F(n)   (eps_F = pi n in 2D, (3 pi^2 n)^(2/3)/2 in 3D),
+ *   |Delta|' = g |nu|        (pairing field Delta = g nu, phase held fixed),
+ *   U, |Delta| <- (1 - alpha) old + alpha new,  states with 0 < E < Ec.
+ */
+typedef struct {
+    double B;     /* coefficient of the density term of U               */
+    double g;     /* pairing coupling                                   */
+    double alpha; /* linear mixing weight                               */
+    double Ec;    /* energy cutoff (pi^2/2 = k_max^2/2 on the unit grid) */
+} bdg_scf_params;
+
+/* bdg_scf_workspace -- device workspace (bytes) of bdg_scf_step for `lat`. */
+int bdg_scf_workspace(const bdg_lattice *lat, size_t *bytes);
+
+/*
+ * bdg_scf_step -- one zero-temperature SLDA self-consistency step on the GPU:
+ * assemble H(U, |Delta| e^{i theta}, mu), diagonalise with the window
+ * 0 < E < Ec, form n(r) = 2 sum |v_n|^2 and nu(r) = sum u_n v_n^* (eq.
+ * densities2 at T = 0), update and mix U and |Delta|.
+ *   Vext, theta [nsites] f64 device (external potential, fixed pairing phase).
+ *   U, absDelta [nsites] f64 device, in/out.
+ *   density, nu_abs [nsites] f64 device outputs (may be NULL).
+ *   change  host output: max(|U' - U|, ||Delta|' - |Delta||) before mixing.
+ *   m       host output: number of states in the window.
+ *   work    device workspace of bdg_scf_workspace bytes.
+ * Synchronises `stream`.
+ */
+int bdg_scf_step(const bdg_lattice *lat, const double *Vext, const double *theta, double mu,
+                 const bdg_scf_params *params, double *U, double *absDelta, double *density,
+                 double *nu_abs, double *change, int64_t *m, void *work, size_t work_bytes,
+                 bdg_stream_t stream);
+
+/*
  * bdg_check -- FP64 accuracy of m eigenpairs (W, Z) of the Hermitian H.
  *   H [ldh x n] complex128 (full storage, both triangles read).
  *   max_resid   = max_j ||H z_j - w_j z_j||_2 / max_j |w_j| (host output)

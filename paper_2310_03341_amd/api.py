@@ -296,3 +296,46 @@ def stage_bt1(A, T1, Z, band: int = 64):
     _call("bdg_stage_bt1", n, m, _dev(A), _ld(A), band, _dev(T1), _dev(Z), _ld(Z), _dev(work),
           work.numel(), _stream(Z.device))
     return Z
+
+
+# ---------------------------------------------------------------- SCF step
+class ScfParamsC(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_double), ("g", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("Ec", ctypes.c_double)]
+
+
+def _scf_sigs(L):
+    P, I64, D, S = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    L.bdg_scf_workspace.argtypes = [ctypes.POINTER(Lattice), ctypes.POINTER(ctypes.c_size_t)]
+    L.bdg_scf_step.argtypes = [ctypes.POINTER(Lattice), P, P, D, ctypes.POINTER(ScfParamsC), P, P, P,
+                               P, ctypes.POINTER(D), ctypes.POINTER(I64), P, ctypes.c_size_t, S]
+
+
+class ScfStepper:
+    """Workspace + fixed inputs of the SCF step on one lattice (device tensors)."""
+
+    def __init__(self, dims, Vext: torch.Tensor, theta: torch.Tensor, mu: float, params):
+        L = lib()
+        _scf_sigs(L)
+        self.lat = Lattice()
+        self.lat.ndim = len(dims)
+        for d, v in enumerate(dims):
+            self.lat.dims[d] = int(v)
+        self.Vext, self.theta, self.mu = Vext, theta, float(mu)
+        self.p = ScfParamsC(params.B, params.g, params.alpha, params.Ec)
+        nb = ctypes.c_size_t(0)
+        _call("bdg_scf_workspace", ctypes.byref(self.lat), ctypes.byref(nb))
+        self.work = torch.empty(int(nb.value), dtype=torch.uint8, device=Vext.device)
+        ns = Vext.numel()
+        self.density = torch.zeros(ns, dtype=torch.float64, device=Vext.device)
+        self.nu_abs = torch.zeros(ns, dtype=torch.float64, device=Vext.device)
+
+    def step(self, U: torch.Tensor, absDelta: torch.Tensor):
+        """In-place update of U and absDelta; returns (change, m)."""
+        ch = ctypes.c_double(0.0)
+        m = ctypes.c_int64(0)
+        _call("bdg_scf_step", ctypes.byref(self.lat), _dev(self.Vext), _dev(self.theta), self.mu,
+              ctypes.byref(self.p), _dev(U), _dev(absDelta), _dev(self.density), _dev(self.nu_abs),
+              ctypes.byref(ch), ctypes.byref(m), _dev(self.work), self.work.numel(),
+              _stream(U.device))
+        return ch.value, int(m.value)

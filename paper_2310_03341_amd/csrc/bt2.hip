@@ -21,10 +21,12 @@
 namespace bdg {
 namespace {
 
-constexpr int NBK = 16;     // sweeps per block
+constexpr int NBK = 32;     // sweeps per block
 constexpr int BMAX = 64;
 constexpr int HMAX = BMAX + NBK - 1;
-constexpr int SLAB = 16;    // columns of Z per workgroup
+constexpr int HT = 6;       // 16-row tiles covering HMAX (<= 96 rows)
+constexpr int VLD = 97;     // LDS leading dimension of V (padding avoids bank conflicts)
+constexpr int SLAB = 64;    // columns of Z per workgroup (16 per wave)
 
 // Phase vector: ph_0 = 1, ph_{i+1} = ph_i e_i / |e_i| (renormalised); |e| out.
 __global__ void phases_kernel(int64_t n, const double *__restrict__ e_cplx, double *__restrict__ ph,
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const doub
                                                     const double *__restrict__ tau2,
                                                     const int64_t *__restrict__ voff, int64_t nsb,
                                                     int64_t tmax, double *__restrict__ TF) {
-    __shared__ double2 Vs[HMAX * NBK];
+    __shared__ double2 Vs[VLD * NBK];
     __shared__ double2 Gs[NBK * NBK];
     __shared__ double2 Ts[NBK * NBK];
     __shared__ double ts[NBK];
@@ -76,32 +78,34 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const doub
     const int tid = threadIdx.x;
     const int64_t nsw = n - 2;
     // parallelogram: column j holds reflector (s0 + j, t) at rows j .. j + b - 1
-    for (int e = tid; e < HMAX * NBK; e += blockDim.x) {
-        const int r = e % HMAX, j = e / HMAX;
-        const int64_t s = s0 + j;
+    for (int e = tid; e < HT * 16 * NBK; e += blockDim.x) {
+        const int r = e % (HT * 16), j = e / (HT * 16);
+        const int64_t sw = s0 + j;
         double2 v = make_double2(0.0, 0.0);
-        if (s < nsw && t < (n - 2 - s) / b + 1) {
+        if (sw < nsw && t < (n - 2 - sw) / b + 1) {
             const int o = r - j;
-            if (o >= 0 && o < b) v = *(const double2 *)(V2 + 2 * ((voff[s] + t) * b + o));
+            if (o >= 0 && o < b) v = *(const double2 *)(V2 + 2 * ((voff[sw] + t) * b + o));
         }
-        Vs[r + j * HMAX] = v;
+        Vs[r + j * VLD] = v;
     }
     if (tid < NBK) {
-        const int64_t s = s0 + tid;
-        ts[tid] = (s < nsw && t < (n - 2 - s) / b + 1) ? tau2[voff[s] + t] : 0.0;
+        const int64_t sw = s0 + tid;
+        ts[tid] = (sw < nsw && t < (n - 2 - sw) / b + 1) ? tau2[voff[sw] + t] : 0.0;
     }
     __syncthreads();
-    // G = V^H V
-    {
-        const int i = tid % NBK, j = tid / NBK;  // 256 = 16 x 16
+    // G = V^H V (only the strictly upper part is used)
+    for (int e = tid; e < NBK * NBK; e += blockDim.x) {
+        const int i = e % NBK, j = e / NBK;
         double gr = 0.0, gi = 0.0;
-        for (int r = 0; r < HMAX; ++r) {
-            const double2 a = Vs[r + i * HMAX], c = Vs[r + j * HMAX];
-            gr += a.x * c.x + a.y * c.y;
-            gi += a.x * c.y - a.y * c.x;
+        if (i < j) {
+            for (int r = j; r < i + b && r < HT * 16; ++r) {
+                const double2 a = Vs[r + i * VLD], c = Vs[r + j * VLD];
+                gr += a.x * c.x + a.y * c.y;
+                gi += a.x * c.y - a.y * c.x;
+            }
         }
-        Gs[i + j * NBK] = make_double2(gr, gi);
-        Ts[i + j * NBK] = make_double2(0.0, 0.0);
+        Gs[e] = make_double2(gr, gi);
+        Ts[e] = make_double2(0.0, 0.0);
     }
     __syncthreads();
     for (int j = 0; j < NBK; ++j) {
@@ -118,91 +122,149 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const doub
         if (tid == j) Ts[j + j * NBK] = make_double2(tj, 0.0);
         __syncthreads();
     }
-    {
-        const int i = tid % NBK, j = tid / NBK;
-        *(double2 *)(TF + 2 * (blk * NBK * NBK + i + j * NBK)) = Ts[i + j * NBK];
-    }
+    for (int e = tid; e < NBK * NBK; e += blockDim.x)
+        *(double2 *)(TF + 2 * (blk * NBK * NBK + e)) = Ts[e];
 }
 
-// Apply every block to a slab of SLAB columns.  256 threads = 16 columns x 16 lanes.
-__global__ __launch_bounds__(256) void bt2_apply(int64_t n, int b, int64_t m,
+// Apply every block to a slab of SLAB columns on the FP64 matrix cores.
+// Each wave keeps its 96 x 16 window of Z in MFMA accumulator layout
+// (element r of lane l = row (l/16) + 4 r of a 16-row tile, column l%16).
+// The same registers serve as the B operand of the next product with the k
+// index permuted accordingly (a sum over k does not depend on its order).
+//   W  = V^H Z   (32 x 16)     W2 = T W     Z -= V W2
+// Tiles of the parallelogram V that are zero by construction are skipped.
+__global__ __launch_bounds__(256, 2) void bt2_apply(int64_t n, int b, int64_t m,
                                                  const double *__restrict__ V2,
                                                  const int64_t *__restrict__ voff, int64_t nsb,
                                                  int64_t tmax, const double *__restrict__ TF,
                                                  double *__restrict__ Z, int64_t ldz) {
-    __shared__ double2 Vs[HMAX * NBK];
+    __shared__ double2 Vs[VLD * NBK];
     __shared__ double2 Ts[NBK * NBK];
-    __shared__ double2 Zs[HMAX * SLAB];
-    __shared__ double2 Ws[NBK * SLAB];
-    __shared__ double2 W2[NBK * SLAB];
+    __shared__ int64_t vb[NBK];  // reflector base of each sweep of the block
+    __shared__ int64_t vt[NBK];  // task count of each sweep (0 beyond the last sweep)
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
     const int64_t j0 = (int64_t)blockIdx.x * SLAB;
-    const int ncol = (int)min((int64_t)SLAB, m - j0);
+    const int64_t col = j0 + wave * 16 + li;  // this lane's column of Z
+    const bool colok = col < m;
     const int64_t nsw = n - 2;
     for (int64_t S = nsb - 1; S >= 0; --S) {
         const int64_t s0 = S * NBK;
-        const int64_t T0 = (n - 2 - s0) / b + 1;  // tasks of the first sweep (the most)
+        const int64_t T0 = (n - 2 - s0) / b + 1;
+        __syncthreads();
+        if (tid < NBK) {
+            const int64_t sw = s0 + tid;
+            vb[tid] = sw < nsw ? voff[sw] : 0;
+            vt[tid] = sw < nsw ? (n - 2 - sw) / b + 1 : 0;
+        }
         for (int64_t t = 0; t < T0; ++t) {
             const int64_t rs = s0 + 1 + t * b;
             if (rs >= n) break;
-            const int h = (int)min((int64_t)HMAX, n - rs);
+            const int h = (int)min((int64_t)(HT * 16), n - rs);
             __syncthreads();
-            for (int e = tid; e < HMAX * NBK; e += blockDim.x) {
-                const int r = e % HMAX, j = e / HMAX;
-                const int64_t s = s0 + j;
-                double2 v = make_double2(0.0, 0.0);
-                if (s < nsw && t < (n - 2 - s) / b + 1 && r < h) {
+            {
+                // parallelogram: 96 x 32 entries, 12 per thread, loads issued first
+                double2 rv[HT * 16 * NBK / 256];
+#pragma unroll
+                for (int i = 0; i < HT * 16 * NBK / 256; ++i) {
+                    const int e = tid + 256 * i;
+                    const int r = e % (HT * 16), j = e / (HT * 16);
                     const int o = r - j;
-                    if (o >= 0 && o < b) v = *(const double2 *)(V2 + 2 * ((voff[s] + t) * b + o));
+                    rv[i] = make_double2(0.0, 0.0);
+                    if (r < h && o >= 0 && o < b && t < vt[j])
+                        rv[i] = *(const double2 *)(V2 + 2 * ((vb[j] + t) * b + o));
                 }
-                Vs[r + j * HMAX] = v;
+                double2 rt4[NBK * NBK / 256];
+#pragma unroll
+                for (int i = 0; i < NBK * NBK / 256; ++i)
+                    rt4[i] = *(const double2 *)(TF + 2 * ((S * tmax + t) * NBK * NBK + tid + 256 * i));
+#pragma unroll
+                for (int i = 0; i < HT * 16 * NBK / 256; ++i) {
+                    const int e = tid + 256 * i;
+                    const int r = e % (HT * 16), j = e / (HT * 16);
+                    Vs[r + j * VLD] = rv[i];
+                }
+#pragma unroll
+                for (int i = 0; i < NBK * NBK / 256; ++i) Ts[tid + 256 * i] = rt4[i];
             }
-            {
-                const int i = tid % NBK, j = tid / NBK;
-                Ts[i + j * NBK] = *(const double2 *)(TF + 2 * ((S * tmax + t) * NBK * NBK + i + j * NBK));
-            }
-            for (int e = tid; e < HMAX * SLAB; e += blockDim.x) {
-                const int r = e % HMAX, c = e / HMAX;
-                double2 z = make_double2(0.0, 0.0);
-                if (r < h && c < ncol) z = *(const double2 *)(Z + 2 * ((rs + r) + (j0 + c) * ldz));
-                Zs[r + c * HMAX] = z;
+            // Z window in accumulator layout
+            d4 zr[HT], zi[HT];
+#pragma unroll
+            for (int rt = 0; rt < HT; ++rt) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = rt * 16 + lk + 4 * q;
+                    double2 z = make_double2(0.0, 0.0);
+                    if (row < h && colok) z = *(const double2 *)(Z + 2 * ((rs + row) + col * ldz));
+                    zr[rt][q] = z.x;
+                    zi[rt][q] = z.y;
+                }
             }
             __syncthreads();
-            // W = V^H Z  (NBK x SLAB)
-            {
-                const int i = tid % NBK, c = tid / NBK;
-                double wr = 0.0, wi = 0.0;
-                for (int r = 0; r < h; ++r) {
-                    const double2 v = Vs[r + i * HMAX], z = Zs[r + c * HMAX];
-                    wr += v.x * z.x + v.y * z.y;
-                    wi += v.x * z.y - v.y * z.x;
+            // W = V^H Z
+            d4 wr[2], wi[2];
+#pragma unroll
+            for (int it = 0; it < 2; ++it) {
+                wr[it] = d4{0, 0, 0, 0};
+                wi[it] = d4{0, 0, 0, 0};
+#pragma unroll
+                for (int kt = 0; kt < HT; ++kt) {
+                    if (16 * kt + 15 < 16 * it || 16 * kt > 16 * it + 14 + b) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double2 v = Vs[(16 * kt + lk + 4 * q) + (16 * it + li) * VLD];
+                        wr[it] = mfma16(v.x, zr[kt][q], wr[it]);
+                        wi[it] = mfma16(v.x, zi[kt][q], wi[it]);
+                        wr[it] = mfma16(v.y, zi[kt][q], wr[it]);
+                        wi[it] = mfma16(-v.y, zr[kt][q], wi[it]);
+                    }
                 }
-                Ws[i + c * NBK] = make_double2(wr, wi);
             }
-            __syncthreads();
-            // W2 = T W
-            {
-                const int i = tid % NBK, c = tid / NBK;
-                double wr = 0.0, wi = 0.0;
-                for (int l = i; l < NBK; ++l) {
-                    const double2 a = Ts[i + l * NBK], w = Ws[l + c * NBK];
-                    wr += a.x * w.x - a.y * w.y;
-                    wi += a.x * w.y + a.y * w.x;
+            // W2 = T W   (T upper triangular), stored negated
+            d4 ur[2], ui[2];
+#pragma unroll
+            for (int it = 0; it < 2; ++it) {
+                ur[it] = d4{0, 0, 0, 0};
+                ui[it] = d4{0, 0, 0, 0};
+#pragma unroll
+                for (int kt = it; kt < 2; ++kt) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double2 tv = Ts[(16 * it + li) + (16 * kt + lk + 4 * q) * NBK];
+                        ur[it] = mfma16(tv.x, wr[kt][q], ur[it]);
+                        ui[it] = mfma16(tv.x, wi[kt][q], ui[it]);
+                        ur[it] = mfma16(-tv.y, wi[kt][q], ur[it]);
+                        ui[it] = mfma16(tv.y, wr[kt][q], ui[it]);
+                    }
                 }
-                W2[i + c * NBK] = make_double2(wr, wi);
+                ur[it] = -ur[it];
+                ui[it] = -ui[it];
             }
-            __syncthreads();
-            // Z -= V W2
-            for (int e = tid; e < h * SLAB; e += blockDim.x) {
-                const int r = e % h, c = e / h;
-                if (c >= ncol) continue;
-                double zr = Zs[r + c * HMAX].x, zi = Zs[r + c * HMAX].y;
-                for (int l = 0; l < NBK; ++l) {
-                    const double2 v = Vs[r + l * HMAX], w = W2[l + c * NBK];
-                    zr -= v.x * w.x - v.y * w.y;
-                    zi -= v.x * w.y + v.y * w.x;
+            // Z += V (-W2)
+#pragma unroll
+            for (int rt = 0; rt < HT; ++rt) {
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt) {
+                    if (16 * rt + 15 < 16 * kt || 16 * rt > 16 * kt + 14 + b) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double2 v = Vs[(16 * rt + li) + (16 * kt + lk + 4 * q) * VLD];
+                        zr[rt] = mfma16(v.x, ur[kt][q], zr[rt]);
+                        zi[rt] = mfma16(v.x, ui[kt][q], zi[rt]);
+                        zr[rt] = mfma16(-v.y, ui[kt][q], zr[rt]);
+                        zi[rt] = mfma16(v.y, ur[kt][q], zi[rt]);
+                    }
                 }
-                *(double2 *)(Z + 2 * ((rs + r) + (j0 + c) * ldz)) = make_double2(zr, zi);
+            }
+#pragma unroll
+            for (int rt = 0; rt < HT; ++rt) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = rt * 16 + lk + 4 * q;
+                    if (row < h && colok)
+                        *(double2 *)(Z + 2 * ((rs + row) + col * ldz)) = make_double2(zr[rt][q], zi[rt][q]);
+                }
             }
         }
     }

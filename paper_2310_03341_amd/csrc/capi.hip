@@ -221,3 +221,52 @@ int bdg_stage_bt1(int64_t n, int64_t m, const double *A, int64_t lda, int band, 
 }
 
 }  // extern "C"
+
+extern "C" {
+
+static int lattice_ok(const bdg_lattice *lat, const char *fn) {
+    if (!lat || lat->ndim < 1 || lat->ndim > 3) {
+        set_error("%s: lattice must have ndim in 1..3", fn);
+        return -1;
+    }
+    for (int d = 0; d < lat->ndim; ++d) {
+        const int N = lat->dims[d];
+        if (N < 2 || (N & 1) || N > 64) {
+            set_error("%s: dims[%d]=%d must be even and in [2, 64]", fn, d, N);
+            return -1;
+        }
+    }
+    return 0;
+}
+
+int bdg_scf_workspace(const bdg_lattice *lat, size_t *bytes) {
+    BDG_TRY(lattice_ok(lat, "bdg_scf_workspace"));
+    if (!bytes) return -2;
+    *bytes = bdg::scf_workspace(lat);
+    return 0;
+}
+
+int bdg_scf_step(const bdg_lattice *lat, const double *Vext, const double *theta, double mu,
+                 const bdg_scf_params *params, double *U, double *absDelta, double *density,
+                 double *nu_abs, double *change, int64_t *m, void *work, size_t work_bytes,
+                 bdg_stream_t stream) {
+    BDG_TRY(lattice_ok(lat, "bdg_scf_step"));
+    if (!Vext) return -2;
+    if (!theta) return -3;
+    if (!params || !(params->Ec > 0.0) || !(params->alpha > 0.0 && params->alpha <= 1.0)) {
+        set_error("bdg_scf_step: params must have Ec > 0 and 0 < alpha <= 1");
+        return -5;
+    }
+    if (!U) return -6;
+    if (!absDelta) return -7;
+    if (!change) return -10;
+    if (!m) return -11;
+    if (!work || work_bytes < bdg::scf_workspace(lat)) {
+        set_error("bdg_scf_step: workspace too small");
+        return BDG_ERR_WORKSPACE;
+    }
+    return bdg::scf_step(lat, Vext, theta, mu, params, U, absDelta, density, nu_abs, change, m, work,
+                         (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -9,10 +9,11 @@
 //   t >= 1: A[R, C] <- A[R, C] H_{t-1} (creates the bulge); reflector H_t zeroes
 //           A[r0+1:, r0-b] (first bulge column); A[R, C] <- H_t^H A[R, C];
 //           two-sided on A[R, R].
-// Consecutive sweeps lag by three tasks: task t of sweep s+1 only needs tasks
-// <= t+2 of sweep s, and task t+3 of sweep s touches indices disjoint from
-// task t of sweep s+1.  One launch executes every (s, t) with t = g - 3 s, so
-// the kernel boundary orders dependent tasks and needs no in-kernel waits.
+// Consecutive sweeps lag by two tasks: task t of sweep s+1 reads and writes
+// entries with row and column <= i* = s+1+(t+1)b, which task t+1 of sweep s
+// finished, while task t+2 of sweep s only touches rows >= i* + b.  One launch
+// executes every (s, t) with t = g - 2 s, so the kernel boundary orders the
+// dependent tasks and no in-kernel waits are needed.
 //
 // The band lives in lower band storage AB[(i - j) + j ldab] (ldab >= 2b + 2
 // holds the bulge).  Reflector (s, t) is stored with v_0 = 1 (length b, zero
@@ -25,6 +26,7 @@ namespace {
 
 constexpr int BMAX = 64;
 constexpr int LDS = BMAX + 1;
+constexpr int LAG = 2;  // task t of sweep s runs in step t + LAG s
 
 __device__ inline double2 ld2(const double *p) { return *(const double2 *)p; }
 __device__ inline void st2(double *p, double2 v) { *(double2 *)p = v; }
@@ -36,69 +38,90 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, double *__re
                                                   int64_t s_lo) {
     __shared__ double2 Bs[BMAX * LDS];
     __shared__ double2 Ds[BMAX * LDS];
-    __shared__ double2 vp[BMAX], vn[BMAX], yv[BMAX], wv[BMAX];
-    __shared__ double red[4][2];
+    __shared__ double2 vp[BMAX], vn[BMAX], yv[BMAX], pv[BMAX], wb[BMAX];
+    __shared__ double red[4][4];
     __shared__ double sc[8];
     const int64_t s = s_lo + blockIdx.x;
-    const int64_t t = g - 3 * s;
+    const int64_t t = g - LAG * s;
     if (s > n - 3 || t < 0) return;
     const int64_t Ts = (n - 2 - s) / b + 1;
     if (t >= Ts) return;
     const int tid = threadIdx.x;
+    const int w = tid >> 6, l = tid & 63;
     const int64_t r0 = s + 1 + t * b;
     const int Lr = (int)min((int64_t)b, n - r0);
     const int64_t ridx = voff[s] + t;
+    const int64_t c0 = r0 - b;
+    double tp = 0.0;
 
-    // ---- load x (t == 0) or B = A[R, C] and apply previous reflector from the right
-    if (t == 0) {
-        for (int r = tid; r < Lr; r += blockDim.x) vn[r] = ld2(AB + 2 * ((1 + r) + s * ldab));
-    } else {
-        const int64_t c0 = r0 - b;
-        for (int e = tid; e < Lr * b; e += blockDim.x) {
-            const int r = e % Lr, c = e / Lr;
-            Bs[r + c * LDS] = ld2(AB + 2 * ((b + r - c) + (c0 + c) * ldab));
-        }
-        for (int c = tid; c < b; c += blockDim.x) vp[c] = ld2(V2 + 2 * ((ridx - 1) * b + c));
-        const double tp = tau2[ridx - 1];
-        __syncthreads();
-        if (tp != 0.0) {
-            // y = B v (row sums): 4 threads per row
-            for (int base = 0; base < Lr * 4; base += blockDim.x) {
-                const int e = base + tid;
-                const int r = e >> 2, q = e & 3;
-                double yr = 0.0, yi = 0.0;
-                if (r < Lr) {
-                    for (int c = q; c < b; c += 4) {
-                        const double2 a = Bs[r + c * LDS], v = vp[c];
-                        yr += a.x * v.x - a.y * v.y;
-                        yi += a.x * v.y + a.y * v.x;
-                    }
+    // ---- phase 0: load B = A[R, C] (t > 0), D = A[R, R] (full Hermitian), previous v.
+    // Fixed trip counts (64 x 64 tiles, 16 elements per thread) so that all
+    // global loads are issued before their LDS stores.
+    {
+        double2 rb[16], rd[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e & 63, c = e >> 6;
+            rb[i] = make_double2(0.0, 0.0);
+            if (t > 0 && r < Lr && c < b) rb[i] = ld2(AB + 2 * ((b + r - c) + (c0 + c) * ldab));
+            rd[i] = make_double2(0.0, 0.0);
+            if (r < Lr && c < Lr) {
+                if (r >= c) rd[i] = ld2(AB + 2 * ((r - c) + (r0 + c) * ldab));
+                else {
+                    rd[i] = ld2(AB + 2 * ((c - r) + (r0 + r) * ldab));
+                    rd[i].y = -rd[i].y;
                 }
-                yr += __shfl_xor(yr, 1, 64); yi += __shfl_xor(yi, 1, 64);
-                yr += __shfl_xor(yr, 2, 64); yi += __shfl_xor(yi, 2, 64);
-                if (r < Lr && q == 0) yv[r] = make_double2(tp * yr, tp * yi);
             }
-            __syncthreads();
-            // B -= (tau y) v^H
-            for (int e = tid; e < Lr * b; e += blockDim.x) {
-                const int r = e % Lr, c = e / Lr;
-                const double2 y = yv[r], v = vp[c];
-                double2 a = Bs[r + c * LDS];
-                a.x -= y.x * v.x + y.y * v.y;
-                a.y -= y.y * v.x - y.x * v.y;
-                Bs[r + c * LDS] = a;
-            }
-            __syncthreads();
         }
-        for (int r = tid; r < Lr; r += blockDim.x) vn[r] = Bs[r];
+        if (t > 0) {
+            if (tid < b) vp[tid] = ld2(V2 + 2 * ((ridx - 1) * b + tid));
+            tp = tau2[ridx - 1];
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e & 63, c = e >> 6;
+            Bs[r + c * LDS] = rb[i];
+            Ds[r + c * LDS] = rd[i];
+        }
     }
     __syncthreads();
 
-    // ---- reflector from x = vn[0..Lr)
+    // ---- phase 1: y = tp * B vp  (row sums, 4 threads per row)
+    if (t > 0) {
+        for (int base = 0; base < Lr * 4; base += blockDim.x) {
+            const int e = base + tid;
+            const int r = e >> 2, q = e & 3;
+            double yr = 0.0, yi = 0.0;
+            if (r < Lr && tp != 0.0) {
+                for (int c = q; c < b; c += 4) {
+                    const double2 a = Bs[r + c * LDS], v = vp[c];
+                    yr += a.x * v.x - a.y * v.y;
+                    yi += a.x * v.y + a.y * v.x;
+                }
+            }
+            yr += __shfl_xor(yr, 1, 64); yi += __shfl_xor(yi, 1, 64);
+            yr += __shfl_xor(yr, 2, 64); yi += __shfl_xor(yi, 2, 64);
+            if (r < Lr && q == 0) yv[r] = make_double2(tp * yr, tp * yi);
+        }
+        __syncthreads();
+    }
+
+    // ---- phase 2: x (first bulge column after the right update), reflector
     {
-        const int w = tid >> 6, l = tid & 63;
         double t2 = 0.0;
-        for (int r = 1 + tid; r < Lr; r += blockDim.x) t2 += vn[r].x * vn[r].x + vn[r].y * vn[r].y;
+        for (int r = tid; r < Lr; r += blockDim.x) {
+            double2 x;
+            if (t > 0) {
+                const double2 a = Bs[r], y = yv[r];
+                x = make_double2(a.x - y.x, a.y - y.y);  // vp_0 = 1
+            } else {
+                x = ld2(AB + 2 * ((1 + r) + s * ldab));
+            }
+            vn[r] = x;
+            if (r > 0) t2 += x.x * x.x + x.y * x.y;
+        }
         t2 = wave_sum(t2);
         if (l == 0) red[w][0] = t2;
         __syncthreads();
@@ -123,87 +146,45 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, double *__re
         __syncthreads();
     }
     const double tj = sc[2];
-    const double ur = sc[0], ui = sc[1];
     const double2 beta = make_double2(sc[3], sc[4]);
-    // v: v_0 = 1, v_r = x_r / u0 ; stored (zero padded to b)
-    __syncthreads();
-    for (int r = tid; r < b; r += blockDim.x) {
-        double2 v;
-        if (r == 0) v = make_double2(1.0, 0.0);
-        else if (r < Lr && tj != 0.0) {
-            const double2 x = vn[r];
-            v = make_double2(x.x * ur - x.y * ui, x.x * ui + x.y * ur);
-        } else v = make_double2(0.0, 0.0);
-        wv[r] = v;  // wv temporarily holds v
-        st2(V2 + 2 * (ridx * b + r), v);
+    {
+        const double ur = sc[0], ui = sc[1];
+        double2 vr0 = make_double2(0.0, 0.0);
+        if (tid < b) {
+            double2 v;
+            if (tid == 0) v = make_double2(1.0, 0.0);
+            else if (tid < Lr && tj != 0.0) {
+                const double2 x = vn[tid];
+                v = make_double2(x.x * ur - x.y * ui, x.x * ui + x.y * ur);
+            } else v = make_double2(0.0, 0.0);
+            vr0 = v;
+            st2(V2 + 2 * (ridx * b + tid), v);
+        }
+        if (tid == 0) tau2[ridx] = tj;
+        __syncthreads();
+        if (tid < b) vn[tid] = vr0;
+        __syncthreads();
     }
-    if (tid == 0) tau2[ridx] = tj;
-    __syncthreads();
-    for (int r = tid; r < b; r += blockDim.x) vn[r] = wv[r];
-    __syncthreads();
 
-    // ---- left application to B (t >= 1): column 0 -> beta e_0, others B -= tau v (v^H B)
-    if (t > 0) {
-        if (tj != 0.0) {
+    // ---- phase 3: wB = v^H B (column sums, original B), gamma = v^H y, p = tau D v
+    if (tj != 0.0) {
+        if (t > 0) {
             for (int base = 0; base < b * 4; base += blockDim.x) {
                 const int e = base + tid;
                 const int c = e >> 2, q = e & 3;
                 double sr = 0.0, si = 0.0;
-                if (c < b && c > 0) {
+                if (c < b) {
                     for (int r = q; r < Lr; r += 4) {
                         const double2 v = vn[r], a = Bs[r + c * LDS];
-                        sr += v.x * a.x + v.y * a.y;   // conj(v) a
+                        sr += v.x * a.x + v.y * a.y;
                         si += v.x * a.y - v.y * a.x;
                     }
                 }
                 sr += __shfl_xor(sr, 1, 64); si += __shfl_xor(si, 1, 64);
                 sr += __shfl_xor(sr, 2, 64); si += __shfl_xor(si, 2, 64);
-                if (c < b && q == 0) wv[c] = make_double2(tj * sr, tj * si);
+                if (c < b && q == 0) wb[c] = make_double2(sr, si);
             }
-            __syncthreads();
-            for (int e = tid; e < Lr * b; e += blockDim.x) {
-                const int r = e % Lr, c = e / Lr;
-                double2 a = Bs[r + c * LDS];
-                if (c == 0) {
-                    a = (r == 0) ? beta : make_double2(0.0, 0.0);
-                } else {
-                    const double2 v = vn[r], w = wv[c];
-                    a.x -= v.x * w.x - v.y * w.y;
-                    a.y -= v.x * w.y + v.y * w.x;
-                }
-                Bs[r + c * LDS] = a;
-            }
-            __syncthreads();
         }
-        // write B back
-        const int64_t c0 = r0 - b;
-        for (int e = tid; e < Lr * b; e += blockDim.x) {
-            const int r = e % Lr, c = e / Lr;
-            st2(AB + 2 * ((b + r - c) + (c0 + c) * ldab), Bs[r + c * LDS]);
-        }
-    } else {
-        // t == 0: column s -> beta on the sub-diagonal, zeros below
-        for (int r = tid; r < Lr; r += blockDim.x) {
-            const double2 a = (tj == 0.0) ? ld2(AB + 2 * ((1 + r) + s * ldab))
-                                          : (r == 0 ? beta : make_double2(0.0, 0.0));
-            st2(AB + 2 * ((1 + r) + s * ldab), a);
-        }
-    }
-
-    // ---- two-sided application to D = A[R, R]
-    if (tj != 0.0) {
-        for (int e = tid; e < Lr * Lr; e += blockDim.x) {
-            const int r = e % Lr, c = e / Lr;
-            double2 a;
-            if (r >= c) a = ld2(AB + 2 * ((r - c) + (r0 + c) * ldab));
-            else {
-                a = ld2(AB + 2 * ((c - r) + (r0 + r) * ldab));
-                a.y = -a.y;
-            }
-            Ds[r + c * LDS] = a;
-        }
-        __syncthreads();
-        // p = tau D v
         for (int base = 0; base < Lr * 4; base += blockDim.x) {
             const int e = base + tid;
             const int r = e >> 2, q = e & 3;
@@ -217,44 +198,83 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, double *__re
             }
             pr += __shfl_xor(pr, 1, 64); pi += __shfl_xor(pi, 1, 64);
             pr += __shfl_xor(pr, 2, 64); pi += __shfl_xor(pi, 2, 64);
-            if (r < Lr && q == 0) yv[r] = make_double2(tj * pr, tj * pi);
+            if (r < Lr && q == 0) pv[r] = make_double2(tj * pr, tj * pi);
         }
         __syncthreads();
-        // K = (tau/2) v^H p
-        {
-            const int w = tid >> 6, l = tid & 63;
-            double kr = 0.0, ki = 0.0;
-            for (int r = tid; r < Lr; r += blockDim.x) {
-                const double2 v = vn[r], p = yv[r];
-                kr += v.x * p.x + v.y * p.y;
-                ki += v.x * p.y - v.y * p.x;
+        // K = (tau/2) v^H p  and  gamma = v^H y
+        double kr = 0.0, ki = 0.0, gr = 0.0, gi = 0.0;
+        for (int r = tid; r < Lr; r += blockDim.x) {
+            const double2 v = vn[r], p = pv[r];
+            kr += v.x * p.x + v.y * p.y;
+            ki += v.x * p.y - v.y * p.x;
+            if (t > 0) {
+                const double2 y = yv[r];
+                gr += v.x * y.x + v.y * y.y;
+                gi += v.x * y.y - v.y * y.x;
             }
-            kr = wave_sum(kr);
-            ki = wave_sum(ki);
-            if (l == 0) { red[w][0] = kr; red[w][1] = ki; }
-            __syncthreads();
-            if (tid == 0) {
-                sc[5] = 0.5 * tj * (red[0][0] + red[1][0] + red[2][0] + red[3][0]);
-                sc[6] = 0.5 * tj * (red[0][1] + red[1][1] + red[2][1] + red[3][1]);
-            }
-            __syncthreads();
         }
-        // w = p - K v
-        {
-            const double Kr = sc[5], Ki = sc[6];
-            for (int r = tid; r < Lr; r += blockDim.x) {
-                const double2 v = vn[r], p = yv[r];
-                wv[r] = make_double2(p.x - (Kr * v.x - Ki * v.y), p.y - (Kr * v.y + Ki * v.x));
-            }
+        kr = wave_sum(kr); ki = wave_sum(ki); gr = wave_sum(gr); gi = wave_sum(gi);
+        if (l == 0) { red[w][0] = kr; red[w][1] = ki; red[w][2] = gr; red[w][3] = gi; }
+        __syncthreads();
+        if (tid == 0) {
+            sc[5] = 0.5 * tj * (red[0][0] + red[1][0] + red[2][0] + red[3][0]);
+            sc[6] = 0.5 * tj * (red[0][1] + red[1][1] + red[2][1] + red[3][1]);
+            sc[7] = 0.0;
+            red[0][2] = red[0][2] + red[1][2] + red[2][2] + red[3][2];
+            red[0][3] = red[0][3] + red[1][3] + red[2][3] + red[3][3];
         }
         __syncthreads();
-        // D -= v w^H + w v^H  (lower part written back)
-        for (int e = tid; e < Lr * Lr; e += blockDim.x) {
-            const int r = e % Lr, c = e / Lr;
-            if (r < c) continue;
-            const double2 vr = vn[r], vc = vn[c], wr = wv[r], wc = wv[c];
+    }
+
+    // ---- phase 4: write B and D
+    if (t > 0) {
+        const double gmr = red[0][2], gmi = red[0][3];
+#pragma unroll 4
+        for (int i = 0; i < 16; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e & 63, c = e >> 6;
+            if (r >= Lr || c >= b) continue;
+            double2 a;
+            if (c == 0) {
+                a = (tj == 0.0) ? make_double2(vn[0].x * 0 + Bs[r].x - yv[r].x, Bs[r].y - yv[r].y)
+                                : (r == 0 ? beta : make_double2(0.0, 0.0));
+            } else {
+                a = Bs[r + c * LDS];
+                const double2 vpc = vp[c], y = yv[r];
+                // right update: - y conj(vp_c)
+                a.x -= y.x * vpc.x + y.y * vpc.y;
+                a.y -= y.y * vpc.x - y.x * vpc.y;
+                if (tj != 0.0) {
+                    // left update: - tau v_r (wB_c - gamma conj(vp_c)),  gamma = v^H y (y holds tp)
+                    const double2 wbc = wb[c];
+                    const double qr = wbc.x - (gmr * vpc.x + gmi * vpc.y);
+                    const double qi = wbc.y - (gmi * vpc.x - gmr * vpc.y);
+                    const double2 v = vn[r];
+                    a.x -= tj * (v.x * qr - v.y * qi);
+                    a.y -= tj * (v.x * qi + v.y * qr);
+                }
+            }
+            st2(AB + 2 * ((b + r - c) + (c0 + c) * ldab), a);
+        }
+    } else {
+        for (int r = tid; r < Lr; r += blockDim.x) {
+            const double2 a = (tj == 0.0) ? vn[r] : (r == 0 ? beta : make_double2(0.0, 0.0));
+            // when tj == 0 the column is unchanged (vn was overwritten by v; reload)
+            if (tj == 0.0) continue;
+            st2(AB + 2 * ((1 + r) + s * ldab), a);
+        }
+    }
+    if (tj != 0.0) {
+        const double Kr = sc[5], Ki = sc[6];
+#pragma unroll 4
+        for (int i = 0; i < 16; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e & 63, c = e >> 6;
+            if (r >= Lr || c >= Lr || r < c) continue;
+            const double2 vr = vn[r], vc = vn[c], pr = pv[r], pc = pv[c];
+            const double2 wr = make_double2(pr.x - (Kr * vr.x - Ki * vr.y), pr.y - (Kr * vr.y + Ki * vr.x));
+            const double2 wc = make_double2(pc.x - (Kr * vc.x - Ki * vc.y), pc.y - (Kr * vc.y + Ki * vc.x));
             double2 a = Ds[r + c * LDS];
-            // v_r conj(w_c) + w_r conj(v_c)
             a.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
             a.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
             if (r == c) a.y = 0.0;
@@ -300,13 +320,13 @@ int hb2st(int64_t n, int b, double *AB, int64_t ldab, double *V2, double *tau2,
     if (n >= 3) {
         const int64_t nsw = n - 2;  // sweeps 0 .. n-3
         const int64_t T0 = (n - 2) / b + 1;
-        const int64_t gmax = 3 * (nsw - 1) + T0;  // last step index + 1 upper bound
+        const int64_t gmax = LAG * (nsw - 1) + T0;  // last step index + 1 upper bound
         int64_t s_lo = 0;
         for (int64_t g = 0; g < gmax; ++g) {
-            // smallest sweep still active at step g: g - 3 s < T_s
-            while (s_lo < nsw && g - 3 * s_lo >= (n - 2 - s_lo) / b + 1) ++s_lo;
+            // smallest sweep still active at step g: g - LAG s < T_s
+            while (s_lo < nsw && g - LAG * s_lo >= (n - 2 - s_lo) / b + 1) ++s_lo;
             if (s_lo >= nsw) break;
-            int64_t s_hi = g / 3;
+            int64_t s_hi = g / LAG;
             if (s_hi > nsw - 1) s_hi = nsw - 1;
             if (s_hi < s_lo) continue;
             hipLaunchKernelGGL(hb2st_step, dim3((unsigned)(s_hi - s_lo + 1)), dim3(256), 0, s, n, b,

@@ -129,11 +129,23 @@ __global__ __launch_bounds__(256) void panel_step(double *__restrict__ P, int64_
                     pj[0] = vr;
                     pj[1] = vi;
                 }
-                for (int c = j + 1; c < nb; ++c) {
-                    double *pc = P + 2 * (r + (int64_t)c * ld);
-                    const double wr = wc[2 * c], wi = wc[2 * c + 1];
-                    pc[0] -= vr * wr - vi * wi;
-                    pc[1] -= vr * wi + vi * wr;
+                // columns in chunks of 16: all loads of a chunk are issued first
+                for (int c0 = j + 1; c0 < nb; c0 += 16) {
+                    double2 pv[16];
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int c = c0 + q;
+                        pv[q] = (c < nb) ? *(const double2 *)(P + 2 * (r + (int64_t)c * ld))
+                                         : make_double2(0.0, 0.0);
+                    }
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        const int c = c0 + q;
+                        if (c >= nb) break;
+                        const double wr = wc[2 * c], wi = wc[2 * c + 1];
+                        *(double2 *)(P + 2 * (r + (int64_t)c * ld)) =
+                            make_double2(pv[q].x - (vr * wr - vi * wi), pv[q].y - (vr * wi + vi * wr));
+                    }
                 }
             }
         } else if (have && r == j) {
@@ -157,18 +169,24 @@ __global__ __launch_bounds__(256) void panel_step(double *__restrict__ P, int64_
         double t2 = (in && r > jn) ? xr * xr + xi * xi : 0.0;
         t2 = wave_sum(t2);
         if (l == 0) { red[w][2 * nb] = t2; red[w][2 * nb + 1] = 0.0; }
-        for (int c = jn + 1; c < nb; ++c) {
-            double pr = 0.0, pi = 0.0;
-            if (in) {
-                const double *pc = P + 2 * (r + (int64_t)c * ld);
-                pr = pc[0];
-                pi = pc[1];
+        for (int c0 = jn + 1; c0 < nb; c0 += 16) {
+            double2 pv[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int c = c0 + q;
+                pv[q] = (in && c < nb) ? *(const double2 *)(P + 2 * (r + (int64_t)c * ld))
+                                       : make_double2(0.0, 0.0);
             }
-            // conj(x) * p
-            double sr = xr * pr + xi * pi, si = xr * pi - xi * pr;
-            sr = wave_sum(sr);
-            si = wave_sum(si);
-            if (l == 0) { red[w][2 * c] = sr; red[w][2 * c + 1] = si; }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int c = c0 + q;
+                if (c >= nb) break;
+                // conj(x) * p
+                double sr = xr * pv[q].x + xi * pv[q].y, si = xr * pv[q].y - xi * pv[q].x;
+                sr = wave_sum(sr);
+                si = wave_sum(si);
+                if (l == 0) { red[w][2 * c] = sr; red[w][2 * c + 1] = si; }
+            }
         }
         __syncthreads();
         for (int c = t; c <= nb; c += blockDim.x) {
@@ -250,16 +268,22 @@ __global__ void band_copy_tail(const double *__restrict__ A, int64_t lda, int64_
 __global__ void tfactor(int nb, const double *__restrict__ G, const double *__restrict__ tau,
                         double *__restrict__ T) {
     __shared__ double Ts[2 * MAXB * MAXB];
+    __shared__ double Gs[2 * MAXB * MAXB];
+    __shared__ double taus[MAXB];
     const int t = threadIdx.x;
-    for (int e = t; e < nb * nb; e += blockDim.x) { Ts[2 * e] = 0.0; Ts[2 * e + 1] = 0.0; }
+    for (int e = t; e < nb * nb; e += blockDim.x) {
+        Ts[2 * e] = 0.0; Ts[2 * e + 1] = 0.0;
+        Gs[2 * e] = G[2 * e]; Gs[2 * e + 1] = G[2 * e + 1];
+    }
+    for (int e = t; e < nb; e += blockDim.x) taus[e] = tau[e];
     __syncthreads();
     for (int j = 0; j < nb; ++j) {
-        const double tj = tau[j];
+        const double tj = taus[j];
         if (t < j) {
             double sr = 0.0, si = 0.0;
             for (int l = t; l < j; ++l) {
                 const double ar = Ts[2 * (t + l * nb)], ai = Ts[2 * (t + l * nb) + 1];
-                const double gr = G[2 * (l + j * nb)], gi = G[2 * (l + j * nb) + 1];
+                const double gr = Gs[2 * (l + j * nb)], gi = Gs[2 * (l + j * nb) + 1];
                 sr += ar * gr - ai * gi;
                 si += ar * gi + ai * gr;
             }

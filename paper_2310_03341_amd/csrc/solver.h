@@ -21,3 +21,12 @@ int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
          size_t work_bytes, bdg_err_report *report, hipStream_t s);
 
 }  // namespace bdg
+
+namespace bdg {
+
+size_t scf_workspace(const bdg_lattice *lat);
+int scf_step(const bdg_lattice *lat, const double *Vext, const double *theta, double mu,
+             const bdg_scf_params *p, double *U, double *absDelta, double *density, double *nu_abs,
+             double *change, int64_t *m_out, void *work, hipStream_t s);
+
+}  // namespace bdg

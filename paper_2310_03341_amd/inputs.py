@@ -215,3 +215,23 @@ def random_hermitian(n: int, seed: int) -> np.ndarray:
 def random_tridiagonal(n: int, seed: int):
     rng = _rng(seed)
     return rng.standard_normal(n), rng.standard_normal(max(n - 1, 0))
+
+
+# ---- SCF functional constants (a synthetic SLDA-like functional) -----------------
+@dataclasses.dataclass(frozen=True)
+class ScfParams:
+    """Constants of the self-consistency update (plain numbers, no arithmetic).
+
+    U = Vext + B * eps_F(n) (eps_F = pi n in 2D, (3 pi^2 n)^(2/3) / 2 in 3D),
+    |Delta| = g |nu| with the phase held fixed, linear mixing alpha, window
+    0 < E < Ec, convergence when max|dU|, max|d|Delta|| <= tol.  B and g are
+    test constants, not the paper's (its A, B, C are not printed); g makes the
+    uniform 2D gas at mu = 1, U = 0 carry Delta = 0.3 on a 64x64 lattice
+    (value written by tests/golden/make_scf_constant.py from the oracle).
+    """
+    B: float = -0.3
+    g: float = 2.356643412040275
+    alpha: float = 0.3
+    Ec: float = 4.934802200544679   # pi^2 / 2
+    tol: float = 1e-6
+    max_iter: int = 200
