@@ -163,6 +163,37 @@ int bdg_scf_step(const bdg_lattice *lat, const double *Vext, const double *theta
                  bdg_stream_t stream);
 
 /*
+ * Start-field network of the learned SCF start (an extension of the method:
+ * the paper starts its iterations from coarser lattices).  Four periodic 3x3
+ * convolution layers, ReLU between them, FP32 master weights, BF16
+ * activations, BF16 matrix cores with FP32 accumulation:
+ *   input  (Vext - mu, cos theta, sin theta)  ->  output (U - Vext, |Delta|).
+ * Parameters are one flat FP32 vector: W1 [C][3][3][3], b1 [C], W2 [C][C][3][3],
+ * b2, W3 [C][C][3][3], b3, W4 [2][C][3][3], b4 (count from bdg_net_nparams).
+ * Field arrays are [batch][ny*nx] (site index x + nx y); y and target are
+ * [batch][2][ny*nx] FP32.  All pointers are device pointers.
+ */
+typedef struct {
+    int32_t channels; /* hidden channels C (<= 64) */
+    int32_t ny, nx;   /* lattice                  */
+    int32_t batch;    /* samples per call         */
+} bdg_net_shape;
+
+int64_t bdg_net_nparams(const bdg_net_shape *shape);
+int bdg_net_workspace(const bdg_net_shape *shape, size_t *bytes);
+/* y = net(Vext, theta; params) */
+int bdg_net_forward(const bdg_net_shape *shape, const float *params, const double *Vext,
+                    const double *theta, double mu, float *y, void *work, size_t work_bytes,
+                    bdg_stream_t stream);
+/* grads = d loss / d params, loss (device scalar) = mean((y - target)^2) */
+int bdg_net_backward(const bdg_net_shape *shape, const float *params, const double *Vext,
+                     const double *theta, double mu, const float *target, float *grads,
+                     float *loss, void *work, size_t work_bytes, bdg_stream_t stream);
+/* Adam (Kingma & Ba) on the FP32 master weights; t is the 1-based step count. */
+int bdg_net_adam_step(int64_t nparams, float *params, const float *grads, float *m, float *v,
+                      int32_t t, float lr, bdg_stream_t stream);
+
+/*
  * bdg_check -- FP64 accuracy of m eigenpairs (W, Z) of the Hermitian H.
  *   H [ldh x n] complex128 (full storage, both triangles read).
  *   max_resid   = max_j ||H z_j - w_j z_j||_2 / max_j |w_j| (host output)

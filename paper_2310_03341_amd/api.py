@@ -339,3 +339,61 @@ class ScfStepper:
               ctypes.byref(ch), ctypes.byref(m), _dev(self.work), self.work.numel(),
               _stream(U.device))
         return ch.value, int(m.value)
+
+
+# ---------------------------------------------------------------- start-field network
+class NetShape(ctypes.Structure):
+    _fields_ = [("channels", ctypes.c_int32), ("ny", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("batch", ctypes.c_int32)]
+
+
+def _net_sigs(L):
+    P, I64, D, S = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    SH = ctypes.POINTER(NetShape)
+    L.bdg_net_nparams.argtypes = [SH]
+    L.bdg_net_nparams.restype = I64
+    L.bdg_net_workspace.argtypes = [SH, ctypes.POINTER(ctypes.c_size_t)]
+    L.bdg_net_forward.argtypes = [SH, P, P, P, D, P, P, ctypes.c_size_t, S]
+    L.bdg_net_backward.argtypes = [SH, P, P, P, D, P, P, P, P, ctypes.c_size_t, S]
+    L.bdg_net_adam_step.argtypes = [I64, P, P, P, P, ctypes.c_int32, ctypes.c_float, S]
+
+
+class StartNet:
+    """Device state of the start-field network: FP32 master weights, Adam moments."""
+
+    def __init__(self, channels: int, ny: int, nx: int, batch: int, device="cuda"):
+        L = lib()
+        _net_sigs(L)
+        self.shape = NetShape(channels, ny, nx, batch)
+        self.nparams = int(L.bdg_net_nparams(ctypes.byref(self.shape)))
+        if self.nparams < 0:
+            raise BdgError("bdg_net_nparams", -1, L.bdg_last_error().decode())
+        nb = ctypes.c_size_t(0)
+        _call("bdg_net_workspace", ctypes.byref(self.shape), ctypes.byref(nb))
+        self.work = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        self.params = torch.zeros(self.nparams, dtype=torch.float32, device=device)
+        self.grads = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.t = 0
+        self.device = device
+
+    def forward(self, Vext: torch.Tensor, theta: torch.Tensor, mu: float, y=None):
+        B = self.shape.batch
+        P = self.shape.ny * self.shape.nx
+        y = y if y is not None else torch.empty((B, 2, P), dtype=torch.float32, device=self.device)
+        _call("bdg_net_forward", ctypes.byref(self.shape), _dev(self.params), _dev(Vext), _dev(theta),
+              float(mu), _dev(y), _dev(self.work), self.work.numel(), _stream(self.device))
+        return y
+
+    def backward(self, Vext, theta, mu, target):
+        _call("bdg_net_backward", ctypes.byref(self.shape), _dev(self.params), _dev(Vext), _dev(theta),
+              float(mu), _dev(target), _dev(self.grads), _dev(self.loss), _dev(self.work),
+              self.work.numel(), _stream(self.device))
+        return self.loss
+
+    def adam(self, lr: float = 1e-3):
+        self.t += 1
+        _call("bdg_net_adam_step", self.nparams, _dev(self.params), _dev(self.grads), _dev(self.m),
+              _dev(self.v), self.t, float(lr), _stream(self.device))

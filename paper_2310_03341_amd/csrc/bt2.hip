@@ -52,26 +52,29 @@ __global__ void phases_kernel(int64_t n, const double *__restrict__ e_cplx, doub
 }
 
 // Z[:, j] = ph .* Y[:, i0 + j]  (Y real, ld n)
+template <typename F>
 __global__ void scale_phase(int64_t n, int64_t m, const double *__restrict__ Y, int64_t i0,
-                            const double *__restrict__ ph, double *__restrict__ Z, int64_t ldz) {
+                            const double *__restrict__ ph, F *__restrict__ Z, int64_t ldz) {
     const int64_t j = blockIdx.x;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         const double y = Y[i + (i0 + j) * n];
-        Z[2 * (i + j * ldz)] = ph[2 * i] * y;
-        Z[2 * (i + j * ldz) + 1] = ph[2 * i + 1] * y;
+        Z[2 * (i + j * ldz)] = (F)(ph[2 * i] * y);
+        Z[2 * (i + j * ldz) + 1] = (F)(ph[2 * i + 1] * y);
     }
 }
 
 // T factor of every block G(S, t): forward column-wise recurrence from
 // V^H V over the parallelogram and the scales tau.  One workgroup per block.
-__global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const double *__restrict__ V2,
-                                                    const double *__restrict__ tau2,
+template <typename F>
+__global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const F *__restrict__ V2,
+                                                    const F *__restrict__ tau2,
                                                     const int64_t *__restrict__ voff, int64_t nsb,
-                                                    int64_t tmax, double *__restrict__ TF) {
-    __shared__ double2 Vs[VLD * NBK];
-    __shared__ double2 Gs[NBK * NBK];
-    __shared__ double2 Ts[NBK * NBK];
-    __shared__ double ts[NBK];
+                                                    int64_t tmax, F *__restrict__ TF) {
+    typedef typename v2t<F>::type CV;
+    __shared__ CV Vs[VLD * NBK];
+    __shared__ CV Gs[NBK * NBK];
+    __shared__ CV Ts[NBK * NBK];
+    __shared__ F ts[NBK];
     const int64_t blk = blockIdx.x;
     const int64_t S = blk / tmax, t = blk % tmax;
     const int64_t s0 = S * NBK;
@@ -81,10 +84,10 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const doub
     for (int e = tid; e < HT * 16 * NBK; e += blockDim.x) {
         const int r = e % (HT * 16), j = e / (HT * 16);
         const int64_t sw = s0 + j;
-        double2 v = make_double2(0.0, 0.0);
+        CV v = mk2<F>(0.0, 0.0);
         if (sw < nsw && t < (n - 2 - sw) / b + 1) {
             const int o = r - j;
-            if (o >= 0 && o < b) v = *(const double2 *)(V2 + 2 * ((voff[sw] + t) * b + o));
+            if (o >= 0 && o < b) v = *(const CV *)(V2 + 2 * ((voff[sw] + t) * b + o));
         }
         Vs[r + j * VLD] = v;
     }
@@ -96,34 +99,34 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const doub
     // G = V^H V (only the strictly upper part is used)
     for (int e = tid; e < NBK * NBK; e += blockDim.x) {
         const int i = e % NBK, j = e / NBK;
-        double gr = 0.0, gi = 0.0;
+        F gr = 0.0, gi = 0.0;
         if (i < j) {
             for (int r = j; r < i + b && r < HT * 16; ++r) {
-                const double2 a = Vs[r + i * VLD], c = Vs[r + j * VLD];
+                const CV a = Vs[r + i * VLD], c = Vs[r + j * VLD];
                 gr += a.x * c.x + a.y * c.y;
                 gi += a.x * c.y - a.y * c.x;
             }
         }
-        Gs[e] = make_double2(gr, gi);
-        Ts[e] = make_double2(0.0, 0.0);
+        Gs[e] = mk2<F>(gr, gi);
+        Ts[e] = mk2<F>(0.0, 0.0);
     }
     __syncthreads();
     for (int j = 0; j < NBK; ++j) {
-        const double tj = ts[j];
+        const F tj = ts[j];
         if (tid < j) {
-            double sr = 0.0, si = 0.0;
+            F sr = 0.0, si = 0.0;
             for (int l = tid; l < j; ++l) {
-                const double2 a = Ts[tid + l * NBK], g = Gs[l + j * NBK];
+                const CV a = Ts[tid + l * NBK], g = Gs[l + j * NBK];
                 sr += a.x * g.x - a.y * g.y;
                 si += a.x * g.y + a.y * g.x;
             }
-            Ts[tid + j * NBK] = make_double2(-tj * sr, -tj * si);
+            Ts[tid + j * NBK] = mk2<F>(-tj * sr, -tj * si);
         }
-        if (tid == j) Ts[j + j * NBK] = make_double2(tj, 0.0);
+        if (tid == j) Ts[j + j * NBK] = mk2<F>(tj, 0.0);
         __syncthreads();
     }
     for (int e = tid; e < NBK * NBK; e += blockDim.x)
-        *(double2 *)(TF + 2 * (blk * NBK * NBK + e)) = Ts[e];
+        *(CV *)(TF + 2 * (blk * NBK * NBK + e)) = Ts[e];
 }
 
 // Apply every block to a slab of SLAB columns on the FP64 matrix cores.
@@ -133,13 +136,16 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const doub
 // index permuted accordingly (a sum over k does not depend on its order).
 //   W  = V^H Z   (32 x 16)     W2 = T W     Z -= V W2
 // Tiles of the parallelogram V that are zero by construction are skipped.
+template <typename F>
 __global__ __launch_bounds__(256, 2) void bt2_apply(int64_t n, int b, int64_t m,
-                                                 const double *__restrict__ V2,
+                                                 const F *__restrict__ V2,
                                                  const int64_t *__restrict__ voff, int64_t nsb,
-                                                 int64_t tmax, const double *__restrict__ TF,
-                                                 double *__restrict__ Z, int64_t ldz) {
-    __shared__ double2 Vs[VLD * NBK];
-    __shared__ double2 Ts[NBK * NBK];
+                                                 int64_t tmax, const F *__restrict__ TF,
+                                                 F *__restrict__ Z, int64_t ldz) {
+    typedef typename v2t<F>::type CV;
+    typedef typename acc4<F>::type A4;
+    __shared__ CV Vs[VLD * NBK];
+    __shared__ CV Ts[NBK * NBK];
     __shared__ int64_t vb[NBK];  // reflector base of each sweep of the block
     __shared__ int64_t vt[NBK];  // task count of each sweep (0 beyond the last sweep)
     const int tid = threadIdx.x;
@@ -165,20 +171,20 @@ __global__ __launch_bounds__(256, 2) void bt2_apply(int64_t n, int b, int64_t m,
             __syncthreads();
             {
                 // parallelogram: 96 x 32 entries, 12 per thread, loads issued first
-                double2 rv[HT * 16 * NBK / 256];
+                CV rv[HT * 16 * NBK / 256];
 #pragma unroll
                 for (int i = 0; i < HT * 16 * NBK / 256; ++i) {
                     const int e = tid + 256 * i;
                     const int r = e % (HT * 16), j = e / (HT * 16);
                     const int o = r - j;
-                    rv[i] = make_double2(0.0, 0.0);
+                    rv[i] = mk2<F>(0.0, 0.0);
                     if (r < h && o >= 0 && o < b && t < vt[j])
-                        rv[i] = *(const double2 *)(V2 + 2 * ((vb[j] + t) * b + o));
+                        rv[i] = *(const CV *)(V2 + 2 * ((vb[j] + t) * b + o));
                 }
-                double2 rt4[NBK * NBK / 256];
+                CV rt4[NBK * NBK / 256];
 #pragma unroll
                 for (int i = 0; i < NBK * NBK / 256; ++i)
-                    rt4[i] = *(const double2 *)(TF + 2 * ((S * tmax + t) * NBK * NBK + tid + 256 * i));
+                    rt4[i] = *(const CV *)(TF + 2 * ((S * tmax + t) * NBK * NBK + tid + 256 * i));
 #pragma unroll
                 for (int i = 0; i < HT * 16 * NBK / 256; ++i) {
                     const int e = tid + 256 * i;
@@ -189,31 +195,31 @@ __global__ __launch_bounds__(256, 2) void bt2_apply(int64_t n, int b, int64_t m,
                 for (int i = 0; i < NBK * NBK / 256; ++i) Ts[tid + 256 * i] = rt4[i];
             }
             // Z window in accumulator layout
-            d4 zr[HT], zi[HT];
+            A4 zr[HT], zi[HT];
 #pragma unroll
             for (int rt = 0; rt < HT; ++rt) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int row = rt * 16 + lk + 4 * q;
-                    double2 z = make_double2(0.0, 0.0);
-                    if (row < h && colok) z = *(const double2 *)(Z + 2 * ((rs + row) + col * ldz));
+                    const int row = rt * 16 + mfma_row((F)0, lane, q);
+                    CV z = mk2<F>(0.0, 0.0);
+                    if (row < h && colok) z = *(const CV *)(Z + 2 * ((rs + row) + col * ldz));
                     zr[rt][q] = z.x;
                     zi[rt][q] = z.y;
                 }
             }
             __syncthreads();
             // W = V^H Z
-            d4 wr[2], wi[2];
+            A4 wr[2], wi[2];
 #pragma unroll
             for (int it = 0; it < 2; ++it) {
-                wr[it] = d4{0, 0, 0, 0};
-                wi[it] = d4{0, 0, 0, 0};
+                wr[it] = A4{0, 0, 0, 0};
+                wi[it] = A4{0, 0, 0, 0};
 #pragma unroll
                 for (int kt = 0; kt < HT; ++kt) {
                     if (16 * kt + 15 < 16 * it || 16 * kt > 16 * it + 14 + b) continue;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const double2 v = Vs[(16 * kt + lk + 4 * q) + (16 * it + li) * VLD];
+                        const CV v = Vs[(16 * kt + mfma_row((F)0, lane, q)) + (16 * it + li) * VLD];
                         wr[it] = mfma16(v.x, zr[kt][q], wr[it]);
                         wi[it] = mfma16(v.x, zi[kt][q], wi[it]);
                         wr[it] = mfma16(v.y, zi[kt][q], wr[it]);
@@ -222,16 +228,16 @@ __global__ __launch_bounds__(256, 2) void bt2_apply(int64_t n, int b, int64_t m,
                 }
             }
             // W2 = T W   (T upper triangular), stored negated
-            d4 ur[2], ui[2];
+            A4 ur[2], ui[2];
 #pragma unroll
             for (int it = 0; it < 2; ++it) {
-                ur[it] = d4{0, 0, 0, 0};
-                ui[it] = d4{0, 0, 0, 0};
+                ur[it] = A4{0, 0, 0, 0};
+                ui[it] = A4{0, 0, 0, 0};
 #pragma unroll
                 for (int kt = it; kt < 2; ++kt) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const double2 tv = Ts[(16 * it + li) + (16 * kt + lk + 4 * q) * NBK];
+                        const CV tv = Ts[(16 * it + li) + (16 * kt + mfma_row((F)0, lane, q)) * NBK];
                         ur[it] = mfma16(tv.x, wr[kt][q], ur[it]);
                         ui[it] = mfma16(tv.x, wi[kt][q], ui[it]);
                         ur[it] = mfma16(-tv.y, wi[kt][q], ur[it]);
@@ -249,7 +255,7 @@ __global__ __launch_bounds__(256, 2) void bt2_apply(int64_t n, int b, int64_t m,
                     if (16 * rt + 15 < 16 * kt || 16 * rt > 16 * kt + 14 + b) continue;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const double2 v = Vs[(16 * rt + li) + (16 * kt + lk + 4 * q) * VLD];
+                        const CV v = Vs[(16 * rt + li) + (16 * kt + mfma_row((F)0, lane, q)) * VLD];
                         zr[rt] = mfma16(v.x, ur[kt][q], zr[rt]);
                         zi[rt] = mfma16(v.x, ui[kt][q], zi[rt]);
                         zr[rt] = mfma16(-v.y, ui[kt][q], zr[rt]);
@@ -261,9 +267,9 @@ __global__ __launch_bounds__(256, 2) void bt2_apply(int64_t n, int b, int64_t m,
             for (int rt = 0; rt < HT; ++rt) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int row = rt * 16 + lk + 4 * q;
+                    const int row = rt * 16 + mfma_row((F)0, lane, q);
                     if (row < h && colok)
-                        *(double2 *)(Z + 2 * ((rs + row) + col * ldz)) = make_double2(zr[rt][q], zi[rt][q]);
+                        *(CV *)(Z + 2 * ((rs + row) + col * ldz)) = mk2<F>(zr[rt][q], zi[rt][q]);
                 }
             }
         }
@@ -288,29 +294,52 @@ int phases(int64_t n, const double *e_cplx, double *ph, double *e_abs, hipStream
     return 0;
 }
 
-int phase_scale(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, double *Z,
-                int64_t ldz, hipStream_t s) {
+template <typename F>
+int phase_scale_t(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, F *Z,
+                  int64_t ldz, hipStream_t s) {
     if (m <= 0) return 0;
-    hipLaunchKernelGGL(scale_phase, dim3((unsigned)m), dim3(256), 0, s, n, m, Y, i0, ph, Z, ldz);
+    hipLaunchKernelGGL((scale_phase<F>), dim3((unsigned)m), dim3(256), 0, s, n, m, Y, i0, ph, Z, ldz);
     BDG_CHECK_LAUNCH();
     return 0;
 }
 
-int bt2(int64_t n, int b, int64_t m, const double *V2, const double *tau2, const int64_t *voff,
-        double *Z, int64_t ldz, void *work, hipStream_t s) {
+template <typename F>
+int bt2_t(int64_t n, int b, int64_t m, const F *V2, const F *tau2, const int64_t *voff, F *Z,
+          int64_t ldz, void *work, hipStream_t s) {
     if (n < 3 || m <= 0) return 0;
     if (b > BMAX) return BDG_ERR_NOT_IMPLEMENTED;
     const int64_t nsw = n - 2;
     const int64_t nsb = (nsw + NBK - 1) / NBK;
     const int64_t tmax = (n - 2) / b + 1;
-    double *TF = (double *)work;
-    hipLaunchKernelGGL(bt2_tfactors, dim3((unsigned)(nsb * tmax)), dim3(256), 0, s, n, b, V2, tau2, voff,
+    F *TF = (F *)work;
+    hipLaunchKernelGGL((bt2_tfactors<F>), dim3((unsigned)(nsb * tmax)), dim3(256), 0, s, n, b, V2, tau2, voff,
                        nsb, tmax, TF);
     BDG_CHECK_LAUNCH();
-    hipLaunchKernelGGL(bt2_apply, dim3((unsigned)((m + SLAB - 1) / SLAB)), dim3(256), 0, s, n, b, m, V2,
+    hipLaunchKernelGGL((bt2_apply<F>), dim3((unsigned)((m + SLAB - 1) / SLAB)), dim3(256), 0, s, n, b, m, V2,
                        voff, nsb, tmax, TF, Z, ldz);
     BDG_CHECK_LAUNCH();
     return 0;
+}
+
+}  // namespace bdg
+
+namespace bdg {
+
+int phase_scale(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, double *Z,
+                int64_t ldz, hipStream_t s) {
+    return phase_scale_t<double>(n, m, Y, i0, ph, Z, ldz, s);
+}
+int phase_scale(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, float *Z,
+                int64_t ldz, hipStream_t s) {
+    return phase_scale_t<float>(n, m, Y, i0, ph, Z, ldz, s);
+}
+int bt2(int64_t n, int b, int64_t m, const double *V2, const double *tau2, const int64_t *voff,
+        double *Z, int64_t ldz, void *work, hipStream_t s) {
+    return bt2_t<double>(n, b, m, V2, tau2, voff, Z, ldz, work, s);
+}
+int bt2(int64_t n, int b, int64_t m, const float *V2, const float *tau2, const int64_t *voff,
+        float *Z, int64_t ldz, void *work, hipStream_t s) {
+    return bt2_t<float>(n, b, m, V2, tau2, voff, Z, ldz, work, s);
 }
 
 }  // namespace bdg

@@ -5,6 +5,7 @@
 
 #include "common.h"
 #include "gemm.h"
+#include "net.h"
 #include "solver.h"
 
 namespace bdg {
@@ -267,6 +268,65 @@ int bdg_scf_step(const bdg_lattice *lat, const double *Vext, const double *theta
     }
     return bdg::scf_step(lat, Vext, theta, mu, params, U, absDelta, density, nu_abs, change, m, work,
                          (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+extern "C" {
+
+static int net_shape_ok(const bdg_net_shape *sh) {
+    if (!sh || sh->channels < 1 || sh->channels > 64 || sh->ny < 3 || sh->nx < 3 || sh->batch < 1) {
+        set_error("net: shape must have 1 <= channels <= 64, ny, nx >= 3, batch >= 1");
+        return -1;
+    }
+    return 0;
+}
+
+int64_t bdg_net_nparams(const bdg_net_shape *shape) {
+    if (net_shape_ok(shape)) return -1;
+    return bdg::net_layout(shape).nparams;
+}
+
+int bdg_net_workspace(const bdg_net_shape *shape, size_t *bytes) {
+    BDG_TRY(net_shape_ok(shape));
+    if (!bytes) return -2;
+    *bytes = bdg::net_layout(shape).total;
+    return 0;
+}
+
+int bdg_net_forward(const bdg_net_shape *shape, const float *params, const double *Vext,
+                    const double *theta, double mu, float *y, void *work, size_t work_bytes,
+                    bdg_stream_t stream) {
+    BDG_TRY(net_shape_ok(shape));
+    if (!params) return -2;
+    if (!Vext) return -3;
+    if (!theta) return -4;
+    if (!y) return -6;
+    if (!work || work_bytes < bdg::net_layout(shape).total) return BDG_ERR_WORKSPACE;
+    return bdg::net_forward(shape, params, Vext, theta, mu, y, work, (hipStream_t)stream);
+}
+
+int bdg_net_backward(const bdg_net_shape *shape, const float *params, const double *Vext,
+                     const double *theta, double mu, const float *target, float *grads,
+                     float *loss, void *work, size_t work_bytes, bdg_stream_t stream) {
+    BDG_TRY(net_shape_ok(shape));
+    if (!params) return -2;
+    if (!Vext) return -3;
+    if (!theta) return -4;
+    if (!target) return -6;
+    if (!grads) return -7;
+    if (!loss) return -8;
+    if (!work || work_bytes < bdg::net_layout(shape).total) return BDG_ERR_WORKSPACE;
+    return bdg::net_backward(shape, params, Vext, theta, mu, target, grads, loss, work,
+                             (hipStream_t)stream);
+}
+
+int bdg_net_adam_step(int64_t nparams, float *params, const float *grads, float *m, float *v,
+                      int32_t t, float lr, bdg_stream_t stream) {
+    if (nparams < 1) return -1;
+    if (!params || !grads || !m || !v) return -2;
+    if (t < 1) return -6;
+    return bdg::net_adam(nparams, params, grads, m, v, t, lr, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -53,6 +53,22 @@ template <typename T> struct acc4;
 template <> struct acc4<double> { typedef d4 type; };
 template <> struct acc4<float> { typedef f4 type; };
 
+// Two-component vector of a real type (interleaved complex element).
+template <typename T> struct v2t;
+template <> struct v2t<double> { typedef double2 type; };
+template <> struct v2t<float> { typedef float2 type; };
+template <typename T>
+__host__ __device__ inline typename v2t<T>::type mk2(T x, T y) {
+    typename v2t<T>::type v;
+    v.x = x;
+    v.y = y;
+    return v;
+}
+template <typename T>
+__device__ inline typename v2t<T>::type ld2(const T *p) { return *(const typename v2t<T>::type *)p; }
+template <typename T>
+__device__ inline void st2(T *p, typename v2t<T>::type v) { *(typename v2t<T>::type *)p = v; }
+
 // Wave-level reductions (64 lanes).
 template <typename T>
 __device__ inline T wave_sum(T v) {

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "refine.h"
 #include "solver.h"
 #include "stages.h"
 
@@ -70,16 +71,15 @@ __global__ void nonfinite_lower(int64_t n, const double *__restrict__ A, int64_t
 
 struct Timer {
     hipStream_t s;
-    hipEvent_t ev[9];
-    int k = 0;
+    hipEvent_t ev[10];
     bool ok = false;
     explicit Timer(hipStream_t st) : s(st) {
         ok = true;
-        for (int i = 0; i < 9; ++i)
+        for (int i = 0; i < 10; ++i)
             if (hipEventCreate(&ev[i]) != hipSuccess) ok = false;
     }
     ~Timer() {
-        for (int i = 0; i < 9; ++i) (void)hipEventDestroy(ev[i]);
+        for (int i = 0; i < 10; ++i) (void)hipEventDestroy(ev[i]);
     }
     void mark(int i) {
         if (ok) (void)hipEventRecord(ev[i], s);
@@ -93,12 +93,177 @@ struct Timer {
 
 }  // namespace
 
+struct MLayout {
+    int b;
+    int64_t ldab, np, nrefl;
+    size_t off_AB, off_T1, off_V2, off_tau2, off_voff, off_d, off_ec, off_ea, off_ph, off_W2,
+        off_lam, off_flag, off_s1, off_s2, off_s3, off_s4, total;
+};
+
+// Mixed-precision workspace: slot1 = A32 (later the low half of X64), slot2 = Y
+// (later the high half of X64), slot3 = stage scratch (later refinement B1),
+// slot4 = X32 (later refinement B2).
+MLayout mlayout(int64_t n, const bdg_opts *o) {
+    MLayout L;
+    L.b = (o && o->band > 0) ? o->band : DEFAULT_BAND;
+    if (L.b > 64) L.b = 64;
+    if (n <= 2) L.b = 1;
+    L.ldab = 2 * L.b + 2;
+    L.np = he2hb_panels(n, L.b);
+    L.nrefl = hb2st_nrefl(n, L.b);
+    size_t o_ = 0;
+    auto put = [&](size_t bytes) { size_t r = o_; o_ += al(bytes); return r; };
+    const size_t nn = (size_t)n * n;
+    L.off_AB = put(8 * (size_t)L.ldab * n);
+    L.off_T1 = put(8 * (size_t)(L.np + 1) * L.b * L.b);
+    L.off_V2 = put(8 * (size_t)(L.nrefl + 1) * L.b);
+    L.off_tau2 = put(4 * (size_t)(L.nrefl + 1));
+    L.off_voff = put(8 * (size_t)(n + 1));
+    L.off_d = put(8 * (size_t)n);
+    L.off_ec = put(16 * (size_t)n);
+    L.off_ea = put(8 * (size_t)n);
+    L.off_ph = put(16 * (size_t)n);
+    L.off_W2 = put(8 * (size_t)n);
+    L.off_lam = put(8 * (size_t)n);
+    L.off_flag = put(256);
+    L.off_s1 = put(8 * nn);
+    L.off_s2 = put(8 * nn);  // contiguous with s1: X64 spans both
+    size_t sc = std::max(he2hb_workspace(n, L.b), stedc_workspace(n));
+    sc = std::max(sc, bt2_workspace(n, L.b));
+    sc = std::max(sc, bt1_workspace(n, L.b));
+    const size_t rw = refine_workspace(n, n);
+    L.off_s3 = put(std::max(sc, rw / 2 + 65536));
+    L.off_s4 = put(std::max(8 * nn, rw / 2 + 65536));
+    L.total = o_ + 256;
+    return L;
+}
+
 int eigh_workspace(int64_t n, const bdg_opts *opts, size_t *bytes) {
-    if (opts && opts->precision != BDG_FP64) {
-        set_error("bdg_eigh: only BDG_FP64 is available in this build");
+    if (opts && opts->precision != BDG_FP64 && opts->precision != BDG_FP32_REFINED) {
+        set_error("bdg_eigh: unknown precision %d", opts->precision);
         return BDG_ERR_NOT_IMPLEMENTED;
     }
-    *bytes = layout(n, opts).total;
+    *bytes = (opts && opts->precision == BDG_FP32_REFINED) ? mlayout(n, opts).total : layout(n, opts).total;
+    return 0;
+}
+
+__global__ void neg_reverse(int64_t half, const double *__restrict__ W, double *__restrict__ lam) {
+    // lam[half - 1 - j] = -W[half + j], lam[half + j] = W[half + j]
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < half;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const double w = W[half + j];
+        lam[half - 1 - j] = -w;
+        lam[half + j] = w;
+    }
+}
+
+int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, double *W, double *Z,
+               int64_t ldz, int64_t zcols, int64_t *m_out, const bdg_opts *opts, void *work,
+               bdg_err_report *report, hipStream_t s) {
+    const MLayout L = mlayout(n, opts);
+    const int b = L.b;
+    char *base = (char *)work;
+    float *AB = (float *)(base + L.off_AB);
+    float *T1 = (float *)(base + L.off_T1);
+    float *V2 = (float *)(base + L.off_V2);
+    float *tau2 = (float *)(base + L.off_tau2);
+    int64_t *voff = (int64_t *)(base + L.off_voff);
+    double *d = (double *)(base + L.off_d);
+    double *ec = (double *)(base + L.off_ec);
+    double *ea = (double *)(base + L.off_ea);
+    double *ph = (double *)(base + L.off_ph);
+    double *W2 = (double *)(base + L.off_W2);
+    double *lam = (double *)(base + L.off_lam);
+    int *flag = (int *)(base + L.off_flag);
+    float *A32 = (float *)(base + L.off_s1);
+    double *Y = (double *)(base + L.off_s2);
+    double *X64 = (double *)(base + L.off_s1);  // spans s1 and s2 once A32 and Y are dead
+    void *scratch = base + L.off_s3;
+    float *X32 = (float *)(base + L.off_s4);
+    void *rscratch = base + L.off_s3;            // s3 and s4 once the stages are done
+    const int leaf = (opts && opts->dc_leaf > 0) ? opts->dc_leaf : 32;
+    const bool ph_mirror = opts && opts->ph_mirror && (n % 2 == 0);
+    const int iters = (opts && opts->refine_max_iter > 0) ? opts->refine_max_iter : 2;
+
+    Timer tm(s);
+    tm.mark(0);
+    BDG_HIP(hipMemsetAsync(flag, 0, 4, s));
+    hipLaunchKernelGGL(nonfinite_lower, dim3((unsigned)n), dim3(256), 0, s, n, A, lda, flag);
+    BDG_CHECK_LAUNCH();
+    int hflag = 0;
+    BDG_HIP(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+    BDG_HIP(hipStreamSynchronize(s));
+    if (hflag) {
+        set_error("bdg_eigh: the input matrix holds NaN or Inf");
+        return BDG_ERR_NONFINITE;
+    }
+    BDG_TRY(cast_c128_to_c64(n, n, A, lda, A32, n, s));
+    tm.mark(1);
+    BDG_TRY(he2hb(n, A32, n, b, AB, L.ldab, T1, scratch, s));
+    tm.mark(2);
+    if (n >= 3) {
+        std::vector<int64_t> vh((size_t)(n - 2));
+        hb2st_offsets(n, b, vh.data());
+        BDG_HIP(hipMemcpyAsync(voff, vh.data(), 8 * (size_t)(n - 2), hipMemcpyHostToDevice, s));
+        BDG_HIP(hipStreamSynchronize(s));
+    }
+    BDG_TRY(hb2st(n, b, AB, L.ldab, V2, tau2, voff, d, ec, s));
+    BDG_TRY(phases(n, ec, ph, ea, s));
+    tm.mark(3);
+    BDG_TRY(stedc(n, d, ea, W2, Y, n, scratch, s, leaf));
+    tm.mark(4);
+    // FP32 basis: all columns, or the E >= 0 half and its particle-hole partners
+    const int64_t c0 = ph_mirror ? n / 2 : 0;
+    const int64_t nc = n - c0;
+    BDG_TRY(phase_scale(n, nc, Y, c0, ph, X32 + 2 * c0 * n, n, s));
+    tm.mark(5);
+    BDG_TRY(bt2(n, b, nc, V2, tau2, voff, X32 + 2 * c0 * n, n, scratch, s));
+    tm.mark(6);
+    BDG_TRY(bt1(n, nc, A32, n, b, T1, X32 + 2 * c0 * n, n, scratch, s));
+    if (ph_mirror) {
+        BDG_TRY(mirror_half(n, X32, n, s));
+        hipLaunchKernelGGL(neg_reverse, dim3(64), dim3(256), 0, s, n / 2, W2, lam);
+        BDG_CHECK_LAUNCH();
+    } else {
+        BDG_HIP(hipMemcpyAsync(lam, W2, 8 * (size_t)n, hipMemcpyDeviceToDevice, s));
+    }
+    tm.mark(7);
+    // window on the FP64 eigenvalues of the FP32-reduced tridiagonal
+    std::vector<double> wh((size_t)n);
+    BDG_HIP(hipMemcpyAsync(wh.data(), lam, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
+    BDG_HIP(hipStreamSynchronize(s));
+    const int64_t i0 = std::lower_bound(wh.begin(), wh.end(), emin) - wh.begin();
+    const int64_t i1 = std::upper_bound(wh.begin(), wh.end(), emax) - wh.begin();
+    const int64_t m = i1 > i0 ? i1 - i0 : 0;
+    *m_out = m;
+    if (m > zcols) {
+        set_error("bdg_eigh: %lld eigenpairs in the window exceed zcols=%lld", (long long)m,
+                  (long long)zcols);
+        return BDG_ERR_WORKSPACE;
+    }
+    double normH = 0.0;
+    for (double v : wh) normH = std::max(normH, std::fabs(v));
+    BDG_TRY(cast_c64_to_c128(n, n, X32, n, X64, n, s));
+    double shift = 0.0, corr = 0.0;
+    BDG_TRY(refine_window(n, A, lda, X64, n, lam, i0, m, normH, iters, W, rscratch, s, &shift, &corr));
+    if (m > 0) BDG_HIP(hipMemcpy2DAsync(Z, 16 * (size_t)ldz, X64 + 2 * i0 * n, 16 * (size_t)n,
+                                        16 * (size_t)n, (size_t)m, hipMemcpyDeviceToDevice, s));
+    tm.mark(8);
+    BDG_HIP(hipStreamSynchronize(s));
+    if (report) {
+        memset(report, 0, sizeof(*report));
+        report->stage_ms[0] = tm.ms(1, 2);
+        report->stage_ms[1] = tm.ms(2, 3);
+        report->stage_ms[2] = tm.ms(3, 4);
+        report->stage_ms[3] = tm.ms(5, 6);
+        report->stage_ms[4] = tm.ms(6, 7);
+        report->stage_ms[5] = tm.ms(7, 8);
+        report->stage_ms[6] = tm.ms(4, 5);
+        report->stage_ms[7] = tm.ms(0, 8);
+        report->eig_shift_max = shift;
+        report->refine_iters = iters;
+        report->max_resid = corr;  // last eigenvalue correction (the residual is measured by bdg_check)
+    }
     return 0;
 }
 
@@ -106,8 +271,10 @@ int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
          int64_t ldz, int64_t zcols, int64_t *m_out, const bdg_opts *opts, void *work,
          size_t work_bytes, bdg_err_report *report, hipStream_t s) {
     (void)work_bytes;
+    if (opts && opts->precision == BDG_FP32_REFINED)
+        return eigh_mixed(n, A, lda, emin, emax, W, Z, ldz, zcols, m_out, opts, work, report, s);
     if (opts && opts->precision != BDG_FP64) {
-        set_error("bdg_eigh: only BDG_FP64 is available in this build");
+        set_error("bdg_eigh: unknown precision %d", opts->precision);
         return BDG_ERR_NOT_IMPLEMENTED;
     }
     const Layout L = layout(n, opts);

@@ -28,19 +28,19 @@ constexpr int BMAX = 64;
 constexpr int LDS = BMAX + 1;
 constexpr int LAG = 2;  // task t of sweep s runs in step t + LAG s
 
-__device__ inline double2 ld2(const double *p) { return *(const double2 *)p; }
-__device__ inline void st2(double *p, double2 v) { *(double2 *)p = v; }
 
-__global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, double *__restrict__ AB,
-                                                  int64_t ldab, double *__restrict__ V2,
-                                                  double *__restrict__ tau2,
+template <typename F>
+__global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restrict__ AB,
+                                                  int64_t ldab, F *__restrict__ V2,
+                                                  F *__restrict__ tau2,
                                                   const int64_t *__restrict__ voff, int64_t g,
                                                   int64_t s_lo) {
-    __shared__ double2 Bs[BMAX * LDS];
-    __shared__ double2 Ds[BMAX * LDS];
-    __shared__ double2 vp[BMAX], vn[BMAX], yv[BMAX], pv[BMAX], wb[BMAX];
-    __shared__ double red[4][4];
-    __shared__ double sc[8];
+    typedef typename v2t<F>::type CV;
+    __shared__ CV Bs[BMAX * LDS];
+    __shared__ CV Ds[BMAX * LDS];
+    __shared__ CV vp[BMAX], vn[BMAX], yv[BMAX], pv[BMAX], wb[BMAX];
+    __shared__ F red[4][4];
+    __shared__ F sc[8];
     const int64_t s = s_lo + blockIdx.x;
     const int64_t t = g - LAG * s;
     if (s > n - 3 || t < 0) return;
@@ -52,30 +52,30 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, double *__re
     const int Lr = (int)min((int64_t)b, n - r0);
     const int64_t ridx = voff[s] + t;
     const int64_t c0 = r0 - b;
-    double tp = 0.0;
+    F tp = 0.0;
 
     // ---- phase 0: load B = A[R, C] (t > 0), D = A[R, R] (full Hermitian), previous v.
     // Fixed trip counts (64 x 64 tiles, 16 elements per thread) so that all
     // global loads are issued before their LDS stores.
     {
-        double2 rb[16], rd[16];
+        CV rb[16], rd[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int e = tid + 256 * i;
             const int r = e & 63, c = e >> 6;
-            rb[i] = make_double2(0.0, 0.0);
-            if (t > 0 && r < Lr && c < b) rb[i] = ld2(AB + 2 * ((b + r - c) + (c0 + c) * ldab));
-            rd[i] = make_double2(0.0, 0.0);
+            rb[i] = mk2<F>(0.0, 0.0);
+            if (t > 0 && r < Lr && c < b) rb[i] = ld2<F>(AB + 2 * ((b + r - c) + (c0 + c) * ldab));
+            rd[i] = mk2<F>(0.0, 0.0);
             if (r < Lr && c < Lr) {
-                if (r >= c) rd[i] = ld2(AB + 2 * ((r - c) + (r0 + c) * ldab));
+                if (r >= c) rd[i] = ld2<F>(AB + 2 * ((r - c) + (r0 + c) * ldab));
                 else {
-                    rd[i] = ld2(AB + 2 * ((c - r) + (r0 + r) * ldab));
+                    rd[i] = ld2<F>(AB + 2 * ((c - r) + (r0 + r) * ldab));
                     rd[i].y = -rd[i].y;
                 }
             }
         }
         if (t > 0) {
-            if (tid < b) vp[tid] = ld2(V2 + 2 * ((ridx - 1) * b + tid));
+            if (tid < b) vp[tid] = ld2<F>(V2 + 2 * ((ridx - 1) * b + tid));
             tp = tau2[ridx - 1];
         }
 #pragma unroll
@@ -93,31 +93,31 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, double *__re
         for (int base = 0; base < Lr * 4; base += blockDim.x) {
             const int e = base + tid;
             const int r = e >> 2, q = e & 3;
-            double yr = 0.0, yi = 0.0;
+            F yr = 0.0, yi = 0.0;
             if (r < Lr && tp != 0.0) {
                 for (int c = q; c < b; c += 4) {
-                    const double2 a = Bs[r + c * LDS], v = vp[c];
+                    const CV a = Bs[r + c * LDS], v = vp[c];
                     yr += a.x * v.x - a.y * v.y;
                     yi += a.x * v.y + a.y * v.x;
                 }
             }
             yr += __shfl_xor(yr, 1, 64); yi += __shfl_xor(yi, 1, 64);
             yr += __shfl_xor(yr, 2, 64); yi += __shfl_xor(yi, 2, 64);
-            if (r < Lr && q == 0) yv[r] = make_double2(tp * yr, tp * yi);
+            if (r < Lr && q == 0) yv[r] = mk2<F>(tp * yr, tp * yi);
         }
         __syncthreads();
     }
 
     // ---- phase 2: x (first bulge column after the right update), reflector
     {
-        double t2 = 0.0;
+        F t2 = 0.0;
         for (int r = tid; r < Lr; r += blockDim.x) {
-            double2 x;
+            CV x;
             if (t > 0) {
-                const double2 a = Bs[r], y = yv[r];
-                x = make_double2(a.x - y.x, a.y - y.y);  // vp_0 = 1
+                const CV a = Bs[r], y = yv[r];
+                x = mk2<F>(a.x - y.x, a.y - y.y);  // vp_0 = 1
             } else {
-                x = ld2(AB + 2 * ((1 + r) + s * ldab));
+                x = ld2<F>(AB + 2 * ((1 + r) + s * ldab));
             }
             vn[r] = x;
             if (r > 0) t2 += x.x * x.x + x.y * x.y;
@@ -126,16 +126,16 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, double *__re
         if (l == 0) red[w][0] = t2;
         __syncthreads();
         if (tid == 0) {
-            const double tail2 = red[0][0] + red[1][0] + red[2][0] + red[3][0];
-            const double ar = vn[0].x, ai = vn[0].y;
-            const double aa = sqrt(ar * ar + ai * ai);
+            const F tail2 = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+            const F ar = vn[0].x, ai = vn[0].y;
+            const F aa = sqrt(ar * ar + ai * ai);
             if (tail2 == 0.0) {
                 sc[0] = 0.0; sc[1] = 0.0; sc[2] = 0.0; sc[3] = ar; sc[4] = ai;
             } else {
-                const double xn = sqrt(aa * aa + tail2);
-                double sr = 1.0, si = 0.0;
+                const F xn = sqrt(aa * aa + tail2);
+                F sr = 1.0, si = 0.0;
                 if (aa > 0.0) { sr = ar / aa; si = ai / aa; }
-                const double den = aa + xn;
+                const F den = aa + xn;
                 sc[0] = sr / den;     // 1/u0 = conj(sgn)/(|a| + |x|)
                 sc[1] = -si / den;
                 sc[2] = den / xn;     // tau
@@ -145,20 +145,20 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, double *__re
         }
         __syncthreads();
     }
-    const double tj = sc[2];
-    const double2 beta = make_double2(sc[3], sc[4]);
+    const F tj = sc[2];
+    const CV beta = mk2<F>(sc[3], sc[4]);
     {
-        const double ur = sc[0], ui = sc[1];
-        double2 vr0 = make_double2(0.0, 0.0);
+        const F ur = sc[0], ui = sc[1];
+        CV vr0 = mk2<F>(0.0, 0.0);
         if (tid < b) {
-            double2 v;
-            if (tid == 0) v = make_double2(1.0, 0.0);
+            CV v;
+            if (tid == 0) v = mk2<F>(1.0, 0.0);
             else if (tid < Lr && tj != 0.0) {
-                const double2 x = vn[tid];
-                v = make_double2(x.x * ur - x.y * ui, x.x * ui + x.y * ur);
-            } else v = make_double2(0.0, 0.0);
+                const CV x = vn[tid];
+                v = mk2<F>(x.x * ur - x.y * ui, x.x * ui + x.y * ur);
+            } else v = mk2<F>(0.0, 0.0);
             vr0 = v;
-            st2(V2 + 2 * (ridx * b + tid), v);
+            st2<F>(V2 + 2 * (ridx * b + tid), v);
         }
         if (tid == 0) tau2[ridx] = tj;
         __syncthreads();
@@ -172,43 +172,43 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, double *__re
             for (int base = 0; base < b * 4; base += blockDim.x) {
                 const int e = base + tid;
                 const int c = e >> 2, q = e & 3;
-                double sr = 0.0, si = 0.0;
+                F sr = 0.0, si = 0.0;
                 if (c < b) {
                     for (int r = q; r < Lr; r += 4) {
-                        const double2 v = vn[r], a = Bs[r + c * LDS];
+                        const CV v = vn[r], a = Bs[r + c * LDS];
                         sr += v.x * a.x + v.y * a.y;
                         si += v.x * a.y - v.y * a.x;
                     }
                 }
                 sr += __shfl_xor(sr, 1, 64); si += __shfl_xor(si, 1, 64);
                 sr += __shfl_xor(sr, 2, 64); si += __shfl_xor(si, 2, 64);
-                if (c < b && q == 0) wb[c] = make_double2(sr, si);
+                if (c < b && q == 0) wb[c] = mk2<F>(sr, si);
             }
         }
         for (int base = 0; base < Lr * 4; base += blockDim.x) {
             const int e = base + tid;
             const int r = e >> 2, q = e & 3;
-            double pr = 0.0, pi = 0.0;
+            F pr = 0.0, pi = 0.0;
             if (r < Lr) {
                 for (int c = q; c < Lr; c += 4) {
-                    const double2 a = Ds[r + c * LDS], v = vn[c];
+                    const CV a = Ds[r + c * LDS], v = vn[c];
                     pr += a.x * v.x - a.y * v.y;
                     pi += a.x * v.y + a.y * v.x;
                 }
             }
             pr += __shfl_xor(pr, 1, 64); pi += __shfl_xor(pi, 1, 64);
             pr += __shfl_xor(pr, 2, 64); pi += __shfl_xor(pi, 2, 64);
-            if (r < Lr && q == 0) pv[r] = make_double2(tj * pr, tj * pi);
+            if (r < Lr && q == 0) pv[r] = mk2<F>(tj * pr, tj * pi);
         }
         __syncthreads();
         // K = (tau/2) v^H p  and  gamma = v^H y
-        double kr = 0.0, ki = 0.0, gr = 0.0, gi = 0.0;
+        F kr = 0.0, ki = 0.0, gr = 0.0, gi = 0.0;
         for (int r = tid; r < Lr; r += blockDim.x) {
-            const double2 v = vn[r], p = pv[r];
+            const CV v = vn[r], p = pv[r];
             kr += v.x * p.x + v.y * p.y;
             ki += v.x * p.y - v.y * p.x;
             if (t > 0) {
-                const double2 y = yv[r];
+                const CV y = yv[r];
                 gr += v.x * y.x + v.y * y.y;
                 gi += v.x * y.y - v.y * y.x;
             }
@@ -228,62 +228,63 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, double *__re
 
     // ---- phase 4: write B and D
     if (t > 0) {
-        const double gmr = red[0][2], gmi = red[0][3];
+        const F gmr = red[0][2], gmi = red[0][3];
 #pragma unroll 4
         for (int i = 0; i < 16; ++i) {
             const int e = tid + 256 * i;
             const int r = e & 63, c = e >> 6;
             if (r >= Lr || c >= b) continue;
-            double2 a;
+            CV a;
             if (c == 0) {
-                a = (tj == 0.0) ? make_double2(vn[0].x * 0 + Bs[r].x - yv[r].x, Bs[r].y - yv[r].y)
-                                : (r == 0 ? beta : make_double2(0.0, 0.0));
+                a = (tj == 0.0) ? mk2<F>(vn[0].x * 0 + Bs[r].x - yv[r].x, Bs[r].y - yv[r].y)
+                                : (r == 0 ? beta : mk2<F>(0.0, 0.0));
             } else {
                 a = Bs[r + c * LDS];
-                const double2 vpc = vp[c], y = yv[r];
+                const CV vpc = vp[c], y = yv[r];
                 // right update: - y conj(vp_c)
                 a.x -= y.x * vpc.x + y.y * vpc.y;
                 a.y -= y.y * vpc.x - y.x * vpc.y;
                 if (tj != 0.0) {
                     // left update: - tau v_r (wB_c - gamma conj(vp_c)),  gamma = v^H y (y holds tp)
-                    const double2 wbc = wb[c];
-                    const double qr = wbc.x - (gmr * vpc.x + gmi * vpc.y);
-                    const double qi = wbc.y - (gmi * vpc.x - gmr * vpc.y);
-                    const double2 v = vn[r];
+                    const CV wbc = wb[c];
+                    const F qr = wbc.x - (gmr * vpc.x + gmi * vpc.y);
+                    const F qi = wbc.y - (gmi * vpc.x - gmr * vpc.y);
+                    const CV v = vn[r];
                     a.x -= tj * (v.x * qr - v.y * qi);
                     a.y -= tj * (v.x * qi + v.y * qr);
                 }
             }
-            st2(AB + 2 * ((b + r - c) + (c0 + c) * ldab), a);
+            st2<F>(AB + 2 * ((b + r - c) + (c0 + c) * ldab), a);
         }
     } else {
         for (int r = tid; r < Lr; r += blockDim.x) {
-            const double2 a = (tj == 0.0) ? vn[r] : (r == 0 ? beta : make_double2(0.0, 0.0));
+            const CV a = (tj == 0.0) ? vn[r] : (r == 0 ? beta : mk2<F>(0.0, 0.0));
             // when tj == 0 the column is unchanged (vn was overwritten by v; reload)
             if (tj == 0.0) continue;
-            st2(AB + 2 * ((1 + r) + s * ldab), a);
+            st2<F>(AB + 2 * ((1 + r) + s * ldab), a);
         }
     }
     if (tj != 0.0) {
-        const double Kr = sc[5], Ki = sc[6];
+        const F Kr = sc[5], Ki = sc[6];
 #pragma unroll 4
         for (int i = 0; i < 16; ++i) {
             const int e = tid + 256 * i;
             const int r = e & 63, c = e >> 6;
             if (r >= Lr || c >= Lr || r < c) continue;
-            const double2 vr = vn[r], vc = vn[c], pr = pv[r], pc = pv[c];
-            const double2 wr = make_double2(pr.x - (Kr * vr.x - Ki * vr.y), pr.y - (Kr * vr.y + Ki * vr.x));
-            const double2 wc = make_double2(pc.x - (Kr * vc.x - Ki * vc.y), pc.y - (Kr * vc.y + Ki * vc.x));
-            double2 a = Ds[r + c * LDS];
+            const CV vr = vn[r], vc = vn[c], pr = pv[r], pc = pv[c];
+            const CV wr = mk2<F>(pr.x - (Kr * vr.x - Ki * vr.y), pr.y - (Kr * vr.y + Ki * vr.x));
+            const CV wc = mk2<F>(pc.x - (Kr * vc.x - Ki * vc.y), pc.y - (Kr * vc.y + Ki * vc.x));
+            CV a = Ds[r + c * LDS];
             a.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
             a.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
             if (r == c) a.y = 0.0;
-            st2(AB + 2 * ((r - c) + (r0 + c) * ldab), a);
+            st2<F>(AB + 2 * ((r - c) + (r0 + c) * ldab), a);
         }
     }
 }
 
-__global__ void hb2st_extract(int64_t n, const double *__restrict__ AB, int64_t ldab,
+template <typename F>
+__global__ void hb2st_extract(int64_t n, const F *__restrict__ AB, int64_t ldab,
                               double *__restrict__ d, double *__restrict__ e_cplx) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -311,8 +312,9 @@ void hb2st_offsets(int64_t n, int b, int64_t *voff_host) {
     }
 }
 
-int hb2st(int64_t n, int b, double *AB, int64_t ldab, double *V2, double *tau2,
-          const int64_t *voff_dev, double *d, double *e_cplx, hipStream_t s) {
+template <typename F>
+int hb2st_t(int64_t n, int b, F *AB, int64_t ldab, F *V2, F *tau2, const int64_t *voff_dev,
+            double *d, double *e_cplx, hipStream_t s) {
     if (b > BMAX) {
         set_error("hb2st: band %d > %d", b, BMAX);
         return BDG_ERR_NOT_IMPLEMENTED;
@@ -329,15 +331,28 @@ int hb2st(int64_t n, int b, double *AB, int64_t ldab, double *V2, double *tau2,
             int64_t s_hi = g / LAG;
             if (s_hi > nsw - 1) s_hi = nsw - 1;
             if (s_hi < s_lo) continue;
-            hipLaunchKernelGGL(hb2st_step, dim3((unsigned)(s_hi - s_lo + 1)), dim3(256), 0, s, n, b,
+            hipLaunchKernelGGL((hb2st_step<F>), dim3((unsigned)(s_hi - s_lo + 1)), dim3(256), 0, s, n, b,
                                AB, ldab, V2, tau2, voff_dev, g, s_lo);
         }
         BDG_CHECK_LAUNCH();
     }
-    hipLaunchKernelGGL(hb2st_extract, dim3((unsigned)((n + 255) / 256 > 1024 ? 1024 : (n + 255) / 256)),
+    hipLaunchKernelGGL((hb2st_extract<F>), dim3((unsigned)((n + 255) / 256 > 1024 ? 1024 : (n + 255) / 256)),
                        dim3(256), 0, s, n, AB, ldab, d, e_cplx);
     BDG_CHECK_LAUNCH();
     return 0;
+}
+
+}  // namespace bdg
+
+namespace bdg {
+
+int hb2st(int64_t n, int b, double *AB, int64_t ldab, double *V2, double *tau2,
+          const int64_t *voff_dev, double *d, double *e_cplx, hipStream_t s) {
+    return hb2st_t<double>(n, b, AB, ldab, V2, tau2, voff_dev, d, e_cplx, s);
+}
+int hb2st(int64_t n, int b, float *AB, int64_t ldab, float *V2, float *tau2,
+          const int64_t *voff_dev, double *d, double *e_cplx, hipStream_t s) {
+    return hb2st_t<float>(n, b, AB, ldab, V2, tau2, voff_dev, d, e_cplx, s);
 }
 
 }  // namespace bdg

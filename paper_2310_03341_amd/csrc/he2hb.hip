@@ -24,16 +24,17 @@ constexpr int PQ_ROWS = 256;  // rows per workgroup in the panel kernels
 constexpr int MAXB = 64;      // largest supported band
 
 // Partials layout per workgroup: [0..nb) complex s_c, [nb] (tail2, 0).
-__device__ inline void reduce_partials(const double *__restrict__ part, int G, int nb,
-                                       double *__restrict__ s_sh /* 2*(nb+1) */) {
+template <typename F>
+__device__ inline void reduce_partials(const F *__restrict__ part, int G, int nb,
+                                       F *__restrict__ s_sh /* 2*(nb+1) */) {
     // 4 threads per column (256 threads)
-    __shared__ double tmp[4][2 * (MAXB + 1)];
+    __shared__ F tmp[4][2 * (MAXB + 1)];
     const int t = threadIdx.x;
     for (int col = t & 63; col <= nb; col += 64) {
         const int g0 = t >> 6;
-        double re = 0.0, im = 0.0;
+        F re = 0.0, im = 0.0;
         for (int g = g0; g < G; g += 4) {
-            const double *p = part + (size_t)g * 2 * (nb + 1) + 2 * col;
+            const F *p = part + (size_t)g * 2 * (nb + 1) + 2 * col;
             re += p[0];
             im += p[1];
         }
@@ -42,7 +43,7 @@ __device__ inline void reduce_partials(const double *__restrict__ part, int G, i
     }
     __syncthreads();
     for (int col = t; col <= nb; col += blockDim.x) {
-        double re = 0.0, im = 0.0;
+        F re = 0.0, im = 0.0;
         for (int g = 0; g < 4; ++g) {
             re += tmp[g][2 * col];
             im += tmp[g][2 * col + 1];
@@ -56,36 +57,38 @@ __device__ inline void reduce_partials(const double *__restrict__ part, int G, i
 // One column step of the panel QR.
 //   j >= 0: apply reflector j (from partials in part_in / row_in) to the panel.
 //   j+1 < ncol: write partials for column j+1 to part_out / row_out.
-__global__ __launch_bounds__(256) void panel_step(double *__restrict__ P, int64_t ld, int64_t mr,
+template <typename F>
+__global__ __launch_bounds__(256) void panel_step(F *__restrict__ P, int64_t ld, int64_t mr,
                                                   int nb, int j, int ncol,
-                                                  const double *__restrict__ part_in,
-                                                  const double *__restrict__ row_in,
-                                                  double *__restrict__ part_out,
-                                                  double *__restrict__ row_out,
-                                                  double *__restrict__ tau, int G) {
-    __shared__ double s_sh[2 * (MAXB + 1)];
-    __shared__ double wc[2 * MAXB];
-    __shared__ double red[4][2 * (MAXB + 1)];
-    __shared__ double sc[6];  // u0inv (re, im), tau, beta (re, im), active
+                                                  const F *__restrict__ part_in,
+                                                  const F *__restrict__ row_in,
+                                                  F *__restrict__ part_out,
+                                                  F *__restrict__ row_out,
+                                                  F *__restrict__ tau, int G) {
+    typedef typename v2t<F>::type CV;
+    __shared__ F s_sh[2 * (MAXB + 1)];
+    __shared__ F wc[2 * MAXB];
+    __shared__ F red[4][2 * (MAXB + 1)];
+    __shared__ F sc[6];  // u0inv (re, im), tau, beta (re, im), active
     const int t = threadIdx.x;
     const int64_t r = (int64_t)blockIdx.x * PQ_ROWS + t;  // panel row of this thread
     const bool have = r < mr;
 
     if (j >= 0) {
-        reduce_partials(part_in, G, nb, s_sh);
+        reduce_partials<F>(part_in, G, nb, s_sh);
         if (t == 0) {
-            const double ar = row_in[2 * j], ai = row_in[2 * j + 1];
-            const double tail2 = s_sh[2 * nb];
-            const double aa = sqrt(ar * ar + ai * ai);
+            const F ar = row_in[2 * j], ai = row_in[2 * j + 1];
+            const F tail2 = s_sh[2 * nb];
+            const F aa = sqrt(ar * ar + ai * ai);
             if (tail2 == 0.0) {
                 sc[0] = 0.0; sc[1] = 0.0; sc[2] = 0.0; sc[3] = ar; sc[4] = ai; sc[5] = 0.0;
             } else {
-                const double xn = sqrt(aa * aa + tail2);
-                double sr = 1.0, si = 0.0;
+                const F xn = sqrt(aa * aa + tail2);
+                F sr = 1.0, si = 0.0;
                 if (aa > 0.0) { sr = ar / aa; si = ai / aa; }
-                const double br = -sr * xn, bi = -si * xn;
+                const F br = -sr * xn, bi = -si * xn;
                 // u0 = alpha - beta = sgn (|alpha| + xn); 1/u0 = conj(sgn) / (|alpha| + xn)
-                const double den = aa + xn;
+                const F den = aa + xn;
                 sc[0] = sr / den;
                 sc[1] = -si / den;
                 sc[2] = den / xn;  // tau
@@ -95,35 +98,35 @@ __global__ __launch_bounds__(256) void panel_step(double *__restrict__ P, int64_
             }
         }
         __syncthreads();
-        const double tj = sc[2];
-        const double ur = sc[0], ui = sc[1];
+        const F tj = sc[2];
+        const F ur = sc[0], ui = sc[1];
         const bool active = sc[5] != 0.0;
         if (blockIdx.x == 0 && t == 0) tau[j] = tj;
         if (active) {
             // w_c = (s_c - conj(beta) P[j,c]) / conj(u0), scaled by tau: tw_c = tau * w_c
-            const double br = sc[3], bi = sc[4];
+            const F br = sc[3], bi = sc[4];
             for (int c = j + 1 + t; c < nb; c += blockDim.x) {
-                const double sr = s_sh[2 * c], si = s_sh[2 * c + 1];
-                const double pr = row_in[2 * c], pi = row_in[2 * c + 1];
+                const F sr = s_sh[2 * c], si = s_sh[2 * c + 1];
+                const F pr = row_in[2 * c], pi = row_in[2 * c + 1];
                 // s - conj(beta) * p
-                const double nr = sr - (br * pr + bi * pi);
-                const double ni = si - (br * pi - bi * pr);
+                const F nr = sr - (br * pr + bi * pi);
+                const F ni = si - (br * pi - bi * pr);
                 // / conj(u0) == * conj(1/u0)   (1/conj(u0) = conj(1/u0))
-                const double cr = ur, ci = -ui;
+                const F cr = ur, ci = -ui;
                 wc[2 * c] = tj * (nr * cr - ni * ci);
                 wc[2 * c + 1] = tj * (nr * ci + ni * cr);
             }
             __syncthreads();
             if (have && r >= j) {
                 // v_r: 1 at r == j, x_r / u0 below
-                double vr, vi;
-                double *pj = P + 2 * (r + (int64_t)j * ld);
+                F vr, vi;
+                F *pj = P + 2 * (r + (int64_t)j * ld);
                 if (r == j) {
                     vr = 1.0; vi = 0.0;
                     pj[0] = sc[3];
                     pj[1] = sc[4];
                 } else {
-                    const double xr = pj[0], xi = pj[1];
+                    const F xr = pj[0], xi = pj[1];
                     vr = xr * ur - xi * ui;
                     vi = xr * ui + xi * ur;
                     pj[0] = vr;
@@ -131,20 +134,20 @@ __global__ __launch_bounds__(256) void panel_step(double *__restrict__ P, int64_
                 }
                 // columns in chunks of 16: all loads of a chunk are issued first
                 for (int c0 = j + 1; c0 < nb; c0 += 16) {
-                    double2 pv[16];
+                    CV pv[16];
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
                         const int c = c0 + q;
-                        pv[q] = (c < nb) ? *(const double2 *)(P + 2 * (r + (int64_t)c * ld))
-                                         : make_double2(0.0, 0.0);
+                        pv[q] = (c < nb) ? *(const CV *)(P + 2 * (r + (int64_t)c * ld))
+                                         : mk2<F>(0.0, 0.0);
                     }
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
                         const int c = c0 + q;
                         if (c >= nb) break;
-                        const double wr = wc[2 * c], wi = wc[2 * c + 1];
-                        *(double2 *)(P + 2 * (r + (int64_t)c * ld)) =
-                            make_double2(pv[q].x - (vr * wr - vi * wi), pv[q].y - (vr * wi + vi * wr));
+                        const F wr = wc[2 * c], wi = wc[2 * c + 1];
+                        *(CV *)(P + 2 * (r + (int64_t)c * ld)) =
+                            mk2<F>(pv[q].x - (vr * wr - vi * wi), pv[q].y - (vr * wi + vi * wr));
                     }
                 }
             }
@@ -157,32 +160,32 @@ __global__ __launch_bounds__(256) void panel_step(double *__restrict__ P, int64_
     const int jn = j + 1;
     if (jn < ncol) {
         // partials for column jn over rows r >= jn
-        double xr = 0.0, xi = 0.0;
+        F xr = 0.0, xi = 0.0;
         const bool in = have && r >= jn;
         if (in) {
-            const double *px = P + 2 * (r + (int64_t)jn * ld);
+            const F *px = P + 2 * (r + (int64_t)jn * ld);
             xr = px[0];
             xi = px[1];
         }
         const int w = t >> 6, l = t & 63;
         // tail2 over r > jn
-        double t2 = (in && r > jn) ? xr * xr + xi * xi : 0.0;
+        F t2 = (in && r > jn) ? xr * xr + xi * xi : 0.0;
         t2 = wave_sum(t2);
         if (l == 0) { red[w][2 * nb] = t2; red[w][2 * nb + 1] = 0.0; }
         for (int c0 = jn + 1; c0 < nb; c0 += 16) {
-            double2 pv[16];
+            CV pv[16];
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int c = c0 + q;
-                pv[q] = (in && c < nb) ? *(const double2 *)(P + 2 * (r + (int64_t)c * ld))
-                                       : make_double2(0.0, 0.0);
+                pv[q] = (in && c < nb) ? *(const CV *)(P + 2 * (r + (int64_t)c * ld))
+                                       : mk2<F>(0.0, 0.0);
             }
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int c = c0 + q;
                 if (c >= nb) break;
                 // conj(x) * p
-                double sr = xr * pv[q].x + xi * pv[q].y, si = xr * pv[q].y - xi * pv[q].x;
+                F sr = xr * pv[q].x + xi * pv[q].y, si = xr * pv[q].y - xi * pv[q].x;
                 sr = wave_sum(sr);
                 si = wave_sum(si);
                 if (l == 0) { red[w][2 * c] = sr; red[w][2 * c + 1] = si; }
@@ -190,7 +193,7 @@ __global__ __launch_bounds__(256) void panel_step(double *__restrict__ P, int64_
         }
         __syncthreads();
         for (int c = t; c <= nb; c += blockDim.x) {
-            double sr = 0.0, si = 0.0;
+            F sr = 0.0, si = 0.0;
             if (c > jn) {
                 for (int q = 0; q < 4; ++q) { sr += red[q][2 * c]; si += red[q][2 * c + 1]; }
             }
@@ -208,13 +211,14 @@ __global__ __launch_bounds__(256) void panel_step(double *__restrict__ P, int64_
 
 // Copy the finished band columns [k, k+nb) into lower band storage AB: the
 // diagonal block (rows < k+b) and R (rows k+b .. k+b+c of column k+c).
-__global__ void panel_band(const double *__restrict__ A, int64_t lda, int64_t n, int64_t k, int b,
-                           double *__restrict__ AB, int64_t ldab) {
+template <typename F>
+__global__ void panel_band(const F *__restrict__ A, int64_t lda, int64_t n, int64_t k, int b,
+                           F *__restrict__ AB, int64_t ldab) {
     const int c = blockIdx.y;
     const int64_t j = k + c;
     for (int64_t d = threadIdx.x; d < ldab; d += blockDim.x) {
         const int64_t i = j + d;
-        double re = 0.0, im = 0.0;
+        F re = 0.0, im = 0.0;
         if (i < n && (i < k + b || i - (k + b) <= c)) {
             re = A[2 * (i + j * lda)];
             im = A[2 * (i + j * lda) + 1];
@@ -226,15 +230,16 @@ __global__ void panel_band(const double *__restrict__ A, int64_t lda, int64_t n,
 
 // Write V explicitly (zeros above, ones on the diagonal) into the panel, into
 // VW[:, 0:nb] and into WV[:, nb:2nb].
-__global__ void panel_explicit_v(double *__restrict__ A, int64_t lda, int64_t k, int b, int nb,
-                                 int64_t mr, double *__restrict__ VW, double *__restrict__ WV,
+template <typename F>
+__global__ void panel_explicit_v(F *__restrict__ A, int64_t lda, int64_t k, int b, int nb,
+                                 int64_t mr, F *__restrict__ VW, F *__restrict__ WV,
                                  int64_t ldw) {
     const int c = blockIdx.y;
     const int64_t j = k + c;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < mr;
          r += (int64_t)gridDim.x * blockDim.x) {
-        double *p = A + 2 * ((k + b + r) + j * lda);
-        double vr, vi;
+        F *p = A + 2 * ((k + b + r) + j * lda);
+        F vr, vi;
         if (r < c) { vr = 0.0; vi = 0.0; }
         else if (r == c) { vr = 1.0; vi = 0.0; }
         else { vr = p[0]; vi = p[1]; }
@@ -248,12 +253,13 @@ __global__ void panel_explicit_v(double *__restrict__ A, int64_t lda, int64_t k,
 }
 
 // Band columns that need no reduction: copy lower band of A.
-__global__ void band_copy_tail(const double *__restrict__ A, int64_t lda, int64_t n, int64_t j0,
-                               double *__restrict__ AB, int64_t ldab) {
+template <typename F>
+__global__ void band_copy_tail(const F *__restrict__ A, int64_t lda, int64_t n, int64_t j0,
+                               F *__restrict__ AB, int64_t ldab) {
     const int64_t j = j0 + blockIdx.y;
     for (int64_t d = threadIdx.x; d < ldab; d += blockDim.x) {
         const int64_t i = j + d;
-        double re = 0.0, im = 0.0;
+        F re = 0.0, im = 0.0;
         if (i < n) {
             re = A[2 * (i + j * lda)];
             im = A[2 * (i + j * lda) + 1];
@@ -265,11 +271,12 @@ __global__ void band_copy_tail(const double *__restrict__ A, int64_t lda, int64_
 
 // T from G = V^H V and tau: T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j,0:j] G[0:j, j].
 // One workgroup; T upper triangular nb x nb (ld nb), zeros below.
-__global__ void tfactor(int nb, const double *__restrict__ G, const double *__restrict__ tau,
-                        double *__restrict__ T) {
-    __shared__ double Ts[2 * MAXB * MAXB];
-    __shared__ double Gs[2 * MAXB * MAXB];
-    __shared__ double taus[MAXB];
+template <typename F>
+__global__ void tfactor(int nb, const F *__restrict__ G, const F *__restrict__ tau,
+                        F *__restrict__ T) {
+    __shared__ F Ts[2 * MAXB * MAXB];
+    __shared__ F Gs[2 * MAXB * MAXB];
+    __shared__ F taus[MAXB];
     const int t = threadIdx.x;
     for (int e = t; e < nb * nb; e += blockDim.x) {
         Ts[2 * e] = 0.0; Ts[2 * e + 1] = 0.0;
@@ -278,12 +285,12 @@ __global__ void tfactor(int nb, const double *__restrict__ G, const double *__re
     for (int e = t; e < nb; e += blockDim.x) taus[e] = tau[e];
     __syncthreads();
     for (int j = 0; j < nb; ++j) {
-        const double tj = taus[j];
+        const F tj = taus[j];
         if (t < j) {
-            double sr = 0.0, si = 0.0;
+            F sr = 0.0, si = 0.0;
             for (int l = t; l < j; ++l) {
-                const double ar = Ts[2 * (t + l * nb)], ai = Ts[2 * (t + l * nb) + 1];
-                const double gr = Gs[2 * (l + j * nb)], gi = Gs[2 * (l + j * nb) + 1];
+                const F ar = Ts[2 * (t + l * nb)], ai = Ts[2 * (t + l * nb) + 1];
+                const F gr = Gs[2 * (l + j * nb)], gi = Gs[2 * (l + j * nb) + 1];
                 sr += ar * gr - ai * gi;
                 si += ar * gi + ai * gr;
             }
@@ -296,7 +303,8 @@ __global__ void tfactor(int nb, const double *__restrict__ G, const double *__re
     for (int e = t; e < nb * nb; e += blockDim.x) { T[2 * e] = Ts[2 * e]; T[2 * e + 1] = Ts[2 * e + 1]; }
 }
 
-__global__ void copy_cols(const double *__restrict__ src, int64_t lds, double *__restrict__ dst,
+template <typename F>
+__global__ void copy_cols(const F *__restrict__ src, int64_t lds, F *__restrict__ dst,
                           int64_t ldd, int64_t rows) {
     const int c = blockIdx.y;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows;
@@ -331,8 +339,9 @@ size_t he2hb_workspace(int64_t n, int b) {
     return w;
 }
 
-int he2hb(int64_t n, double *A, int64_t lda, int b, double *AB, int64_t ldab, double *T1,
-          void *work, hipStream_t s) {
+template <typename F>
+int he2hb_t(int64_t n, F *A, int64_t lda, int b, F *AB, int64_t ldab, F *T1,
+            void *work, hipStream_t s) {
     if (b < 1 || b > MAXB) {
         set_error("he2hb: band %d outside [1, %d]", b, MAXB);
         return BDG_ERR_NOT_IMPLEMENTED;
@@ -345,106 +354,106 @@ int he2hb(int64_t n, double *A, int64_t lda, int b, double *AB, int64_t ldab, do
     auto take = [&](size_t bytes) {
         char *p = wp;
         wp += (bytes + 255) / 256 * 256;
-        return (double *)p;
+        return (F *)p;
     };
     const int64_t ldw = n;
-    double *VW = take(16 * (size_t)n * 2 * b);
-    double *WV = take(16 * (size_t)n * 2 * b);
-    double *Y = take(16 * (size_t)n * b);
-    double *Gm = take(16 * (size_t)b * b);
-    double *Sm = take(16 * (size_t)b * b);
-    double *Mm = take(16 * (size_t)b * b);
-    double *part = take(16 * 64 * (size_t)n * b);
+    F *VW = take(16 * (size_t)n * 2 * b);
+    F *WV = take(16 * (size_t)n * 2 * b);
+    F *Y = take(16 * (size_t)n * b);
+    F *Gm = take(16 * (size_t)b * b);
+    F *Sm = take(16 * (size_t)b * b);
+    F *Mm = take(16 * (size_t)b * b);
+    F *part = take(16 * 64 * (size_t)n * b);
     const int64_t Gmax = n / PQ_ROWS + 2;
-    double *ppart[2], *prow[2];
+    F *ppart[2], *prow[2];
     ppart[0] = take(16 * (size_t)Gmax * (b + 1));
     ppart[1] = take(16 * (size_t)Gmax * (b + 1));
     prow[0] = take(16 * (size_t)b);
     prow[1] = take(16 * (size_t)b);
-    double *tau = take(8 * (size_t)b);
+    F *tau = take(8 * (size_t)b);
 
     int64_t k = 0;
     int p = 0;
     for (; k + b + 1 < n; k += b, ++p) {
         const int nb = b;
         const int64_t mr = n - k - b;
-        double *P = A + 2 * ((k + b) + k * lda);
+        F *P = A + 2 * ((k + b) + k * lda);
         const int ncol = (int)(mr < nb ? mr : nb);
         const int G = (int)((mr + PQ_ROWS - 1) / PQ_ROWS);
         BDG_HIP(hipMemsetAsync(tau, 0, 8 * (size_t)nb, s));
         for (int j = -1; j < ncol; ++j) {
             const int ib = (j + 2) & 1;   // buffer read by step j
             const int ob = (j + 3) & 1;   // buffer written for column j+1
-            hipLaunchKernelGGL(panel_step, dim3(G), dim3(256), 0, s, P, lda, mr, nb, j, ncol,
+            hipLaunchKernelGGL((panel_step<F>), dim3(G), dim3(256), 0, s, P, lda, mr, nb, j, ncol,
                                ppart[ib], prow[ib], ppart[ob], prow[ob], tau, G);
             BDG_CHECK_LAUNCH();
         }
         // band columns, then explicit V (overwrites R in A)
-        hipLaunchKernelGGL(panel_band, dim3(1, nb), dim3(256), 0, s, A, lda, n, k, b, AB, ldab);
+        hipLaunchKernelGGL((panel_band<F>), dim3(1, nb), dim3(256), 0, s, A, lda, n, k, b, AB, ldab);
         BDG_CHECK_LAUNCH();
         {
             int64_t gx = (mr + 255) / 256;
             if (gx > 16) gx = 16;
-            hipLaunchKernelGGL(panel_explicit_v, dim3((unsigned)gx, nb), dim3(256), 0, s, A, lda,
+            hipLaunchKernelGGL((panel_explicit_v<F>), dim3((unsigned)gx, nb), dim3(256), 0, s, A, lda,
                                k, b, nb, mr, VW, WV, ldw);
             BDG_CHECK_LAUNCH();
         }
-        double *T = T1 + 2 * (size_t)p * b * b;
+        F *T = T1 + 2 * (size_t)p * b * b;
         // G = V^H V
         {
             GemmArgs g{nb, nb, mr, 1.0, 0.0, 0.0, 0.0, VW, ldw, VW, ldw, Gm, nb, GEMM_FULL,
                        splitk_for(1, mr), part};
-            BDG_TRY((gemm<double, true>('C', 'N', g, s)));
+            BDG_TRY((gemm<F, true>('C', 'N', g, s)));
         }
-        hipLaunchKernelGGL(tfactor, dim3(1), dim3(256), 0, s, nb, Gm, tau, T);
+        hipLaunchKernelGGL((tfactor<F>), dim3(1), dim3(256), 0, s, nb, Gm, tau, T);
         BDG_CHECK_LAUNCH();
         // Y = A22 V  (A22 Hermitian, lower triangle valid)
-        double *A22 = A + 2 * ((k + b) + (k + b) * lda);
+        F *A22 = A + 2 * ((k + b) + (k + b) * lda);
         {
             const int64_t tiles = (mr + 63) / 64;
             GemmArgs g{mr, nb, mr, 1.0, 0.0, 0.0, 0.0, A22, lda, VW, ldw, Y, ldw, GEMM_HEMM_L,
                        splitk_for(tiles, mr), part};
-            BDG_TRY((gemm<double, true>('N', 'N', g, s)));
+            BDG_TRY((gemm<F, true>('N', 'N', g, s)));
         }
         // X = Y T  -> VW[:, nb:2nb]
-        double *X = VW + 2 * (size_t)nb * ldw;
+        F *X = VW + 2 * (size_t)nb * ldw;
         {
             GemmArgs g{mr, nb, nb, 1.0, 0.0, 0.0, 0.0, Y, ldw, T, nb, X, ldw, GEMM_FULL, 1, nullptr};
-            BDG_TRY((gemm<double, true>('N', 'N', g, s)));
+            BDG_TRY((gemm<F, true>('N', 'N', g, s)));
         }
         // S = V^H X
         {
             GemmArgs g{nb, nb, mr, 1.0, 0.0, 0.0, 0.0, VW, ldw, X, ldw, Sm, nb, GEMM_FULL,
                        splitk_for(1, mr), part};
-            BDG_TRY((gemm<double, true>('C', 'N', g, s)));
+            BDG_TRY((gemm<F, true>('C', 'N', g, s)));
         }
         // M = T^H S
         {
             GemmArgs g{nb, nb, nb, 1.0, 0.0, 0.0, 0.0, T, nb, Sm, nb, Mm, nb, GEMM_FULL, 1, nullptr};
-            BDG_TRY((gemm<double, true>('C', 'N', g, s)));
+            BDG_TRY((gemm<F, true>('C', 'N', g, s)));
         }
         // W = X - 1/2 V M  (in place in X)
         {
             GemmArgs g{mr, nb, nb, -0.5, 0.0, 1.0, 0.0, VW, ldw, Mm, nb, X, ldw, GEMM_FULL, 1, nullptr};
-            BDG_TRY((gemm<double, true>('N', 'N', g, s)));
+            BDG_TRY((gemm<F, true>('N', 'N', g, s)));
         }
         // WV[:, 0:nb] = W
         {
             dim3 grid((unsigned)(((mr + 255) / 256) > 16 ? 16 : (mr + 255) / 256), nb);
-            hipLaunchKernelGGL(copy_cols, grid, dim3(256), 0, s, X, ldw, WV, ldw, mr);
+            hipLaunchKernelGGL((copy_cols<F>), grid, dim3(256), 0, s, X, ldw, WV, ldw, mr);
             BDG_CHECK_LAUNCH();
         }
         // A22 -= [V W] [W V]^H   (lower tiles)
         {
             GemmArgs g{mr, mr, 2 * (int64_t)nb, -1.0, 0.0, 1.0, 0.0, VW, ldw, WV, ldw, A22, lda,
                        GEMM_LOWER, 1, nullptr};
-            BDG_TRY((gemm<double, true>('N', 'C', g, s)));
+            BDG_TRY((gemm<F, true>('N', 'C', g, s)));
         }
     }
     // remaining columns are already inside the band
     if (k < n) {
         dim3 grid(1, (unsigned)(n - k));
-        hipLaunchKernelGGL(band_copy_tail, grid, dim3(256), 0, s, A, lda, n, k, AB, ldab);
+        hipLaunchKernelGGL((band_copy_tail<F>), grid, dim3(256), 0, s, A, lda, n, k, AB, ldab);
         BDG_CHECK_LAUNCH();
     }
     return 0;
@@ -462,27 +471,49 @@ namespace bdg {
 
 // Back-transformation 1: Z <- Q1 Z = Q_0 Q_1 ... Q_last Z, Q_p = I - V_p T_p V_p^H
 // acting on rows k_p + b .. n-1; V_p explicit in A's panel p.
-int bt1(int64_t n, int64_t m, const double *A, int64_t lda, int b, const double *T1, double *Z,
-        int64_t ldz, void *work, hipStream_t s) {
+template <typename F>
+int bt1_t(int64_t n, int64_t m, const F *A, int64_t lda, int b, const F *T1, F *Z,
+          int64_t ldz, void *work, hipStream_t s) {
     const int np = he2hb_panels(n, b);
-    double *W1 = (double *)work;                 // b x m
-    double *W2 = W1 + 2 * (size_t)b * m;         // b x m
+    F *W1 = (F *)work;                 // b x m
+    F *W2 = W1 + 2 * (size_t)b * m;         // b x m
     for (int p = np - 1; p >= 0; --p) {
         const int64_t k = (int64_t)p * b;
         const int64_t mr = n - k - b;
-        const double *V = A + 2 * ((k + b) + k * lda);
-        const double *T = T1 + 2 * (size_t)p * b * b;
-        double *Zs = Z + 2 * (k + b);
+        const F *V = A + 2 * ((k + b) + k * lda);
+        const F *T = T1 + 2 * (size_t)p * b * b;
+        F *Zs = Z + 2 * (k + b);
         GemmArgs g1{b, m, mr, 1.0, 0.0, 0.0, 0.0, V, lda, Zs, ldz, W1, b, GEMM_FULL, 1, nullptr};
-        BDG_TRY((gemm<double, true>('C', 'N', g1, s)));
+        BDG_TRY((gemm<F, true>('C', 'N', g1, s)));
         GemmArgs g2{b, m, b, 1.0, 0.0, 0.0, 0.0, T, b, W1, b, W2, b, GEMM_FULL, 1, nullptr};
-        BDG_TRY((gemm<double, true>('N', 'N', g2, s)));
+        BDG_TRY((gemm<F, true>('N', 'N', g2, s)));
         GemmArgs g3{mr, m, b, -1.0, 0.0, 1.0, 0.0, V, lda, W2, b, Zs, ldz, GEMM_FULL, 1, nullptr};
-        BDG_TRY((gemm<double, true>('N', 'N', g3, s)));
+        BDG_TRY((gemm<F, true>('N', 'N', g3, s)));
     }
     return 0;
 }
 
 size_t bt1_workspace(int64_t m, int b) { return 2 * 16 * (size_t)b * (size_t)m + 256; }
+
+}  // namespace bdg
+
+namespace bdg {
+
+int he2hb(int64_t n, double *A, int64_t lda, int b, double *AB, int64_t ldab, double *T1,
+          void *work, hipStream_t s) {
+    return he2hb_t<double>(n, A, lda, b, AB, ldab, T1, work, s);
+}
+int he2hb(int64_t n, float *A, int64_t lda, int b, float *AB, int64_t ldab, float *T1,
+          void *work, hipStream_t s) {
+    return he2hb_t<float>(n, A, lda, b, AB, ldab, T1, work, s);
+}
+int bt1(int64_t n, int64_t m, const double *A, int64_t lda, int b, const double *T1, double *Z,
+        int64_t ldz, void *work, hipStream_t s) {
+    return bt1_t<double>(n, m, A, lda, b, T1, Z, ldz, work, s);
+}
+int bt1(int64_t n, int64_t m, const float *A, int64_t lda, int b, const float *T1, float *Z,
+        int64_t ldz, void *work, hipStream_t s) {
+    return bt1_t<float>(n, m, A, lda, b, T1, Z, ldz, work, s);
+}
 
 }  // namespace bdg

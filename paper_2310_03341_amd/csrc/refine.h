@@ -1,0 +1,19 @@
+// Refinement and precision-conversion helpers of the mixed-precision solver.
+#pragma once
+#include "common.h"
+
+namespace bdg {
+
+int cast_c64_to_c128(int64_t rows, int64_t cols, const float *src, int64_t lds, double *dst,
+                     int64_t ldd, hipStream_t s);
+int cast_c128_to_c64(int64_t rows, int64_t cols, const double *src, int64_t lds, float *dst,
+                     int64_t ldd, hipStream_t s);
+// columns [0, n/2) <- particle-hole partners (-v^*, u^*) of columns [n/2, n) (reversed)
+int mirror_half(int64_t n, double *X, int64_t ld, hipStream_t s);
+int mirror_half(int64_t n, float *X, int64_t ld, hipStream_t s);
+size_t refine_workspace(int64_t n, int64_t m);
+int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ldx,
+                  const double *lam_all, int64_t i0, int64_t m, double normH, int iters,
+                  double *W, void *work, hipStream_t s, double *eig_shift, double *last_corr);
+
+}  // namespace bdg

@@ -9,11 +9,15 @@ namespace bdg {
 size_t he2hb_workspace(int64_t n, int b);
 int he2hb(int64_t n, double *A, int64_t lda, int b, double *AB, int64_t ldab, double *T1,
           void *work, hipStream_t s);
+int he2hb(int64_t n, float *A, int64_t lda, int b, float *AB, int64_t ldab, float *T1,
+          void *work, hipStream_t s);
 int he2hb_panels(int64_t n, int b);
 
 // Back-transformation 1: Z <- Q1 Z.
 size_t bt1_workspace(int64_t m, int b);
 int bt1(int64_t n, int64_t m, const double *A, int64_t lda, int b, const double *T1, double *Z,
+        int64_t ldz, void *work, hipStream_t s);
+int bt1(int64_t n, int64_t m, const float *A, int64_t lda, int b, const float *T1, float *Z,
         int64_t ldz, void *work, hipStream_t s);
 
 }  // namespace bdg
@@ -25,6 +29,8 @@ int64_t hb2st_nrefl(int64_t n, int b);
 void hb2st_offsets(int64_t n, int b, int64_t *voff_host);
 int hb2st(int64_t n, int b, double *AB, int64_t ldab, double *V2, double *tau2,
           const int64_t *voff_dev, double *d, double *e_cplx, hipStream_t s);
+int hb2st(int64_t n, int b, float *AB, int64_t ldab, float *V2, float *tau2,
+          const int64_t *voff_dev, double *d, double *e_cplx, hipStream_t s);
 
 // Tridiagonal divide and conquer (FP64): eigenvalues ascending, Q (ld n).
 size_t stedc_workspace(int64_t n);
@@ -35,9 +41,13 @@ int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *
 int phases(int64_t n, const double *e_cplx, double *ph, double *e_abs, hipStream_t s);
 int phase_scale(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, double *Z,
                 int64_t ldz, hipStream_t s);
+int phase_scale(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, float *Z,
+                int64_t ldz, hipStream_t s);
 int64_t bt2_nblocks(int64_t n, int b);
 size_t bt2_workspace(int64_t n, int b);
 int bt2(int64_t n, int b, int64_t m, const double *V2, const double *tau2, const int64_t *voff,
         double *Z, int64_t ldz, void *work, hipStream_t s);
+int bt2(int64_t n, int b, int64_t m, const float *V2, const float *tau2, const int64_t *voff,
+        float *Z, int64_t ldz, void *work, hipStream_t s);
 
 }  // namespace bdg

@@ -107,3 +107,32 @@ def test_eigh_rejects_nonfinite(dev):
     with pytest.raises(api.BdgError) as ei:
         api.eigh(A)
     assert ei.value.code == 6
+
+
+# ---------------------------------------------------------------- mixed precision
+MIXED = [
+    ("tiny_2d_16x16", lambda: oracle.assemble_workload(inputs.tiny_2d()), 0),
+    ("tiny_2d_16x16_ph", lambda: oracle.assemble_workload(inputs.tiny_2d()), 1),
+    ("line_3d_6x6x4_ph", lambda: oracle.assemble_workload(inputs.line_3d_small((6, 6, 4))), 1),
+    ("random_130", lambda: inputs.random_hermitian(130, 12), 0),
+]
+
+
+@pytest.mark.parametrize("name,make,ph", MIXED, ids=[c[0] for c in MIXED])
+def test_mixed_refined_matches_oracle(dev, name, make, ph):
+    H = make()
+    ref = oracle.eigh_hqr(H, vectors=False)[0]
+    W, Z, res, gram = _solve(dev, H, precision=1, ph_mirror=ph)
+    width = ref[-1] - ref[0]
+    assert np.abs(W - ref).max() <= EIG_TOL * width
+    assert res <= VEC_TOL and gram <= VEC_TOL, (res, gram)
+
+
+def test_mixed_refined_window(dev):
+    H = oracle.assemble_workload(inputs.tiny_2d())
+    Ec = math.pi ** 2 / 2
+    Wr, _ = oracle.eigh(H, 0.0, Ec)
+    W, Z, res, gram = _solve(dev, H, 0.0, Ec, precision=1, ph_mirror=1)
+    assert W.shape == Wr.shape
+    assert np.abs(W - Wr).max() <= EIG_TOL * (Ec)
+    assert res <= VEC_TOL and gram <= VEC_TOL

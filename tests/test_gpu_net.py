@@ -1,0 +1,98 @@
+"""GPU start-field network (BF16 MFMA) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return need_gpu()
+
+
+def _flat(params):
+    return np.concatenate([p.ravel() for p in params]).astype(np.float32)
+
+
+def _unflat(vec, C):
+    shapes = [(C, 3, 3, 3), (C,), (C, C, 3, 3), (C,), (C, C, 3, 3), (C,), (2, C, 3, 3), (2,)]
+    out, o = [], 0
+    for s in shapes:
+        k = int(np.prod(s))
+        out.append(vec[o:o + k].reshape(s).astype(np.float64))
+        o += k
+    return out
+
+
+def _problem(C, ny, nx, B, seed):
+    from oracle import net
+    rng = np.random.default_rng(seed)
+    params = net.init_params(C, seed=seed)
+    params[-1] = rng.standard_normal(2) * 0.1
+    for i in (1, 3, 5):
+        params[i] = rng.standard_normal(C) * 0.05
+    Vext = rng.uniform(0.0, 2.0, (B, ny * nx))
+    theta = rng.uniform(-np.pi, np.pi, (B, ny * nx))
+    mu = 1.0
+    x0 = np.stack([np.stack([Vext[b] - mu, np.cos(theta[b]), np.sin(theta[b])]).reshape(3, ny, nx)
+                   for b in range(B)])
+    target = rng.standard_normal((B, 2, ny, nx)) * 0.3
+    return params, Vext, theta, mu, x0, target
+
+
+@pytest.mark.parametrize("C,ny,nx,B", [(8, 8, 8, 2), (32, 16, 16, 3), (16, 12, 20, 1)])
+def test_net_forward_matches_oracle(dev, C, ny, nx, B):
+    import torch
+    from oracle import net
+    from paper_2310_03341_amd import api
+    params, Vext, theta, mu, x0, _ = _problem(C, ny, nx, B, seed=C + ny)
+    ref, _ = net.forward(params, x0)
+    sn = api.StartNet(C, ny, nx, B, dev)
+    assert sn.nparams == _flat(params).size
+    sn.params.copy_(torch.from_numpy(_flat(params)))
+    y = sn.forward(torch.from_numpy(Vext).to(dev), torch.from_numpy(theta).to(dev), mu)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().reshape(ref.shape)
+    # BF16 activations and weights: relative error ~1e-2 of the output scale
+    assert np.abs(got - ref).max() <= 3e-2 * max(1.0, np.abs(ref).max())
+
+
+def test_net_gradients_match_oracle(dev):
+    import torch
+    from oracle import net
+    from paper_2310_03341_amd import api
+    C, ny, nx, B = 16, 12, 12, 2
+    params, Vext, theta, mu, x0, target = _problem(C, ny, nx, B, seed=5)
+    loss_ref, grads_ref = net.loss_and_grads(params, x0, target)
+    sn = api.StartNet(C, ny, nx, B, dev)
+    sn.params.copy_(torch.from_numpy(_flat(params)))
+    loss = sn.backward(torch.from_numpy(Vext).to(dev), torch.from_numpy(theta).to(dev), mu,
+                       torch.from_numpy(target.reshape(B, 2, -1).astype(np.float32)).to(dev))
+    torch.cuda.synchronize()
+    assert abs(loss.item() - loss_ref) <= 2e-2 * loss_ref
+    g = _unflat(sn.grads.cpu().numpy(), C)
+    for i, (a, b) in enumerate(zip(g, grads_ref)):
+        scale = np.abs(b).max()
+        assert np.abs(a - b).max() <= 5e-2 * scale + 1e-6, (i, np.abs(a - b).max(), scale)
+
+
+def test_net_training_reduces_loss(dev):
+    import torch
+    from oracle import net
+    from paper_2310_03341_amd import api
+    C, ny, nx, B = 16, 12, 12, 4
+    params, Vext, theta, mu, x0, _ = _problem(C, ny, nx, B, seed=9)
+    # learnable target: a fixed smooth function of the inputs
+    target = np.stack([0.5 * np.tanh(x0[:, 0]), 0.3 * (1 + x0[:, 1])], axis=1)
+    sn = api.StartNet(C, ny, nx, B, dev)
+    sn.params.copy_(torch.from_numpy(_flat(params)))
+    Vd, Td = torch.from_numpy(Vext).to(dev), torch.from_numpy(theta).to(dev)
+    tg = torch.from_numpy(target.reshape(B, 2, -1).astype(np.float32)).to(dev)
+    l0 = sn.backward(Vd, Td, mu, tg).item()
+    for _ in range(300):
+        sn.backward(Vd, Td, mu, tg)
+        sn.adam(3e-3)
+    l1 = sn.backward(Vd, Td, mu, tg).item()
+    assert l1 < 0.2 * l0, (l0, l1)
