@@ -339,12 +339,25 @@ int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
         return BDG_ERR_WORKSPACE;
     }
     BDG_HIP(hipMemcpyAsync(W, W2 + i0, 8 * (size_t)m, hipMemcpyDeviceToDevice, s));
-    BDG_TRY(phase_scale(n, m, Y, i0, ph, Z, ldz, s));
+    // Particle-hole mirror: when the window straddles E = 0 and every negative
+    // eigenvalue's partner n-1-i lies inside it, only the E > 0 columns are
+    // back-transformed and the others are built as (-v^*, u^*).
+    const int64_t h = n / 2;
+    int64_t bt_lo = i0, bt_hi = i1;
+    bool mirror = false;
+    if (opts && opts->ph_mirror && (n % 2 == 0) && i0 < h && i1 > h && n - i0 <= i1) {
+        mirror = true;
+        bt_lo = h;
+    }
+    const int64_t mb = bt_hi - bt_lo;
+    double *Zb = Z + 2 * (bt_lo - i0) * ldz;
+    BDG_TRY(phase_scale(n, mb, Y, bt_lo, ph, Zb, ldz, s));
     tm.mark(5);
     // ---- back-transformation 2 (band <- tridiagonal), then 1 (dense <- band)
-    BDG_TRY(bt2(n, b, m, V2, tau2, voff, Z, ldz, scratch, s));
+    BDG_TRY(bt2(n, b, mb, V2, tau2, voff, Zb, ldz, scratch, s));
     tm.mark(6);
-    BDG_TRY(bt1(n, m, A, lda, b, T1, Z, ldz, scratch, s));
+    BDG_TRY(bt1(n, mb, A, lda, b, T1, Zb, ldz, scratch, s));
+    if (mirror) BDG_TRY(mirror_columns(n, Z, ldz, 0, (n - 1 - i0) - i0, h - i0, s));
     tm.mark(7);
     BDG_HIP(hipStreamSynchronize(s));
     if (report) {

@@ -29,6 +29,7 @@ struct GemmArgs {
     void *part;      // device scratch: splitk * M * N elements (used when splitk > 1)
     const int *acol = nullptr;  // opA='N' only: column k of A is A[:, acol[k]]
     const int *ccol = nullptr;  // column j of C is C[:, ccol[j]]
+    const int *brow = nullptr;  // opB='N' only: row k of B is B[brow[k], :]
 };
 
 // T = double/float, cplx = complex (interleaved) or real elements.

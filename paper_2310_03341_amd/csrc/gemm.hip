@@ -46,7 +46,7 @@ __device__ inline void load_tile(const T *__restrict__ P, int64_t ld, int64_t r0
             int64_t off;
             bool cj = CONJ;
             if (KFAST) {
-                off = gk + gi * ld;
+                off = (kmap ? (int64_t)kmap[gk] : gk) + gi * ld;
             } else if (hemm_diag && gk > gi) {
                 off = gk + gi * ld;  // upper element of a Hermitian tile: conj of lower
                 cj = true;
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs g, int64_t kchunk) {
     // B operand: 'N' -> k-fast (B stored K x N), 'C' -> i-fast (B stored N x K).
     auto loadB = [&](int64_t k0) {
         if (CB) load_tile<T, CPLX, false, true>(B, g.ldb, n0, k0, g.N, kend, rb, false);
-        else load_tile<T, CPLX, true, false>(B, g.ldb, n0, k0, g.N, kend, rb, false);
+        else load_tile<T, CPLX, true, false>(B, g.ldb, n0, k0, g.N, kend, rb, false, g.brow);
     };
     auto storeB = [&](int buf) {
         if (CB) store_tile<T, CPLX, false>(Bs[buf], rb);

@@ -11,6 +11,9 @@ int cast_c128_to_c64(int64_t rows, int64_t cols, const double *src, int64_t lds,
 // columns [0, n/2) <- particle-hole partners (-v^*, u^*) of columns [n/2, n) (reversed)
 int mirror_half(int64_t n, double *X, int64_t ld, hipStream_t s);
 int mirror_half(int64_t n, float *X, int64_t ld, hipStream_t s);
+// columns dst0 + k <- particle-hole partner of column src0 - k (k < count)
+int mirror_columns(int64_t n, double *X, int64_t ld, int64_t dst0, int64_t src0, int64_t count,
+                   hipStream_t s);
 size_t refine_workspace(int64_t n, int64_t m);
 int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ldx,
                   const double *lam_all, int64_t i0, int64_t m, double normH, int iters,

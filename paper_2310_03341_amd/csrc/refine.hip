@@ -57,6 +57,24 @@ __global__ void mirror_cols(int64_t n, int64_t half, T *__restrict__ X, int64_t 
     }
 }
 
+// column dst0 + k <- (-conj(v), conj(u)) of column src0 - k, k < count
+template <typename T>
+__global__ void mirror_map(int64_t n, T *__restrict__ X, int64_t ld, int64_t dst0, int64_t src0) {
+    const int64_t k = blockIdx.y;
+    const int64_t ns = n / 2;
+    const T *src = X + 2 * (src0 - k) * ld;
+    T *dst = X + 2 * (dst0 + k) * ld;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < ns;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        const T ur = src[2 * r], ui = src[2 * r + 1];
+        const T vr = src[2 * (ns + r)], vi = src[2 * (ns + r) + 1];
+        dst[2 * r] = -vr;
+        dst[2 * r + 1] = vi;
+        dst[2 * (ns + r)] = ur;
+        dst[2 * (ns + r) + 1] = -ui;
+    }
+}
+
 // R[i0 + j, j] += 1 ;  window block of R and S made Hermitian; lam_j = s_jj/(1 - r_jj)
 __global__ void window_block(int64_t m, int64_t i0, double *__restrict__ R, double *__restrict__ S,
                              int64_t ld, double *__restrict__ lamW) {
@@ -260,6 +278,15 @@ int mirror_half(int64_t n, float *X, int64_t ld, hipStream_t s) {
     if (half <= 0) return 0;
     hipLaunchKernelGGL((mirror_cols<float>), dim3(gx(half), (unsigned)half), dim3(256), 0, s, n, half, X,
                        ld);
+    BDG_CHECK_LAUNCH();
+    return 0;
+}
+
+int mirror_columns(int64_t n, double *X, int64_t ld, int64_t dst0, int64_t src0, int64_t count,
+                   hipStream_t s) {
+    if (count <= 0) return 0;
+    hipLaunchKernelGGL((mirror_map<double>), dim3(gx(n / 2), (unsigned)count), dim3(256), 0, s, n, X, ld,
+                       dst0, src0);
     BDG_CHECK_LAUNCH();
     return 0;
 }

@@ -153,7 +153,12 @@ struct MergeScratch {
     int *posnd;     // k final positions
     int *posdf;     // K - k
     double *lamnd;  // k
-    int *info;      // [0]=k [1]=ndef [2]=nrot [3]=error flag
+    int *mask;      // K: halves in which a block column is nonzero (1 top, 2 bottom)
+    int *ctop;      // nondeflated columns touching the top half, and their rows in U
+    int *rtop;
+    int *cbot;      // ... touching the bottom half
+    int *rbot;
+    int *info;      // [0]=k [1]=ndef [2]=nrot [3]=error [4]=k_top [5]=k_bot
 };
 
 // z, sorted order and deflation (one workgroup; the scan runs on thread 0)
@@ -166,6 +171,7 @@ __global__ __launch_bounds__(1024) void merge_deflate(int64_t K, int64_t n1, dou
     const double inv_sqrt2 = 0.70710678118654752440;
     // z from last row of Q1 / first row of Q2
     for (int64_t i = t; i < K; i += blockDim.x) {
+        m.mask[i] = (i < n1) ? 1 : 2;
         double zi;
         if (i < n1) zi = Qblk[(n1 - 1) + i * ldq];
         else zi = sgn * Qblk[n1 + i * ldq];
@@ -231,6 +237,9 @@ __global__ __launch_bounds__(1024) void merge_deflate(int64_t K, int64_t n1, dou
             m.z[j] = r;
             m.z[pj] = 0.0;
             m.rotp[nrot] = pj; m.rotq[nrot] = j; m.rotc[nrot] = cc; m.rots[nrot] = ss; ++nrot;
+            const int mk = m.mask[pj] | m.mask[j];
+            m.mask[pj] = mk;
+            m.mask[j] = mk;
             const double newp = Dpj * cc * cc + Dj * ss * ss;
             const double newj = Dpj * ss * ss + Dj * cc * cc;
             add_def(pj, newp);
@@ -243,6 +252,15 @@ __global__ __launch_bounds__(1024) void merge_deflate(int64_t K, int64_t n1, dou
         }
     }
     if (pj >= 0) { m.nd[k] = pj; m.Dnd[k] = Dpj; m.znd[k] = m.z[pj]; ++k; }
+    // columns of each half for the split eigenvector product
+    int kt = 0, kb = 0;
+    for (int i = 0; i < k; ++i) {
+        const int mk = m.mask[m.nd[i]];
+        if (mk & 1) { m.ctop[kt] = m.nd[i]; m.rtop[kt] = i; ++kt; }
+        if (mk & 2) { m.cbot[kb] = m.nd[i]; m.rbot[kb] = i; ++kb; }
+    }
+    m.info[4] = kt;
+    m.info[5] = kb;
     m.info[0] = k;
     m.info[1] = ndef;
     m.info[2] = nrot;
@@ -421,7 +439,7 @@ size_t stedc_workspace(int64_t n) {
     w += 8 * (size_t)n * n;       // second Q buffer
     w += 8 * (size_t)n * n;       // U
     w += 8 * (size_t)n * 4;       // dt, lam a/b, spare
-    w += (size_t)n * (8 * 12 + 4 * 12);  // merge scratch
+    w += (size_t)n * (8 * 12 + 4 * 20);  // merge scratch
     w += 8 * (size_t)n + 4096;    // splits, starts, rho, info
     return w;
 }
@@ -463,6 +481,11 @@ int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *
     ms.posnd = (int *)take(4 * (size_t)n);
     ms.posdf = (int *)take(4 * (size_t)n);
     ms.lamnd = (double *)take(8 * (size_t)n);
+    ms.mask = (int *)take(4 * (size_t)n);
+    ms.ctop = (int *)take(4 * (size_t)n);
+    ms.rtop = (int *)take(4 * (size_t)n);
+    ms.cbot = (int *)take(4 * (size_t)n);
+    ms.rbot = (int *)take(4 * (size_t)n);
     ms.info = (int *)take(64);
     double *rho_d = (double *)take(64);
 
@@ -529,10 +552,10 @@ int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *
             hipLaunchKernelGGL(merge_deflate, dim3(1), dim3(1024), 0, s, K, n1, rho, sg, Qblk, n,
                                Lc + nd.a, ms, rho_d);
             BDG_CHECK_LAUNCH();
-            int info[4];
+            int info[6];
             BDG_HIP(hipMemcpyAsync(info, ms.info, sizeof(info), hipMemcpyDeviceToHost, s));
             BDG_HIP(hipStreamSynchronize(s));
-            const int k = info[0], ndef = info[1], nrot = info[2];
+            const int k = info[0], ndef = info[1], nrot = info[2], ktop = info[4], kbot = info[5];
             if (nrot > 0) {
                 hipLaunchKernelGGL(merge_rotate, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, K,
                                    Qblk, n, ms);
@@ -554,15 +577,23 @@ int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *
                 BDG_CHECK_LAUNCH();
             }
             if (k > 0) {
-                GemmArgs g{K, k, k, 1.0, 0.0, 0.0, 0.0, Qblk, n, U, k, Qnb, n, GEMM_FULL, 1, nullptr};
-                g.acol = ms.nd;
-                g.ccol = ms.posnd;
-                BDG_TRY((gemm<double, false>('N', 'N', g, s)));
+                // top rows use the columns nonzero there, bottom rows likewise
+                GemmArgs gt{n1, k, ktop, 1.0, 0.0, 0.0, 0.0, Qblk, n, U, k, Qnb, n, GEMM_FULL, 1, nullptr};
+                gt.acol = ms.ctop;
+                gt.brow = ms.rtop;
+                gt.ccol = ms.posnd;
+                BDG_TRY((gemm<double, false>('N', 'N', gt, s)));
+                GemmArgs gb{K - n1, k, kbot, 1.0, 0.0, 0.0, 0.0, Qblk + n1, n, U, k, Qnb + n1, n, GEMM_FULL, 1,
+                            nullptr};
+                gb.acol = ms.cbot;
+                gb.brow = ms.rbot;
+                gb.ccol = ms.posnd;
+                BDG_TRY((gemm<double, false>('N', 'N', gb, s)));
             }
         }
     }
     BDG_HIP(hipMemcpyAsync(lam_out, Lbuf[depth % 2], 8 * (size_t)n, hipMemcpyDeviceToDevice, s));
-    int info[4];
+    int info[6];
     BDG_HIP(hipMemcpyAsync(info, ms.info, sizeof(info), hipMemcpyDeviceToHost, s));
     BDG_HIP(hipStreamSynchronize(s));
     if (info[3]) {

@@ -1,0 +1,167 @@
+"""SLDA self-consistency with a uniform or a learned start (all steps on the GPU).
+
+The static SLDA state is found "iteratively via a sequence of
+diagonalizations" (paper sec. "Performance of the Matrix Diagonalization
+Algorithm"); each step here is one bdg_scf_step call (assembly, windowed
+eigensolve, T = 0 densities, update with the pairing phase held fixed,
+mixing).  The learned start replaces the uniform initial fields by the
+prediction of the start-field network, trained with the library's own
+kernels on converged fields produced by the same iteration.
+
+CLI: python -m paper_2310_03341_amd.learned_start --dims 32 32 --train 64 --test 16
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+from typing import List
+
+import numpy as np
+import torch
+
+from . import api, inputs
+
+UNIFORM_DELTA = 0.3
+
+
+def uniform_start(inst: inputs.ScfInstance, dev):
+    U = torch.from_numpy(inst.Vext.copy()).to(dev)
+    D = torch.full((inst.Vext.size,), UNIFORM_DELTA, dtype=torch.float64, device=dev)
+    return U, D
+
+
+def run_scf(stepper: api.ScfStepper, U, D, p: inputs.ScfParams, max_iter=None):
+    """Iterate until the change is below p.tol; returns (iterations, converged, history)."""
+    hist = []
+    max_iter = max_iter or p.max_iter
+    for it in range(1, max_iter + 1):
+        change, m = stepper.step(U, D)
+        hist.append(change)
+        if not math.isfinite(change):
+            return it, False, hist
+        if change <= p.tol:
+            return it, True, hist
+    return max_iter, False, hist
+
+
+def solve_instance(inst, p, dev, U=None, D=None):
+    st = api.ScfStepper(inst.dims, torch.from_numpy(inst.Vext).to(dev),
+                        torch.from_numpy(inst.theta).to(dev), inst.mu, p)
+    if U is None:
+        U, D = uniform_start(inst, dev)
+    iters, ok, hist = run_scf(st, U, D, p)
+    return iters, ok, U, D
+
+
+def generate(indices: List[int], dims, p, dev, log=None):
+    """Converged fields of the SCF instances (uniform start)."""
+    out = []
+    for i in indices:
+        inst = inputs.scf_instance(i, dims=dims)
+        t0 = time.time()
+        iters, ok, U, D = solve_instance(inst, p, dev)
+        out.append({"index": i, "inst": inst, "iters": iters, "ok": ok,
+                    "U": U.cpu().numpy(), "D": D.cpu().numpy()})
+        if log:
+            log("instance %d: %d iterations (%s) %.1f s" % (i, iters, "ok" if ok else "not converged",
+                                                          time.time() - t0))
+    return out
+
+
+def _batch(data, idx, dev):
+    Vext = torch.from_numpy(np.stack([data[i]["inst"].Vext for i in idx])).to(dev)
+    theta = torch.from_numpy(np.stack([data[i]["inst"].theta for i in idx])).to(dev)
+    tgt = np.stack([np.stack([data[i]["U"] - data[i]["inst"].Vext, data[i]["D"]]) for i in idx])
+    return Vext, theta, torch.from_numpy(tgt.astype(np.float32)).to(dev)
+
+
+def train(data, dims, dev, channels=32, batch=8, steps=2000, lr=2e-3, seed=0, log=None):
+    """Train the start-field network on converged fields; returns the StartNet."""
+    from math import sqrt
+    Nx, Ny = dims
+    net = api.StartNet(channels, Ny, Nx, batch, dev)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    # He initialisation of the flat parameter vector (weights), zero biases
+    shapes = [(channels, 3), (channels, channels), (channels, channels), (2, channels)]
+    vec = []
+    for (o, c) in shapes:
+        vec.append(rng.standard_normal(o * c * 9) * sqrt(2.0 / (9 * c)))
+        vec.append(np.zeros(o))
+    vec[-2] *= 0.1
+    net.params.copy_(torch.from_numpy(np.concatenate(vec).astype(np.float32)))
+    mu = data[0]["inst"].mu
+    n = len(data)
+    for step in range(steps):
+        idx = rng.choice(n, size=batch, replace=n < batch)
+        Vext, theta, tgt = _batch(data, idx, dev)
+        loss = net.backward(Vext, theta, mu, tgt)
+        net.adam(lr * (0.1 if step > 0.75 * steps else 1.0))
+        if log and (step % 500 == 0 or step == steps - 1):
+            log("step %d loss %.3e" % (step, loss.item()))
+    return net
+
+
+def predict_start(net: api.StartNet, inst, dev):
+    B = net.shape.batch
+    Vext = torch.from_numpy(np.stack([inst.Vext] * B)).to(dev)
+    theta = torch.from_numpy(np.stack([inst.theta] * B)).to(dev)
+    y = net.forward(Vext, theta, inst.mu)[0].double()
+    U = torch.from_numpy(inst.Vext).to(dev) + y[0]
+    D = torch.clamp(y[1], min=0.0).contiguous()
+    return U.contiguous(), D
+
+
+def evaluate(net, test, p, dev, log=None):
+    """SCF iterations from uniform vs learned start and the converged-field difference."""
+    rows = []
+    for d in test:
+        inst = d["inst"]
+        U, D = predict_start(net, inst, dev)
+        it_l, ok_l, Ul, Dl = solve_instance(inst, p, dev, U, D)
+        if not ok_l:  # fallback: the uniform start
+            it_l2, ok_l, Ul, Dl = solve_instance(inst, p, dev)
+            it_l += it_l2
+        du = float(np.sqrt(np.mean((Ul.cpu().numpy() - d["U"]) ** 2)))
+        dd = float(np.sqrt(np.mean((Dl.cpu().numpy() - d["D"]) ** 2)))
+        rows.append({"index": d["index"], "iters_uniform": d["iters"], "iters_learned": it_l,
+                     "converged": ok_l, "l2_dU": du, "l2_dDelta": dd})
+        if log:
+            log("test %d: uniform %d, learned %d iterations" % (d["index"], d["iters"], it_l))
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--dims", type=int, nargs=2, default=[32, 32])
+    ap.add_argument("--train", type=int, default=64)
+    ap.add_argument("--test", type=int, default=16)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--channels", type=int, default=32)
+    ap.add_argument("--out", type=str, default="")
+    args = ap.parse_args()
+    dev = torch.device("cuda:0")
+    p = inputs.ScfParams()
+    dims = tuple(args.dims)
+    log = lambda s: print(s, flush=True)  # noqa: E731
+    t0 = time.time()
+    train_set = generate(list(range(args.train)), dims, p, dev, log)
+    test_set = generate(list(range(10000, 10000 + args.test)), dims, p, dev, log)
+    t1 = time.time()
+    net = train(train_set, dims, dev, channels=args.channels, steps=args.steps, log=log)
+    t2 = time.time()
+    rows = evaluate(net, test_set, p, dev, log)
+    iu = np.mean([r["iters_uniform"] for r in rows])
+    il = np.mean([r["iters_learned"] for r in rows])
+    res = {"dims": list(dims), "train": args.train, "test": args.test,
+           "mean_iters_uniform": iu, "mean_iters_learned": il,
+           "max_l2_dU": max(r["l2_dU"] for r in rows), "max_l2_dDelta": max(r["l2_dDelta"] for r in rows),
+           "gen_s": t1 - t0, "train_s": t2 - t1, "rows": rows}
+    print(json.dumps({k: v for k, v in res.items() if k != "rows"}))
+    if args.out:
+        json.dump(res, open(args.out, "w"), indent=1)
+
+
+if __name__ == "__main__":
+    main()

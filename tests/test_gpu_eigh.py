@@ -136,3 +136,16 @@ def test_mixed_refined_window(dev):
     assert W.shape == Wr.shape
     assert np.abs(W - Wr).max() <= EIG_TOL * (Ec)
     assert res <= VEC_TOL and gram <= VEC_TOL
+
+
+@pytest.mark.parametrize("window", ["full", "symmetric"])
+def test_eigh_ph_mirror_fp64(dev, window):
+    w = inputs.line_3d_small((6, 6, 4))
+    H = oracle.assemble_workload(w)
+    ref = oracle.eigh_hqr(H, vectors=False)[0]
+    lo, hi = (-math.inf, math.inf) if window == "full" else (-3.0, 3.0)
+    sel = (ref >= lo) & (ref <= hi)
+    W, Z, res, gram = _solve(dev, H, lo, hi, ph_mirror=1)
+    assert W.shape == ref[sel].shape
+    assert np.abs(W - ref[sel]).max() <= EIG_TOL * (ref[-1] - ref[0])
+    assert res <= VEC_TOL and gram <= VEC_TOL, (res, gram)

@@ -1,0 +1,36 @@
+"""The learned SCF start (network trained by the library's own kernels on
+converged SCF fields) against the uniform start, on small lattices.
+
+The fixed point does not depend on the start, so both starts must converge to
+the same fields; the learned start should need fewer diagonalisations.
+"""
+import numpy as np
+import pytest
+
+from paper_2310_03341_amd import inputs
+from tests.gpu_util import need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return need_gpu()
+
+
+def test_learned_start_converges_to_same_fields_in_fewer_iterations(dev):
+    from paper_2310_03341_amd import learned_start as ls
+    dims = (12, 12)
+    p = inputs.ScfParams(tol=1e-6)
+    train = ls.generate(list(range(16)), dims, p, dev)
+    test = ls.generate(list(range(10000, 10004)), dims, p, dev)
+    assert all(d["ok"] for d in train + test)
+    net = ls.train(train, dims, dev, channels=16, batch=8, steps=600, lr=3e-3)
+    rows = ls.evaluate(net, test, p, dev)
+    assert all(r["converged"] for r in rows)
+    # same fixed point from either start
+    assert max(r["l2_dU"] for r in rows) < 1e-5
+    assert max(r["l2_dDelta"] for r in rows) < 1e-5
+    iu = np.mean([r["iters_uniform"] for r in rows])
+    il = np.mean([r["iters_learned"] for r in rows])
+    assert il < iu, (il, iu)
