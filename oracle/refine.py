@@ -18,6 +18,16 @@ Indust. Appl. Math. 35 (2018), written for complex Hermitian H:
 (the complex case follows from E + E^H = R and S + E^H Lam + Lam E = Lam, as in
 the real case).  The window variant refines only the columns W of X against
 the full basis X: R[:, W] = I[:, W] - X^H X_W, S[:, W] = X^H (H X_W).
+
+Clusters (Ogita & Aishima, part II: clustered eigenvalues, Japan J. Indust.
+Appl. Math. 36 (2019)).  The r_ij / 2 branch only re-orthonormalises a group
+of eigenvalues closer than delta; it never resolves the mixing inside the
+group, so delta (which contains that mixing through ||S - diag||) would stay
+put.  Each cluster (a maximal chain of sorted eigenvalues with consecutive
+gaps <= delta) therefore also gets a Rayleigh-Ritz step in FP64: with
+L = I + R_JJ / 2 (first-order Loewdin orthonormalisation of the cluster
+columns), M = L S_JJ L, M = Q diag(mu) Q^H, the cluster columns become
+X (I + E)[:, J] Q and their eigenvalues mu.
 """
 from __future__ import annotations
 
@@ -28,7 +38,30 @@ def _herm(M):
     return 0.5 * (M + M.conj().T)
 
 
-def oa_step(H: np.ndarray, X: np.ndarray, normH: float | None = None):
+def clusters(lam: np.ndarray, delta: float):
+    """Index arrays of the chains (>= 2 members) of sorted lam with gaps <= delta,
+    each in ascending order of lam."""
+    order = np.argsort(lam, kind="stable")
+    out, start = [], 0
+    for k in range(1, order.size + 1):
+        if k == order.size or lam[order[k]] - lam[order[k - 1]] > delta:
+            if k - start >= 2:
+                out.append(order[start:k])
+            start = k
+    return out
+
+
+def _cluster_rr(E, I_W, Rw, Sw, lam_W, delta):
+    """Rayleigh-Ritz inside each cluster: E[:, J] <- (I_W + E)[:, J] Q - I_W[:, J]."""
+    for J in clusters(lam_W, delta):
+        L = np.eye(J.size) + Rw[np.ix_(J, J)] / 2.0
+        M = _herm(L @ Sw[np.ix_(J, J)] @ L)
+        mu, Q = np.linalg.eigh(M)
+        E[:, J] = (I_W[:, J] + E[:, J]) @ Q - I_W[:, J]
+        lam_W[J] = mu
+
+
+def oa_step(H: np.ndarray, X: np.ndarray, normH: float | None = None, cluster_rr: bool = True):
     """One full Ogita-Aishima step on all columns; returns (X_new, lam)."""
     n = X.shape[1]
     R = _herm(np.eye(n) - X.conj().T @ X)
@@ -41,10 +74,13 @@ def oa_step(H: np.ndarray, X: np.ndarray, normH: float | None = None):
     num = S + lam[None, :] * R
     with np.errstate(divide="ignore", invalid="ignore"):
         E = np.where(np.abs(diff) > delta, num / diff, R / 2.0)
+    if cluster_rr:
+        _cluster_rr(E, np.eye(n), R, S, lam, delta)
     return X + X @ E, lam
 
 
-def oa_step_window(H: np.ndarray, X: np.ndarray, lam0: np.ndarray, cols: np.ndarray, normH: float):
+def oa_step_window(H: np.ndarray, X: np.ndarray, lam0: np.ndarray, cols: np.ndarray, normH: float,
+                   cluster_rr: bool = True):
     """Refine columns `cols` of the full basis X; returns (X_W_new, lam_W).
 
     lam0 are the approximate eigenvalues that came with X; outside the window
@@ -69,6 +105,9 @@ def oa_step_window(H: np.ndarray, X: np.ndarray, lam0: np.ndarray, cols: np.ndar
     num = S + lam_W[None, :] * R
     with np.errstate(divide="ignore", invalid="ignore"):
         E = np.where(np.abs(diff) > delta, num / diff, R / 2.0)
+    if cluster_rr:
+        # clusters are formed inside the window only
+        _cluster_rr(E, I_W, Rw, Sw, lam_W, delta)
     return XW + X @ E, lam_W
 
 

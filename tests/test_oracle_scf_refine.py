@@ -98,3 +98,66 @@ def test_ph_mirror_is_eigenvector_of_minus_E(orc):
     pos = W > 0
     M = refine.ph_mirror(Z[:, pos])
     assert np.abs(H @ M + M * W[pos]).max() < 1e-12
+
+
+def _clustered_problem(n=60, seed=5):
+    """H = Q diag(w) Q^H with a pair 1e-6 apart and an exact triple; X0 mixes
+    both groups inside themselves and carries a 1e-6 perturbation."""
+    rng = np.random.default_rng(seed)
+    w = np.sort(rng.uniform(-5.0, 5.0, n))
+    w[20], w[21] = 1.0, 1.0 + 1e-6
+    w[40] = w[41] = w[42] = 2.5
+    w = np.sort(w)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    H = (Q * w) @ Q.conj().T
+    H = 0.5 * (H + H.conj().T)
+    G = np.eye(n, dtype=complex)
+    p = int(np.searchsorted(w, 1.0))
+    c, s = math.cos(math.pi / 6), math.sin(math.pi / 6)
+    G[p:p + 2, p:p + 2] = [[c, -s], [s, c]]
+    t = int(np.searchsorted(w, 2.5))
+    U3, _ = np.linalg.qr(rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3)))
+    G[t:t + 3, t:t + 3] = U3
+    X0 = (Q @ G) @ (np.eye(n) + 1e-6 * rng.standard_normal((n, n)))
+    lam0 = np.real(np.einsum("ij,ij->j", X0.conj(), H @ X0))
+    return H, w, X0, lam0, p
+
+
+@pytest.mark.parametrize("window", [False, True])
+def test_refinement_cluster_rayleigh_ritz(window):
+    """A pair closer than delta, mixed by 30 degrees, converges only through the
+    in-cluster Rayleigh-Ritz step; without it the pair error stalls at
+    sin^2(30 deg) * gap."""
+    from oracle import refine
+    H, w, X0, lam0, p = _clustered_problem()
+    normH = np.abs(w).max()
+    cols = np.arange(10, H.shape[0])
+
+    def run(rr):
+        X, lam = X0.copy(), lam0.copy()
+        for _ in range(3):
+            if window:
+                XW, lW = refine.oa_step_window(H, X, lam0, cols, normH, cluster_rr=rr)
+                X[:, cols] = XW
+                lam = lam.copy()
+                lam[cols] = lW
+            else:
+                X, lam = refine.oa_step(H, X, normH, cluster_rr=rr)
+        sel = cols if window else np.arange(H.shape[0])
+        return lam[sel], X[:, sel], w[sel]
+
+    lam, X, ref = run(True)
+    res, gram = refine.accuracy(H, lam, X)
+    assert np.abs(lam - ref).max() < 1e-14 * normH
+    assert res < 1e-14 and gram < 1e-14
+    lam_nc, _, _ = run(False)
+    assert np.abs(lam_nc - ref).max() > 1e-8
+
+
+def test_cluster_chains():
+    from oracle import refine
+    lam = np.array([0.0, 3.0, 1.0, 1.05, 1.1, 5.0, 5.2])
+    cl = refine.clusters(lam, 0.06)
+    assert [list(c) for c in cl] == [[2, 3, 4]]
+    assert [list(c) for c in refine.clusters(lam, 0.3)] == [[2, 3, 4], [5, 6]]
+    assert refine.clusters(lam, 0.01) == []
