@@ -80,6 +80,9 @@ def main():
     ap.add_argument("--dims", type=int, nargs="+", default=[24, 24, 24])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--check", action="store_true", help="FP64 residual/Gram check of the last step")
+    ap.add_argument("--no-ph-mirror", action="store_true",
+                    help="back-transform every eigenvector instead of the E > 0 half + mirror")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refinement arm")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver is single-GPU; run with --gpus 1",
@@ -100,7 +103,8 @@ def main():
     U = torch.from_numpy(w.U).to(dev)
     D = torch.from_numpy(w.Delta).to(dev)
     H = api.colmajor(n, n, torch.complex128, dev)
-    opts = api.make_opts()
+    ph = 0 if args.no_ph_mirror else 1
+    opts = api.make_opts(ph_mirror=ph)
     solver = api.Solver(n, opts, dev)
     W = torch.empty(n, dtype=torch.float64, device=dev)
     Z = api.colmajor(n, n, torch.complex128, dev)
@@ -114,11 +118,13 @@ def main():
     torch.cuda.synchronize()
     stage = [0.0] * 8
     t_eigh = []
+    t_bt2 = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         Wk, Zk = step()
         rep = solver.report
         t_eigh.append(rep.stage_ms[7] / 1e3)
+        t_bt2.append(rep.bt2_kernel_ms / 1e3)
         for i in range(8):
             stage[i] += rep.stage_ms[i] / args.steps
     torch.cuda.synchronize()
@@ -126,7 +132,11 @@ def main():
     m = Wk.numel()
     ms_step = 1e3 * wall / args.steps
     t_solve = sum(t_eigh) / len(t_eigh)
-    F = flops_two_stage(n, m)
+    m_bt = m // 2 if ph else m  # back-transformed columns (the rest are particle-hole partners)
+    F = flops_two_stage(n, m_bt)
+    # dominant kernel: the back-transformation-2 apply kernel (one launch per solve)
+    t_k = sum(t_bt2) / len(t_bt2)
+    f_k = 8.0 * n * n * m_bt
     out = {
         "metric": "BdG eigh time (s) + FP64-matrix TFLOP/s at n=27648; mixed+refined vs FP64",
         "value": round(t_solve, 4),
@@ -142,11 +152,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "BdG %s lattice, vortex line, 32 Gaussians, mu=0.8; n=%d, all %d "
                                "eigenpairs, FP64 two-stage" % ("x".join(map(str, dims)), n, m),
-                   "n": n, "m": m, "seed": 2000},
+                   "n": n, "m": m, "seed": 2000, "ph_mirror": bool(ph),
+                   "flop_model": "(16/3+4/3) n^3 + 16 n^2 m_bt, m_bt = %d back-transformed columns" % m_bt},
         "tflops": round(F / t_solve / 1e12, 3),
         "frac_fp64_peak": round(F / t_solve / PEAK_FP64_MFMA, 4),
         "stage_ms": {k: round(v, 2) for k, v in zip(
             ["he2hb", "hb2st", "stedc", "bt2", "bt1", "refine", "select", "total"], stage)},
+        "roofline": {"kernel": "bt2_apply", "bound": "mfma", "achieved": round(f_k / t_k / 1e12, 3),
+                     "peak": 78.6, "unit": "TFLOP/s", "frac": round(f_k / t_k / PEAK_FP64_MFMA, 4),
+                     "traffic": None, "flops_per_launch": f_k, "ms_per_launch": round(1e3 * t_k, 2)},
     }
     if args.check:
         H2 = api.assemble(w.dims, U, D, w.mu)
@@ -154,6 +168,33 @@ def main():
         out["max_resid"] = res
         out["gram_defect"] = gram
         del H2
+    if not args.no_mixed:
+        # the precision arm on the same matrix: FP32 reduction + FP64 refinement
+        W64 = Wk.clone()
+        del solver
+        torch.cuda.empty_cache()
+        mopts = api.make_opts(precision=api.BDG_FP32_REFINED, ph_mirror=ph)
+        msolver = api.Solver(n, mopts, dev)
+        api.assemble(w.dims, U, D, w.mu, out=H)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Wm, Zm = msolver(H, -math.inf, math.inf, W, Z)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0
+        rep = msolver.report
+        mixed = {"time_s": round(rep.stage_ms[7] / 1e3, 4), "wall_s": round(tm, 3),
+                 "refine_iters": rep.refine_iters,
+                 "stage_ms": {k: round(v, 2) for k, v in zip(
+                     ["he2hb32", "hb2st32", "stedc", "bt2_32", "bt1_32", "refine64", "select", "total"],
+                     list(rep.stage_ms))}}
+        if args.check:
+            res, gram = api.check(api.assemble(w.dims, U, D, w.mu), Wm, Zm)
+            mixed["max_resid"] = res
+            mixed["gram_defect"] = gram
+        if Wm.numel() == W64.numel():
+            mixed["max_eig_diff_vs_fp64"] = float((Wm - W64).abs().max())
+        out["mixed_refined"] = mixed
+        del msolver
     if not args.no_cpu:
         dt, n_s, cores, sdims = cpu_baseline()
         scale = (n / n_s) ** 3

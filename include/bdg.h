@@ -68,8 +68,13 @@ typedef struct {
 typedef struct {
     int32_t precision;       /* BDG_FP64 or BDG_FP32_REFINED                     */
     int32_t band;            /* half-bandwidth of stage 1 (0 = default 64)      */
-    int32_t refine_max_iter; /* refinement sweeps for BDG_FP32_REFINED (0 = 3)  */
-    double refine_tol;       /* residual target, relative to ||H||_2 (0=1e-13)  */
+    int32_t refine_max_iter; /* refinement steps for BDG_FP32_REFINED (0 = 3;
+                                < 0 = none: the FP32 result widened to FP64)    */
+    double refine_tol;       /* stop once the step's defect (max |r_ij| and
+                                |s_ij + lam_j r_ij| / ||H||_2 off the diagonal,
+                                in-cluster coupling / ||H||_2) is below this
+                                (0 = 1e-14); BDG_ERR_REFINE_TOL when the last
+                                defect still exceeds sqrt(refine_tol)           */
     int32_t dc_leaf;         /* divide-and-conquer leaf size (0 = default 32)   */
     int32_t ph_mirror;       /* 1: back-transform only E >= 0 vectors and build
                                 the E < 0 ones as (-v^*, u^*) (particle-hole
@@ -79,12 +84,17 @@ typedef struct {
 
 /* Per-call accuracy and timing report (filled when non-NULL). */
 typedef struct {
-    double max_resid;     /* max_j ||H z_j - w_j z_j||_2 / max|w| (when checked) */
+    double max_resid;     /* mixed arm: defect measured by the last refinement
+                             step (see refine_tol)                                */
     double gram_defect;   /* max_ij |(Z^H Z - I)_ij|              (when checked) */
     double eig_shift_max; /* largest eigenvalue change made by refinement        */
     int32_t refine_iters; /* refinement sweeps performed                         */
     int32_t pad;
     double stage_ms[8];   /* he2hb, hb2st, stedc, bt2, bt1, refine, select, total */
+    double bt2_kernel_ms; /* duration of the back-transformation-2 apply kernel     */
+    double refine_delta0; /* mixed arm: cluster threshold delta of the first step  */
+    int32_t refine_cluster_cols; /* mixed arm: columns in clusters at the last step */
+    int32_t pad2;
 } bdg_err_report;
 
 /*

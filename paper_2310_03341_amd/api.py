@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import warnings
 import os
 from typing import Optional, Sequence
 
@@ -45,7 +46,9 @@ class Opts(ctypes.Structure):
 class Report(ctypes.Structure):
     _fields_ = [("max_resid", ctypes.c_double), ("gram_defect", ctypes.c_double),
                 ("eig_shift_max", ctypes.c_double), ("refine_iters", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("stage_ms", ctypes.c_double * 8)]
+                ("pad", ctypes.c_int32), ("stage_ms", ctypes.c_double * 8),
+                ("bt2_kernel_ms", ctypes.c_double), ("refine_delta0", ctypes.c_double),
+                ("refine_cluster_cols", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
 
 def lib():
@@ -74,9 +77,14 @@ def lib():
     return _lib
 
 
-def _call(name: str, *args) -> int:
+BDG_ERR_REFINE_TOL = 2
+
+
+def _call(name: str, *args, warn_codes=()) -> int:
     rc = getattr(lib(), name)(*args)
-    if rc != 0:
+    if rc in warn_codes:
+        warnings.warn("%s: %s" % (name, lib().bdg_last_error().decode()), RuntimeWarning, stacklevel=3)
+    elif rc != 0:
         raise BdgError(name, rc, lib().bdg_last_error().decode())
     return rc
 
@@ -161,7 +169,8 @@ class Solver:
         m = ctypes.c_int64(0)
         _call("bdg_eigh", n, _dev(A), _ld(A), float(emin), float(emax), _dev(W), _dev(Z),
               _ld(Z), Z.shape[1], ctypes.byref(m), ctypes.byref(self.opts), _dev(self.work),
-              self.bytes, ctypes.byref(self.report), _stream(A.device))
+              self.bytes, ctypes.byref(self.report), _stream(A.device),
+              warn_codes=(BDG_ERR_REFINE_TOL,))
         k = int(m.value)
         return W[:k], Z[:, :k]
 

@@ -304,21 +304,39 @@ int phase_scale_t(int64_t n, int64_t m, const double *Y, int64_t i0, const doubl
 }
 
 template <typename F>
-int bt2_t(int64_t n, int b, int64_t m, const F *V2, const F *tau2, const int64_t *voff, F *Z,
-          int64_t ldz, void *work, hipStream_t s) {
+int bt2_prepare_t(int64_t n, int b, const F *V2, const F *tau2, const int64_t *voff, void *work,
+                  hipStream_t s) {
+    if (n < 3) return 0;
+    if (b > BMAX) return BDG_ERR_NOT_IMPLEMENTED;
+    const int64_t nsw = n - 2;
+    const int64_t nsb = (nsw + NBK - 1) / NBK;
+    const int64_t tmax = (n - 2) / b + 1;
+    hipLaunchKernelGGL((bt2_tfactors<F>), dim3((unsigned)(nsb * tmax)), dim3(256), 0, s, n, b, V2, tau2,
+                       voff, nsb, tmax, (F *)work);
+    BDG_CHECK_LAUNCH();
+    return 0;
+}
+
+template <typename F>
+int bt2_apply_t(int64_t n, int b, int64_t m, const F *V2, const int64_t *voff, F *Z, int64_t ldz,
+                void *work, hipStream_t s) {
     if (n < 3 || m <= 0) return 0;
     if (b > BMAX) return BDG_ERR_NOT_IMPLEMENTED;
     const int64_t nsw = n - 2;
     const int64_t nsb = (nsw + NBK - 1) / NBK;
     const int64_t tmax = (n - 2) / b + 1;
-    F *TF = (F *)work;
-    hipLaunchKernelGGL((bt2_tfactors<F>), dim3((unsigned)(nsb * tmax)), dim3(256), 0, s, n, b, V2, tau2, voff,
-                       nsb, tmax, TF);
-    BDG_CHECK_LAUNCH();
-    hipLaunchKernelGGL((bt2_apply<F>), dim3((unsigned)((m + SLAB - 1) / SLAB)), dim3(256), 0, s, n, b, m, V2,
-                       voff, nsb, tmax, TF, Z, ldz);
+    hipLaunchKernelGGL((bt2_apply<F>), dim3((unsigned)((m + SLAB - 1) / SLAB)), dim3(256), 0, s, n, b, m,
+                       V2, voff, nsb, tmax, (const F *)work, Z, ldz);
     BDG_CHECK_LAUNCH();
     return 0;
+}
+
+template <typename F>
+int bt2_t(int64_t n, int b, int64_t m, const F *V2, const F *tau2, const int64_t *voff, F *Z,
+          int64_t ldz, void *work, hipStream_t s) {
+    if (n < 3 || m <= 0) return 0;
+    BDG_TRY(bt2_prepare_t<F>(n, b, V2, tau2, voff, work, s));
+    return bt2_apply_t<F>(n, b, m, V2, voff, Z, ldz, work, s);
 }
 
 }  // namespace bdg
@@ -340,6 +358,27 @@ int bt2(int64_t n, int b, int64_t m, const double *V2, const double *tau2, const
 int bt2(int64_t n, int b, int64_t m, const float *V2, const float *tau2, const int64_t *voff,
         float *Z, int64_t ldz, void *work, hipStream_t s) {
     return bt2_t<float>(n, b, m, V2, tau2, voff, Z, ldz, work, s);
+}
+
+}  // namespace bdg
+
+namespace bdg {
+
+int bt2_prepare(int64_t n, int b, const double *V2, const double *tau2, const int64_t *voff,
+                void *work, hipStream_t s) {
+    return bt2_prepare_t<double>(n, b, V2, tau2, voff, work, s);
+}
+int bt2_prepare(int64_t n, int b, const float *V2, const float *tau2, const int64_t *voff,
+                void *work, hipStream_t s) {
+    return bt2_prepare_t<float>(n, b, V2, tau2, voff, work, s);
+}
+int bt2_apply_blocks(int64_t n, int b, int64_t m, const double *V2, const int64_t *voff, double *Z,
+                     int64_t ldz, void *work, hipStream_t s) {
+    return bt2_apply_t<double>(n, b, m, V2, voff, Z, ldz, work, s);
+}
+int bt2_apply_blocks(int64_t n, int b, int64_t m, const float *V2, const int64_t *voff, float *Z,
+                     int64_t ldz, void *work, hipStream_t s) {
+    return bt2_apply_t<float>(n, b, m, V2, voff, Z, ldz, work, s);
 }
 
 }  // namespace bdg

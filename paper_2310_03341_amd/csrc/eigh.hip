@@ -71,15 +71,15 @@ __global__ void nonfinite_lower(int64_t n, const double *__restrict__ A, int64_t
 
 struct Timer {
     hipStream_t s;
-    hipEvent_t ev[10];
+    hipEvent_t ev[12];
     bool ok = false;
     explicit Timer(hipStream_t st) : s(st) {
         ok = true;
-        for (int i = 0; i < 10; ++i)
+        for (int i = 0; i < 12; ++i)
             if (hipEventCreate(&ev[i]) != hipSuccess) ok = false;
     }
     ~Timer() {
-        for (int i = 0; i < 10; ++i) (void)hipEventDestroy(ev[i]);
+        for (int i = 0; i < 12; ++i) (void)hipEventDestroy(ev[i]);
     }
     void mark(int i) {
         if (ok) (void)hipEventRecord(ev[i], s);
@@ -157,6 +157,13 @@ __global__ void neg_reverse(int64_t half, const double *__restrict__ W, double *
     }
 }
 
+// W[k] = -W[src0 - k] for k < count
+__global__ void neg_reverse_w(int64_t count, double *__restrict__ W, int64_t src0) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+         k += (int64_t)gridDim.x * blockDim.x)
+        W[k] = -W[src0 - k];
+}
+
 int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, double *W, double *Z,
                int64_t ldz, int64_t zcols, int64_t *m_out, const bdg_opts *opts, void *work,
                bdg_err_report *report, hipStream_t s) {
@@ -183,7 +190,9 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
     void *rscratch = base + L.off_s3;            // s3 and s4 once the stages are done
     const int leaf = (opts && opts->dc_leaf > 0) ? opts->dc_leaf : 32;
     const bool ph_mirror = opts && opts->ph_mirror && (n % 2 == 0);
-    const int iters = (opts && opts->refine_max_iter > 0) ? opts->refine_max_iter : 2;
+    // refine_max_iter: 0 = default (3), < 0 = no refinement (the FP32 result)
+    const int iters = (opts && opts->refine_max_iter != 0) ? std::max(opts->refine_max_iter, 0) : 3;
+    const double rtol = (opts && opts->refine_tol > 0.0) ? opts->refine_tol : 1e-14;
 
     Timer tm(s);
     tm.mark(0);
@@ -217,7 +226,10 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
     const int64_t nc = n - c0;
     BDG_TRY(phase_scale(n, nc, Y, c0, ph, X32 + 2 * c0 * n, n, s));
     tm.mark(5);
-    BDG_TRY(bt2(n, b, nc, V2, tau2, voff, X32 + 2 * c0 * n, n, scratch, s));
+    BDG_TRY(bt2_prepare(n, b, V2, tau2, voff, scratch, s));
+    tm.mark(10);
+    BDG_TRY(bt2_apply_blocks(n, b, nc, V2, voff, X32 + 2 * c0 * n, n, scratch, s));
+    tm.mark(11);
     tm.mark(6);
     BDG_TRY(bt1(n, nc, A32, n, b, T1, X32 + 2 * c0 * n, n, scratch, s));
     if (ph_mirror) {
@@ -244,10 +256,28 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
     double normH = 0.0;
     for (double v : wh) normH = std::max(normH, std::fabs(v));
     BDG_TRY(cast_c64_to_c128(n, n, X32, n, X64, n, s));
-    double shift = 0.0, corr = 0.0;
-    BDG_TRY(refine_window(n, A, lda, X64, n, lam, i0, m, normH, iters, W, rscratch, s, &shift, &corr));
-    if (m > 0) BDG_HIP(hipMemcpy2DAsync(Z, 16 * (size_t)ldz, X64 + 2 * i0 * n, 16 * (size_t)n,
-                                        16 * (size_t)n, (size_t)m, hipMemcpyDeviceToDevice, s));
+    double shift = 0.0, corr = 0.0, delta0 = 0.0;
+    int done = 0, ccols = 0;
+    // with the mirror, a window that holds both partners of every pair only
+    // needs its E > 0 half refined; the E < 0 half is rebuilt from it
+    const int64_t h = n / 2;
+    int64_t r0 = i0;
+    const bool mir = ph_mirror && i0 < h && i1 > h && n - i0 <= i1;
+    if (mir) r0 = h;
+    const int64_t mr = i1 - r0;
+    if (iters > 0) {
+        BDG_TRY(refine_window(n, A, lda, X64, n, lam, r0, mr, normH, iters, rtol, W + (r0 - i0), rscratch, s,
+                              &shift, &corr, &done, &delta0, &ccols));
+    } else if (mr > 0) {  // refinement switched off: the FP32 result, widened
+        BDG_HIP(hipMemcpyAsync(W + (r0 - i0), lam + r0, 8 * (size_t)mr, hipMemcpyDeviceToDevice, s));
+    }
+    if (mr > 0) BDG_HIP(hipMemcpy2DAsync(Z + 2 * (r0 - i0) * ldz, 16 * (size_t)ldz, X64 + 2 * r0 * n,
+                                         16 * (size_t)n, 16 * (size_t)n, (size_t)mr, hipMemcpyDeviceToDevice, s));
+    if (mir) {
+        BDG_TRY(mirror_columns(n, Z, ldz, 0, (n - 1 - i0) - i0, h - i0, s));
+        hipLaunchKernelGGL(neg_reverse_w, dim3(64), dim3(256), 0, s, h - i0, W, (n - 1 - i0) - i0);
+        BDG_CHECK_LAUNCH();
+    }
     tm.mark(8);
     BDG_HIP(hipStreamSynchronize(s));
     if (report) {
@@ -261,8 +291,15 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
         report->stage_ms[6] = tm.ms(4, 5);
         report->stage_ms[7] = tm.ms(0, 8);
         report->eig_shift_max = shift;
-        report->refine_iters = iters;
-        report->max_resid = corr;  // last eigenvalue correction (the residual is measured by bdg_check)
+        report->refine_iters = done;
+        report->max_resid = corr;  // last max |E| (the residual itself is measured by bdg_check)
+        report->bt2_kernel_ms = tm.ms(10, 11);
+        report->refine_delta0 = delta0;
+        report->refine_cluster_cols = ccols;
+    }
+    if (iters > 0 && mr > 0 && corr >= std::sqrt(rtol)) {
+        set_error("bdg_eigh: refinement stopped after %d steps with defect %.3e", done, corr);
+        return BDG_ERR_REFINE_TOL;
     }
     return 0;
 }
@@ -354,7 +391,10 @@ int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
     BDG_TRY(phase_scale(n, mb, Y, bt_lo, ph, Zb, ldz, s));
     tm.mark(5);
     // ---- back-transformation 2 (band <- tridiagonal), then 1 (dense <- band)
-    BDG_TRY(bt2(n, b, mb, V2, tau2, voff, Zb, ldz, scratch, s));
+    BDG_TRY(bt2_prepare(n, b, V2, tau2, voff, scratch, s));
+    tm.mark(8);
+    BDG_TRY(bt2_apply_blocks(n, b, mb, V2, voff, Zb, ldz, scratch, s));
+    tm.mark(9);
     tm.mark(6);
     BDG_TRY(bt1(n, mb, A, lda, b, T1, Zb, ldz, scratch, s));
     if (mirror) BDG_TRY(mirror_columns(n, Z, ldz, 0, (n - 1 - i0) - i0, h - i0, s));
@@ -370,6 +410,7 @@ int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
         report->stage_ms[5] = 0.0;
         report->stage_ms[6] = tm.ms(4, 5);
         report->stage_ms[7] = tm.ms(0, 7);
+        report->bt2_kernel_ms = tm.ms(8, 9);
     }
     return 0;
 }

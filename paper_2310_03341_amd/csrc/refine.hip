@@ -11,7 +11,19 @@
 //   X_W  <- X_W + X E
 // All products are FP64 on the matrix cores (HEMM from the lower triangle of
 // H, ZGEMMs for X^H and X E); the 2-norms are power-iteration estimates.
+//
+// Clusters (part II of the method, clustered eigenvalues, 2019): the r_ij / 2
+// branch never resolves the mixing inside a group of eigenvalues closer than
+// delta, and that mixing keeps delta from shrinking.  Each chain of window
+// eigenvalues with consecutive gaps <= delta (at most CMAX members; longer
+// chains are cut into pieces) gets an FP64 Rayleigh-Ritz step:
+//   L = I + R_JJ / 2,  M = L S_JJ L = Q diag(mu) Q^H  (complex Jacobi in LDS)
+//   E[:, J] <- (I_W + E)[:, J] Q - I_W[:, J],  lam_J <- mu
 #include <math.h>
+
+#include <algorithm>
+#include <numeric>
+#include <vector>
 
 #include "gemm.h"
 #include "refine.h"
@@ -169,27 +181,239 @@ __global__ void vec_init(int64_t len, double *__restrict__ v) {
 }
 
 // E (in place of S): off-window rows use lam_all, window rows use lamW
+// emax: per block, max over (i, j) off the window diagonal of
+// max(|r_ij|, |s_ij + lam_j r_ij| / normH), the step's defect in residual units
+// (|E_ij| itself is large for well-separated but very close pairs whose
+// mixing no longer matters)
 __global__ void build_E(int64_t n, int64_t m, int64_t i0, double *__restrict__ S,
                         const double *__restrict__ R, int64_t ld, const double *__restrict__ lam_all,
-                        const double *__restrict__ lamW, double delta) {
+                        const double *__restrict__ lamW, double delta, double inv_normH,
+                        double *__restrict__ emax) {
+    __shared__ double red[4];
     const int64_t j = blockIdx.y;
     const double lj = lamW[j];
+    double mx = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double li = (i >= i0 && i < i0 + m) ? lamW[i - i0] : lam_all[i];
         const double sr = S[2 * (i + j * ld)], si = S[2 * (i + j * ld) + 1];
         const double rr = R[2 * (i + j * ld)], ri = R[2 * (i + j * ld) + 1];
         const double dif = lj - li;
+        const double nr = sr + lj * rr, ni = si + lj * ri;
         double er, ei;
         if (fabs(dif) > delta) {
-            er = (sr + lj * rr) / dif;
-            ei = (si + lj * ri) / dif;
+            er = nr / dif;
+            ei = ni / dif;
         } else {
             er = 0.5 * rr;
             ei = 0.5 * ri;
         }
         S[2 * (i + j * ld)] = er;
         S[2 * (i + j * ld) + 1] = ei;
+        if (i != i0 + j) mx = fmax(mx, fmax(fabs(rr) + fabs(ri), (fabs(nr) + fabs(ni)) * inv_normH));
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        emax[blockIdx.y * gridDim.x + blockIdx.x] = v;
+    }
+}
+
+constexpr int CMAX = 48;
+constexpr int CLD = CMAX + 1;  // LDS row pitch (complex entries)
+
+// c x c complex products in LDS: C = A B (all CLD-pitched, row-major [row][col])
+__device__ void lds_cmatmul(int c, const double2 *A, const double2 *B, double2 *C) {
+    for (int e = threadIdx.x; e < c * c; e += blockDim.x) {
+        const int r = e / c, q = e % c;
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < c; ++k) {
+            const double2 a = A[r * CLD + k], b = B[k * CLD + q];
+            sr += a.x * b.x - a.y * b.y;
+            si += a.x * b.y + a.y * b.x;
+        }
+        C[r * CLD + q] = make_double2(sr, si);
+    }
+}
+
+// One block per cluster: M = L S_JJ L (L = I + R_JJ / 2), Hermitian Jacobi
+// M = Q diag(mu) Q^H, mu ascending.  cidx lists each cluster's window columns in
+// ascending order of their current eigenvalue; Q goes to qbuf (column-major
+// c x c at qoff[b]), mu to mu[cidx], max_{k != l} |M_kl| / normH to cmax[b].
+__global__ void __launch_bounds__(256) cluster_eig(int64_t i0, const int *__restrict__ cidx,
+                                                   const int *__restrict__ coff,
+                                                   const int64_t *__restrict__ qoff,
+                                                   const double *__restrict__ S,
+                                                   const double *__restrict__ R, int64_t ld,
+                                                   double normH, double *__restrict__ qbuf,
+                                                   double *__restrict__ mu, double *__restrict__ cmax) {
+    __shared__ double2 A0[CMAX * CLD], A1[CMAX * CLD], A2[CMAX * CLD];
+    __shared__ double rot[4];
+    __shared__ int flag, perm[CMAX];
+    __shared__ double red[4];
+    const int b = blockIdx.x;
+    const int *J = cidx + coff[b];
+    const int c = coff[b + 1] - coff[b];
+    // A0 = S_JJ, A1 = L
+    for (int e = threadIdx.x; e < c * c; e += blockDim.x) {
+        const int r = e / c, q = e % c;
+        const int64_t off = 2 * ((i0 + J[r]) + (int64_t)J[q] * ld);
+        A0[r * CLD + q] = make_double2(S[off], S[off + 1]);
+        A1[r * CLD + q] = make_double2((r == q ? 1.0 : 0.0) + 0.5 * R[off], 0.5 * R[off + 1]);
+    }
+    __syncthreads();
+    lds_cmatmul(c, A0, A1, A2);  // T = S L
+    __syncthreads();
+    lds_cmatmul(c, A1, A2, A0);  // M = L T
+    __syncthreads();
+    // Hermitian part; Q = I in A1
+    double mx = 0.0;
+    for (int e = threadIdx.x; e < c * c; e += blockDim.x) {
+        const int r = e / c, q = e % c;
+        if (r < q) {
+            const double2 u = A0[r * CLD + q], v = A0[q * CLD + r];
+            const double2 h = make_double2(0.5 * (u.x + v.x), 0.5 * (u.y - v.y));
+            A0[r * CLD + q] = h;
+            A0[q * CLD + r] = make_double2(h.x, -h.y);
+            mx = fmax(mx, sqrt(h.x * h.x + h.y * h.y));
+        } else if (r == q) {
+            A0[r * CLD + r].y = 0.0;
+        }
+        A1[r * CLD + q] = make_double2(r == q ? 1.0 : 0.0, 0.0);
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) cmax[b] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3])) / normH;
+    // cyclic Jacobi with complex rotations G = [[cs, sn e], [-sn conj(e), cs]] on (p, q)
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        if (threadIdx.x == 0) flag = 0;
+        __syncthreads();
+        for (int p = 0; p < c - 1; ++p) {
+            for (int q = p + 1; q < c; ++q) {
+                if (threadIdx.x == 0) {
+                    const double2 bpq = A0[p * CLD + q];
+                    const double ab = sqrt(bpq.x * bpq.x + bpq.y * bpq.y);
+                    const double a = A0[p * CLD + p].x, d = A0[q * CLD + q].x;
+                    if (ab == 0.0 || ab < 1e-17 * (fabs(a) + fabs(d))) {
+                        rot[0] = 1.0;
+                        rot[1] = 0.0;
+                    } else {
+                        const double z = (d - a) / (2.0 * ab);
+                        const double t = fabs(z) < 1e150 ? (z >= 0.0 ? 1.0 : -1.0) / (fabs(z) + sqrt(1.0 + z * z))
+                                                         : 0.5 / z;
+                        const double cs = 1.0 / sqrt(1.0 + t * t);
+                        rot[0] = cs;
+                        rot[1] = t * cs;
+                        rot[2] = bpq.x / ab;
+                        rot[3] = bpq.y / ab;
+                        flag = 1;
+                    }
+                }
+                __syncthreads();
+                const double cs = rot[0], sn = rot[1];
+                if (sn != 0.0) {
+                    const double er = rot[2], ei = rot[3];
+                    const int k = threadIdx.x;
+                    if (k < c) {
+                        // columns p, q of M and Q: [x_p, x_q] G
+                        double2 *cols[2] = {A0, A1};
+                        for (int w = 0; w < 2; ++w) {
+                            double2 *X = cols[w];
+                            const double2 xp = X[k * CLD + p], xq = X[k * CLD + q];
+                            // xp' = cs xp - sn conj(e) xq ; xq' = sn e xp + cs xq
+                            X[k * CLD + p] = make_double2(cs * xp.x - sn * (er * xq.x + ei * xq.y),
+                                                          cs * xp.y - sn * (er * xq.y - ei * xq.x));
+                            X[k * CLD + q] = make_double2(sn * (er * xp.x - ei * xp.y) + cs * xq.x,
+                                                          sn * (er * xp.y + ei * xp.x) + cs * xq.y);
+                        }
+                    }
+                    __syncthreads();
+                    if (k < c) {
+                        // rows p, q of M: G^H [y_p; y_q]
+                        const double2 yp = A0[p * CLD + k], yq = A0[q * CLD + k];
+                        // yp' = cs yp - sn e yq ; yq' = sn conj(e) yp + cs yq
+                        A0[p * CLD + k] = make_double2(cs * yp.x - sn * (er * yq.x - ei * yq.y),
+                                                       cs * yp.y - sn * (er * yq.y + ei * yq.x));
+                        A0[q * CLD + k] = make_double2(sn * (er * yp.x + ei * yp.y) + cs * yq.x,
+                                                       sn * (er * yp.y - ei * yp.x) + cs * yq.y);
+                    }
+                    __syncthreads();
+                    if (threadIdx.x == 0) {
+                        A0[p * CLD + q] = make_double2(0.0, 0.0);
+                        A0[q * CLD + p] = make_double2(0.0, 0.0);
+                        A0[p * CLD + p].y = 0.0;
+                        A0[q * CLD + q].y = 0.0;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (flag == 0) break;
+        __syncthreads();
+    }
+    // ascending order of the eigenvalues
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < c; ++k) perm[k] = k;
+        for (int k = 0; k < c; ++k) {
+            int best = k;
+            for (int l = k + 1; l < c; ++l)
+                if (A0[perm[l] * CLD + perm[l]].x < A0[perm[best] * CLD + perm[best]].x) best = l;
+            const int t = perm[k];
+            perm[k] = perm[best];
+            perm[best] = t;
+        }
+    }
+    __syncthreads();
+    double *Qo = qbuf + 2 * qoff[b];
+    for (int e = threadIdx.x; e < c * c; e += blockDim.x) {
+        const int r = e % c, l = e / c;  // column-major output
+        const double2 v = A1[r * CLD + perm[l]];
+        Qo[2 * e] = v.x;
+        Qo[2 * e + 1] = v.y;
+    }
+    for (int l = threadIdx.x; l < c; l += blockDim.x) mu[J[l]] = A0[perm[l] * CLD + perm[l]].x;
+}
+
+// E[:, J] <- (I_W + E)[:, J] Q - I_W[:, J] for rows of a 64-row tile; lam_J <- mu
+__global__ void __launch_bounds__(64) cluster_apply(int64_t n, int64_t i0, const int *__restrict__ cidx,
+                                                    const int *__restrict__ coff,
+                                                    const int64_t *__restrict__ qoff,
+                                                    const double *__restrict__ qbuf, double *__restrict__ E,
+                                                    int64_t ld, const double *__restrict__ mu,
+                                                    double *__restrict__ lamW) {
+    __shared__ double2 Qs[CMAX * CMAX];
+    __shared__ double2 e[64 * CLD];
+    __shared__ int Js[CMAX];
+    const int b = blockIdx.y;
+    const int *J = cidx + coff[b];
+    const int c = coff[b + 1] - coff[b];
+    const double *Q = qbuf + 2 * qoff[b];
+    for (int t = threadIdx.x; t < c * c; t += 64) Qs[t] = make_double2(Q[2 * t], Q[2 * t + 1]);
+    for (int t = threadIdx.x; t < c; t += 64) Js[t] = J[t];
+    __syncthreads();
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t < c; t += 64) lamW[Js[t]] = mu[Js[t]];
+    const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t wrow = i - i0;  // this row's window column, if any
+    double2 *er = e + threadIdx.x * CLD;
+    for (int k = 0; k < c; ++k) {
+        const int64_t off = 2 * (i + (int64_t)Js[k] * ld);
+        er[k] = make_double2(E[off] + (wrow == Js[k] ? 1.0 : 0.0), E[off + 1]);
+    }
+    for (int l = 0; l < c; ++l) {
+        double sr = 0.0, si = 0.0;
+        for (int k = 0; k < c; ++k) {
+            const double2 a = er[k], q = Qs[k + l * c];
+            sr += a.x * q.x - a.y * q.y;
+            si += a.x * q.y + a.y * q.x;
+        }
+        const int64_t off = 2 * (i + (int64_t)Js[l] * ld);
+        E[off] = sr - (wrow == Js[l] ? 1.0 : 0.0);
+        E[off + 1] = si;
     }
 }
 
@@ -205,7 +429,7 @@ __global__ void max_abs_diff(int64_t m, const double *__restrict__ a, const doub
                              double *__restrict__ out) {
     __shared__ double red[16];
     double mx = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) mx = fmax(mx, fabs(a[i] - b[i]));
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) mx = fmax(mx, fabs(a[i] - (b ? b[i] : 0.0)));
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
     __syncthreads();
@@ -293,14 +517,48 @@ int mirror_columns(int64_t n, double *X, int64_t ld, int64_t dst0, int64_t src0,
 
 size_t refine_workspace(int64_t n, int64_t m) {
     const size_t big = 16 * (size_t)n * (size_t)m;
-    return 2 * ((big + 255) / 256 * 256) + 16 * (size_t)(n + m) * 4 + 8 * (size_t)m * 2 + 4096;
+    const size_t clusters = 16 * (size_t)CMAX * m + 8 * (size_t)m + 4 * (size_t)m + 12 * (size_t)(m + 2) +
+                            8 * (size_t)(m + 2) + 5 * 256;
+    return 2 * ((big + 255) / 256 * 256) + 16 * (size_t)(n + m) * 4 + 8 * (size_t)m * 68 + 8192 + clusters;
 }
+
+namespace {
+
+// Chains of ascending eigenvalues with gaps <= delta, cut into pieces of at most
+// CMAX; members listed in ascending order.  Returns the number of clusters.
+int find_clusters(const std::vector<double> &lam, double delta, std::vector<int> &idx, std::vector<int> &off,
+                  std::vector<int64_t> &qo) {
+    const int m = (int)lam.size();
+    std::vector<int> order((size_t)m);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+    idx.clear();
+    off.assign(1, 0);
+    qo.assign(1, 0);
+    int start = 0;
+    for (int k = 1; k <= m; ++k) {
+        if (k == m || lam[order[k]] - lam[order[k - 1]] > delta) {
+            for (int a = start; k - a >= 2; a += CMAX) {
+                const int c = std::min(CMAX, k - a);
+                if (c < 2) break;
+                for (int t = 0; t < c; ++t) idx.push_back(order[a + t]);
+                off.push_back((int)idx.size());
+                qo.push_back(qo.back() + (int64_t)c * c);
+            }
+            start = k;
+        }
+    }
+    return (int)off.size() - 1;
+}
+
+}  // namespace
 
 // X: full FP64 basis n x n (ld ldx), lam_all[n] its approximate eigenvalues;
 // window columns [i0, i0+m) are refined in place; W receives lam_W.
 int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ldx,
-                  const double *lam_all, int64_t i0, int64_t m, double normH, int iters,
-                  double *W, void *work, hipStream_t s, double *eig_shift, double *last_corr) {
+                  const double *lam_all, int64_t i0, int64_t m, double normH, int iters, double tol,
+                  double *W, void *work, hipStream_t s, double *eig_shift, double *last_corr,
+                  int *iters_done, double *delta0, int *nclusters) {
     if (m <= 0) return 0;
     char *wp = (char *)work;
     auto take = [&](size_t bytes) {
@@ -315,6 +573,16 @@ int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ld
     double *lamW = take(8 * (size_t)m);
     double *lamP = take(8 * (size_t)m);
     double *tmp = take(64);
+    double *emax = take(8 * (size_t)m * 64 + 64);
+    double *qbuf = take(16 * (size_t)CMAX * m);
+    double *mu = take(8 * (size_t)m);
+    int *cidx = (int *)take(4 * (size_t)m);
+    int *coff = (int *)take(4 * (size_t)(m + 2));
+    int64_t *qoff = (int64_t *)take(8 * (size_t)(m + 2));
+    double *cmax = take(8 * (size_t)(m + 2));
+    std::vector<double> lam_h((size_t)m);
+    std::vector<int> idx_h, off_h;
+    std::vector<int64_t> qo_h;
     double *XW = X + 2 * i0 * ldx;
     BDG_HIP(hipMemcpyAsync(lamP, lam_all + i0, 8 * (size_t)m, hipMemcpyDeviceToDevice, s));
     double shift = 0.0;
@@ -335,9 +603,36 @@ int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ld
         BDG_TRY(norm2_est(m, m, B2, n, i0, lamW, vx, vy, tmp, 8, s, &nS));
         BDG_TRY(norm2_est(n, m, B1, n, 0, nullptr, vx, vy, tmp, 8, s, &nR));
         const double delta = 2.0 * 2.0 * (nS + normH * nR);  // x2: power iteration bounds from below
+        // clusters from the current window eigenvalues
+        BDG_HIP(hipMemcpyAsync(lam_h.data(), lamW, 8 * (size_t)m, hipMemcpyDeviceToHost, s));
+        BDG_HIP(hipStreamSynchronize(s));
+        const int ncl = find_clusters(lam_h, delta, idx_h, off_h, qo_h);
+        if (ncl > 0) {
+            BDG_HIP(hipMemcpyAsync(cidx, idx_h.data(), 4 * idx_h.size(), hipMemcpyHostToDevice, s));
+            BDG_HIP(hipMemcpyAsync(coff, off_h.data(), 4 * off_h.size(), hipMemcpyHostToDevice, s));
+            BDG_HIP(hipMemcpyAsync(qoff, qo_h.data(), 8 * qo_h.size(), hipMemcpyHostToDevice, s));
+            // reads S and R before build_E turns S into E
+            hipLaunchKernelGGL(cluster_eig, dim3((unsigned)ncl), dim3(256), 0, s, i0, cidx, coff, qoff, B2, B1,
+                               n, normH > 0.0 ? normH : 1.0, qbuf, mu, cmax);
+            BDG_CHECK_LAUNCH();
+        }
         hipLaunchKernelGGL(build_E, dim3(gx(n), (unsigned)m), dim3(256), 0, s, n, m, i0, B2, B1, n, lam_all,
-                           lamW, delta);
+                           lamW, delta, normH > 0.0 ? 1.0 / normH : 1.0, emax);
         BDG_CHECK_LAUNCH();
+        hipLaunchKernelGGL(max_abs_diff, dim3(1), dim3(1024), 0, s, (int64_t)gx(n) * m, emax,
+                           (const double *)nullptr, tmp + 1);
+        BDG_CHECK_LAUNCH();
+        if (ncl > 0) {
+            hipLaunchKernelGGL(cluster_apply, dim3((unsigned)((n + 63) / 64), (unsigned)ncl), dim3(64), 0, s, n,
+                               i0, cidx, coff, qoff, qbuf, B2, n, mu, lamW);
+            BDG_CHECK_LAUNCH();
+            hipLaunchKernelGGL(max_abs_diff, dim3(1), dim3(1024), 0, s, (int64_t)ncl, cmax,
+                               (const double *)nullptr, tmp + 2);
+            BDG_CHECK_LAUNCH();
+        } else {
+            BDG_HIP(hipMemsetAsync(tmp + 2, 0, 8, s));
+        }
+        if (nclusters) *nclusters = (int)idx_h.size();
         // B1 = X_W ; B1 += X E ; X_W = B1
         hipLaunchKernelGGL(copy_c128, dim3(gx(n), (unsigned)m), dim3(256), 0, s, n, XW, ldx, B1, n);
         BDG_CHECK_LAUNCH();
@@ -347,12 +642,20 @@ int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ld
         BDG_CHECK_LAUNCH();
         hipLaunchKernelGGL(max_abs_diff, dim3(1), dim3(1024), 0, s, m, lamW, lamP, tmp);
         BDG_CHECK_LAUNCH();
-        double h = 0.0;
-        BDG_HIP(hipMemcpyAsync(&h, tmp, 8, hipMemcpyDeviceToHost, s));
+        double h[3] = {0.0, 0.0, 0.0};
+        BDG_HIP(hipMemcpyAsync(h, tmp, 24, hipMemcpyDeviceToHost, s));
         BDG_HIP(hipMemcpyAsync(lamP, lamW, 8 * (size_t)m, hipMemcpyDeviceToDevice, s));
         BDG_HIP(hipStreamSynchronize(s));
-        if (it == 0) shift = h;
-        if (last_corr) *last_corr = h;
+        if (it == 0) {
+            shift = h[0];
+            if (delta0) *delta0 = delta;
+        }
+        const double corr = std::max(h[1], h[2]);
+        if (last_corr) *last_corr = corr;
+        if (iters_done) *iters_done = it + 1;
+        // the defect shrinks quadratically; stop once it (and the in-cluster
+        // coupling) is at rounding level
+        if (corr < tol) break;
     }
     BDG_HIP(hipMemcpyAsync(W, lamW, 8 * (size_t)m, hipMemcpyDeviceToDevice, s));
     if (eig_shift) *eig_shift = shift;

@@ -44,6 +44,15 @@ int phase_scale(int64_t n, int64_t m, const double *Y, int64_t i0, const double 
 int phase_scale(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, float *Z,
                 int64_t ldz, hipStream_t s);
 int64_t bt2_nblocks(int64_t n, int b);
+// block T factors (into work), then the application to Z (same work)
+int bt2_prepare(int64_t n, int b, const double *V2, const double *tau2, const int64_t *voff,
+                void *work, hipStream_t s);
+int bt2_prepare(int64_t n, int b, const float *V2, const float *tau2, const int64_t *voff,
+                void *work, hipStream_t s);
+int bt2_apply_blocks(int64_t n, int b, int64_t m, const double *V2, const int64_t *voff, double *Z,
+                     int64_t ldz, void *work, hipStream_t s);
+int bt2_apply_blocks(int64_t n, int b, int64_t m, const float *V2, const int64_t *voff, float *Z,
+                     int64_t ldz, void *work, hipStream_t s);
 size_t bt2_workspace(int64_t n, int b);
 int bt2(int64_t n, int b, int64_t m, const double *V2, const double *tau2, const int64_t *voff,
         double *Z, int64_t ldz, void *work, hipStream_t s);

@@ -212,6 +212,22 @@ def random_hermitian(n: int, seed: int) -> np.ndarray:
     return (A + A.conj().T) / 2.0
 
 
+def clustered_hermitian(n: int, seed: int):
+    """Hermitian Q diag(w) Q^H with a known spectrum holding tight groups:
+    pairs 1e-6 and 1e-9 apart and an exactly degenerate triple among uniform
+    values in [-5, 5].  Returns (H, w ascending)."""
+    rng = _rng(seed)
+    w = np.sort(rng.uniform(-5.0, 5.0, n))
+    k = n // 5
+    w[k], w[k + 1] = 1.0, 1.0 + 1e-6
+    w[2 * k], w[2 * k + 1] = -2.0, -2.0 + 1e-9
+    w[3 * k] = w[3 * k + 1] = w[3 * k + 2] = 2.5
+    w = np.sort(w)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    H = (Q * w) @ Q.conj().T
+    return 0.5 * (H + H.conj().T), w
+
+
 def random_tridiagonal(n: int, seed: int):
     rng = _rng(seed)
     return rng.standard_normal(n), rng.standard_normal(max(n - 1, 0))

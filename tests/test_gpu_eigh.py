@@ -128,6 +128,39 @@ def test_mixed_refined_matches_oracle(dev, name, make, ph):
     assert res <= VEC_TOL and gram <= VEC_TOL, (res, gram)
 
 
+def _solve_report(dev, H, **kw):
+    from paper_2310_03341_amd import api
+    n = H.shape[0]
+    solver = api.Solver(n, api.make_opts(**kw), dev)
+    W, Z = solver(to_dev_colmajor(H, dev))
+    res, gram = api.check(to_dev_colmajor(H, dev), W, Z)
+    return W.cpu().numpy(), res, gram, solver.report
+
+
+def test_mixed_refined_clustered_spectrum(dev):
+    """Pairs 1e-6 and 1e-9 apart and an exact triple: the in-cluster
+    Rayleigh-Ritz step is what takes them to FP64 accuracy."""
+    H, w = inputs.clustered_hermitian(240, 21)
+    W, res, gram, rep = _solve_report(dev, H, precision=1)
+    print("delta0 %.3e clusters %d iters %d corr %.3e" % (rep.refine_delta0, rep.refine_cluster_cols,
+                                                          rep.refine_iters, rep.max_resid))
+    assert rep.refine_delta0 > 1e-6  # the 1e-6 pair starts inside one cluster
+    assert rep.refine_cluster_cols >= 3
+    assert np.abs(W - w).max() <= 1e-13 * (w[-1] - w[0])
+    assert res <= VEC_TOL and gram <= VEC_TOL, (res, gram)
+
+
+def test_mixed_unrefined_is_fp32_accurate(dev):
+    """refine_max_iter < 0 returns the FP32 pipeline's result: FP32-level
+    residual, far from FP64 (so the refinement is what closes the gap)."""
+    H = oracle.assemble_workload(inputs.tiny_2d())
+    ref = oracle.eigh_hqr(H, vectors=False)[0]
+    W, res, gram, rep = _solve_report(dev, H, precision=1, refine_max_iter=-1)
+    assert rep.refine_iters == 0
+    assert 1e-10 < res < 1e-4 and gram < 1e-3
+    assert np.abs(W - ref).max() < 1e-4 * (ref[-1] - ref[0])
+
+
 def test_mixed_refined_window(dev):
     H = oracle.assemble_workload(inputs.tiny_2d())
     Ec = math.pi ** 2 / 2

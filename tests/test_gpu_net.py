@@ -59,13 +59,47 @@ def test_net_forward_matches_oracle(dev, C, ny, nx, B):
     assert np.abs(got - ref).max() <= 3e-2 * max(1.0, np.abs(ref).max())
 
 
-def test_net_gradients_match_oracle(dev):
+def _bf16(x):
+    """Round to bfloat16 (nearest even), returned as float64."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _grads_bf16_model(params, x0, target):
+    """The oracle's definitions evaluated on operands rounded where the kernels
+    round them: BF16 input features, weights, stored activations and the
+    data-gradient operand; weight and bias gradients from the unrounded output
+    gradient.  The relu masks then come from the same BF16 activations."""
+    from oracle import net
+    h = _bf16(x0)
+    acts = [h]
+    for layer in range(4):
+        z = net.conv(h, _bf16(params[2 * layer]), params[2 * layer + 1])
+        h = _bf16(np.maximum(z, 0.0)) if layer < 3 else z
+        acts.append(h)
+    d = acts[-1] - target
+    g = 2.0 * d / d.size
+    grads = [None] * 8
+    for layer in range(3, -1, -1):
+        _, gW, gb = net.conv_backward(acts[layer], params[2 * layer], g)
+        grads[2 * layer], grads[2 * layer + 1] = gW, gb
+        if layer == 0:
+            break
+        gx, _, _ = net.conv_backward(acts[layer], _bf16(params[2 * layer]), _bf16(g))
+        g = gx * (acts[layer] > 0.0)
+    return grads
+
+
+@pytest.mark.parametrize("seed", [5, 6])
+def test_net_gradients_match_oracle(dev, seed):
     import torch
     from oracle import net
     from paper_2310_03341_amd import api
     C, ny, nx, B = 16, 12, 12, 2
-    params, Vext, theta, mu, x0, target = _problem(C, ny, nx, B, seed=5)
+    params, Vext, theta, mu, x0, target = _problem(C, ny, nx, B, seed=seed)
     loss_ref, grads_ref = net.loss_and_grads(params, x0, target)
+    grads_bf = _grads_bf16_model(params, x0, target)
     sn = api.StartNet(C, ny, nx, B, dev)
     sn.params.copy_(torch.from_numpy(_flat(params)))
     loss = sn.backward(torch.from_numpy(Vext).to(dev), torch.from_numpy(theta).to(dev), mu,
@@ -73,9 +107,14 @@ def test_net_gradients_match_oracle(dev):
     torch.cuda.synchronize()
     assert abs(loss.item() - loss_ref) <= 2e-2 * loss_ref
     g = _unflat(sn.grads.cpu().numpy(), C)
-    for i, (a, b) in enumerate(zip(g, grads_ref)):
-        scale = np.abs(b).max()
-        assert np.abs(a - b).max() <= 5e-2 * scale + 1e-6, (i, np.abs(a - b).max(), scale)
+    for i, (a, b, e) in enumerate(zip(g, grads_ref, grads_bf)):
+        # against the same roundings: only FP32 accumulation order differs
+        rel_bf = np.linalg.norm(a - e) / max(np.linalg.norm(e), 1e-12)
+        assert rel_bf <= 5e-3, (i, rel_bf)
+        # against FP64: the BF16 roundings themselves move the first layer's
+        # gradient by 4-6 % (norm-wise) on these problems, later layers less
+        rel = np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-12)
+        assert rel <= 0.1, (i, rel)
 
 
 def test_net_training_reduces_loss(dev):
