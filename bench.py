@@ -27,6 +27,26 @@ if ROOT not in sys.path:
 PEAK_FP64_MFMA = 78.6e12
 PEAK_HBM = 8.0e12
 
+# HBM traffic of one bt2_apply launch from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# passes (KiB per dispatch), each scaled by what the same counter reads for a
+# 1 GiB device copy in the same run.  Valid only for the kernel source it was
+# measured on (sha256 of csrc/bt2.hip) and the same workload; otherwise the
+# bench reports null.
+BT2_TRAFFIC = None  # {"sha256": ..., "n": ..., "m_bt": ..., "fetch_bytes": ..., "write_bytes": ...}
+
+
+def _bt2_source_sha() -> str:
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2310_03341_amd", "csrc", "bt2.hip"), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def bt2_traffic(n: int, m_bt: int):
+    t = BT2_TRAFFIC
+    if not t or t["sha256"] != _bt2_source_sha() or t["n"] != n or t["m_bt"] != m_bt:
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
+
 
 def flops_two_stage(n: int, m: int) -> float:
     return (16.0 / 3.0 + 4.0 / 3.0) * n ** 3 + 16.0 * n * n * m
@@ -83,6 +103,9 @@ def main():
     ap.add_argument("--no-ph-mirror", action="store_true",
                     help="back-transform every eigenvector instead of the E > 0 half + mirror")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refinement arm")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device copy (read 1 GiB, write 1 GiB) before the solves, "
+                         "as the reference point for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver is single-GPU; run with --gpus 1",
@@ -113,8 +136,21 @@ def main():
         api.assemble(w.dims, U, D, w.mu, out=H)
         return solver(H, -math.inf, math.inf, W, Z)
 
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)  # one elementwise kernel: 1 GiB read, 1 GiB written
+        torch.cuda.synchronize()
+        del src, dst
+
+    def progress(msg):
+        print("[bench] " + msg, file=sys.stderr, flush=True)
+
+    progress("n=%d, workload %s" % (n, w.name))
     for _ in range(args.warmup):
         step()
+        torch.cuda.synchronize()
+        progress("warmup step %.2f s" % (solver.report.stage_ms[7] / 1e3))
     torch.cuda.synchronize()
     stage = [0.0] * 8
     t_eigh = []
@@ -127,6 +163,7 @@ def main():
         t_bt2.append(rep.bt2_kernel_ms / 1e3)
         for i in range(8):
             stage[i] += rep.stage_ms[i] / args.steps
+        progress("timed step %.2f s" % (rep.stage_ms[7] / 1e3))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     m = Wk.numel()
@@ -160,7 +197,8 @@ def main():
             ["he2hb", "hb2st", "stedc", "bt2", "bt1", "refine", "select", "total"], stage)},
         "roofline": {"kernel": "bt2_apply", "bound": "mfma", "achieved": round(f_k / t_k / 1e12, 3),
                      "peak": 78.6, "unit": "TFLOP/s", "frac": round(f_k / t_k / PEAK_FP64_MFMA, 4),
-                     "traffic": None, "flops_per_launch": f_k, "ms_per_launch": round(1e3 * t_k, 2)},
+                     "traffic": bt2_traffic(n, m_bt), "flops_per_launch": f_k,
+                     "ms_per_launch": round(1e3 * t_k, 2)},
     }
     if args.check:
         H2 = api.assemble(w.dims, U, D, w.mu)
@@ -194,8 +232,10 @@ def main():
         if Wm.numel() == W64.numel():
             mixed["max_eig_diff_vs_fp64"] = float((Wm - W64).abs().max())
         out["mixed_refined"] = mixed
+        progress("mixed arm %.2f s" % mixed["time_s"])
         del msolver
     if not args.no_cpu:
+        progress("CPU oracle baseline")
         dt, n_s, cores, sdims = cpu_baseline()
         scale = (n / n_s) ** 3
         out["cpu_baseline"] = {"value": round(dt * scale, 1), "unit": "s", "cores": cores,

@@ -16,8 +16,9 @@ int mirror_columns(int64_t n, double *X, int64_t ld, int64_t dst0, int64_t src0,
                    hipStream_t s);
 size_t refine_workspace(int64_t n, int64_t m);
 // Up to `iters` steps; stops early once the step's defect, max over (i, j) off
-// the window diagonal of max(|r_ij|, |s_ij + lam_j r_ij| / normH), and the
-// in-cluster coupling max |M_kl| / normH are both < tol.  delta0: the
+// the window diagonal of max(|r_ij|, |s_ij + lam_j r_ij| / normH) (only the
+// second term on rows outside the window), and the in-cluster coupling
+// max |M_kl| / normH are both < tol.  delta0: the
 // first step's delta; nclusters: columns in clusters at the last step.
 int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ldx,
                   const double *lam_all, int64_t i0, int64_t m, double normH, int iters, double tol,

@@ -184,7 +184,9 @@ __global__ void vec_init(int64_t len, double *__restrict__ v) {
 // emax: per block, max over (i, j) off the window diagonal of
 // max(|r_ij|, |s_ij + lam_j r_ij| / normH), the step's defect in residual units
 // (|E_ij| itself is large for well-separated but very close pairs whose
-// mixing no longer matters)
+// mixing no longer matters); rows outside the window are columns of the
+// unrefined basis, whose overlap with a converged column stays at the level of
+// their own error, so there only the residual part counts
 __global__ void build_E(int64_t n, int64_t m, int64_t i0, double *__restrict__ S,
                         const double *__restrict__ R, int64_t ld, const double *__restrict__ lam_all,
                         const double *__restrict__ lamW, double delta, double inv_normH,
@@ -195,7 +197,8 @@ __global__ void build_E(int64_t n, int64_t m, int64_t i0, double *__restrict__ S
     double mx = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double li = (i >= i0 && i < i0 + m) ? lamW[i - i0] : lam_all[i];
+        const bool inw = i >= i0 && i < i0 + m;
+        const double li = inw ? lamW[i - i0] : lam_all[i];
         const double sr = S[2 * (i + j * ld)], si = S[2 * (i + j * ld) + 1];
         const double rr = R[2 * (i + j * ld)], ri = R[2 * (i + j * ld) + 1];
         const double dif = lj - li;
@@ -210,7 +213,11 @@ __global__ void build_E(int64_t n, int64_t m, int64_t i0, double *__restrict__ S
         }
         S[2 * (i + j * ld)] = er;
         S[2 * (i + j * ld) + 1] = ei;
-        if (i != i0 + j) mx = fmax(mx, fmax(fabs(rr) + fabs(ri), (fabs(nr) + fabs(ni)) * inv_normH));
+        if (i != i0 + j) {
+            // off-window rows hold the unrefined basis: only the residual part counts there
+            const double dn = (fabs(nr) + fabs(ni)) * inv_normH;
+            mx = fmax(mx, inw ? fmax(fabs(rr) + fabs(ri), dn) : dn);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;

@@ -13,6 +13,7 @@ CLI: python -m paper_2310_03341_amd.learned_start --dims 32 32 --train 64 --test
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import time
@@ -139,22 +140,29 @@ def main():
     ap.add_argument("--test", type=int, default=16)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--channels", type=int, default=32)
+    ap.add_argument("--alpha", type=float, default=0.9, help="linear mixing (same for both starts)")
+    ap.add_argument("--max-iter", type=int, default=400)
     ap.add_argument("--out", type=str, default="")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
-    p = inputs.ScfParams()
+    p = dataclasses.replace(inputs.ScfParams(), alpha=args.alpha, max_iter=args.max_iter)
     dims = tuple(args.dims)
     log = lambda s: print(s, flush=True)  # noqa: E731
     t0 = time.time()
-    train_set = generate(list(range(args.train)), dims, p, dev, log)
-    test_set = generate(list(range(10000, 10000 + args.test)), dims, p, dev, log)
+    # instances whose uniform-start iteration does not converge (limit cycles
+    # of a level on the window edge) are left out of both sets
+    train_all = generate(list(range(args.train)), dims, p, dev, log)
+    test_all = generate(list(range(10000, 10000 + args.test)), dims, p, dev, log)
+    train_set = [d for d in train_all if d["ok"]]
+    test_set = [d for d in test_all if d["ok"]]
     t1 = time.time()
     net = train(train_set, dims, dev, channels=args.channels, steps=args.steps, log=log)
     t2 = time.time()
     rows = evaluate(net, test_set, p, dev, log)
     iu = np.mean([r["iters_uniform"] for r in rows])
     il = np.mean([r["iters_learned"] for r in rows])
-    res = {"dims": list(dims), "train": args.train, "test": args.test,
+    res = {"dims": list(dims), "train": len(train_set), "test": len(test_set), "alpha": p.alpha,
+           "dropped_not_converged": (len(train_all) - len(train_set), len(test_all) - len(test_set)),
            "mean_iters_uniform": iu, "mean_iters_learned": il,
            "max_l2_dU": max(r["l2_dU"] for r in rows), "max_l2_dDelta": max(r["l2_dDelta"] for r in rows),
            "gen_s": t1 - t0, "train_s": t2 - t1, "rows": rows}
