@@ -20,18 +20,28 @@ the real case).  The window variant refines only the columns W of X against
 the full basis X: R[:, W] = I[:, W] - X^H X_W, S[:, W] = X^H (H X_W).
 
 Clusters (Ogita & Aishima, part II: clustered eigenvalues, Japan J. Indust.
-Appl. Math. 36 (2019)).  The r_ij / 2 branch only re-orthonormalises a group
-of eigenvalues closer than delta; it never resolves the mixing inside the
-group, so delta (which contains that mixing through ||S - diag||) would stay
-put.  Each cluster (a maximal chain of sorted eigenvalues with consecutive
-gaps <= delta) therefore also gets a Rayleigh-Ritz step in FP64: with
-L = I + R_JJ / 2 (first-order Loewdin orthonormalisation of the cluster
-columns), M = L S_JJ L, M = Q diag(mu) Q^H, the cluster columns become
-X (I + E)[:, J] Q and their eigenvalues mu.
+Appl. Math. 36 (2019)).  The r_ij / 2 branch only re-orthonormalises a group of
+close eigenvalues; it never resolves the mixing inside the group.  So each
+cluster also gets a Rayleigh-Ritz step in FP64: with L = I + R_JJ / 2
+(first-order Loewdin orthonormalisation of the cluster columns),
+M = L S_JJ L = Q diag(mu) Q^H, the cluster columns become X (I + E)[:, J] Q and
+their eigenvalues mu.
+
+Which pairs are close (rule "pair", the one the GPU path uses): the published
+criterion |lam_i - lam_j| <= delta uses one global delta, and from an FP32
+basis of order 10^4 delta exceeds the mean level spacing, so its chains of
+close eigenvalues join most of the spectrum.  Here a pair is close when its
+first-order coefficient would not be small, |s_ij + lam_j r_ij| >= tau
+|lam_j - lam_i| with tau = 1e-3 (this includes lam_i = lam_j); clusters are the
+connected components of close pairs inside the window; close pairs with a row
+outside the window take r_ij / 2 without Rayleigh-Ritz.  Rule "delta" is the
+published criterion (clusters = chains of sorted eigenvalues with gaps <= delta).
 """
 from __future__ import annotations
 
 import numpy as np
+
+TAU = 1e-3
 
 
 def _herm(M):
@@ -51,9 +61,57 @@ def clusters(lam: np.ndarray, delta: float):
     return out
 
 
-def _cluster_rr(E, I_W, Rw, Sw, lam_W, delta):
+def components(m: int, pairs, lam: np.ndarray):
+    """Connected components (>= 2 members) of the graph on 0..m-1 with the given
+    edges, each in ascending order of lam."""
+    parent = list(range(m))
+
+    def root(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for a, b in pairs:
+        ra, rb = root(int(a)), root(int(b))
+        if ra != rb:
+            parent[ra] = rb
+    groups = {}
+    for a in range(m):
+        groups.setdefault(root(a), []).append(a)
+    out = [np.array(sorted(g, key=lambda t: (lam[t], t))) for g in groups.values() if len(g) >= 2]
+    out.sort(key=lambda J: (lam[J[0]], J[0]))
+    return out
+
+
+def _correction(S, R, lam_rows, lam_W, win_rows, rule, delta, tau=TAU):
+    """E for the rows of S, R (n x m) and the clusters of the window.
+
+    win_rows[k] is the row of window column k."""
+    n, m = S.shape
+    diff = lam_W[None, :] - lam_rows[:, None]        # lam_j - lam_i
+    num = S + lam_W[None, :] * R
+    if rule == "delta":
+        near = np.abs(diff) <= delta
+        cl = clusters(lam_W, delta)
+    else:
+        near = np.abs(num) >= tau * np.abs(diff)
+        Wn = near[win_rows, :]
+        a, b = np.nonzero(np.triu(Wn | Wn.T, 1))
+        cl = components(m, zip(a, b), lam_W)
+        same = np.zeros((m, m), dtype=bool)
+        for J in cl:
+            same[np.ix_(J, J)] = True
+        same[np.arange(m), np.arange(m)] = True
+        near[win_rows, :] = same
+    with np.errstate(divide="ignore", invalid="ignore"):
+        E = np.where(near, R / 2.0, num / np.where(near, 1.0, diff))
+    return E, cl
+
+
+def _cluster_rr(E, I_W, Rw, Sw, lam_W, cl):
     """Rayleigh-Ritz inside each cluster: E[:, J] <- (I_W + E)[:, J] Q - I_W[:, J]."""
-    for J in clusters(lam_W, delta):
+    for J in cl:
         L = np.eye(J.size) + Rw[np.ix_(J, J)] / 2.0
         M = _herm(L @ Sw[np.ix_(J, J)] @ L)
         mu, Q = np.linalg.eigh(M)
@@ -61,26 +119,26 @@ def _cluster_rr(E, I_W, Rw, Sw, lam_W, delta):
         lam_W[J] = mu
 
 
-def oa_step(H: np.ndarray, X: np.ndarray, normH: float | None = None, cluster_rr: bool = True):
+def oa_step(H: np.ndarray, X: np.ndarray, normH: float | None = None, cluster_rr: bool = True,
+            rule: str = "pair"):
     """One full Ogita-Aishima step on all columns; returns (X_new, lam)."""
     n = X.shape[1]
     R = _herm(np.eye(n) - X.conj().T @ X)
     S = _herm(X.conj().T @ (H @ X))
     lam = np.real(np.diag(S)) / (1.0 - np.real(np.diag(R)))
-    if normH is None:
-        normH = np.abs(np.linalg.eigvalsh(H)).max()
-    delta = 2.0 * (np.linalg.norm(S - np.diag(lam), 2) + normH * np.linalg.norm(R, 2))
-    diff = lam[None, :] - lam[:, None]          # lam_j - lam_i
-    num = S + lam[None, :] * R
-    with np.errstate(divide="ignore", invalid="ignore"):
-        E = np.where(np.abs(diff) > delta, num / diff, R / 2.0)
+    delta = None
+    if rule == "delta":
+        if normH is None:
+            normH = np.abs(np.linalg.eigvalsh(H)).max()
+        delta = 2.0 * (np.linalg.norm(S - np.diag(lam), 2) + normH * np.linalg.norm(R, 2))
+    E, cl = _correction(S, R, lam, lam, np.arange(n), rule, delta)
     if cluster_rr:
-        _cluster_rr(E, np.eye(n), R, S, lam, delta)
+        _cluster_rr(E, np.eye(n), R, S, lam, cl)
     return X + X @ E, lam
 
 
 def oa_step_window(H: np.ndarray, X: np.ndarray, lam0: np.ndarray, cols: np.ndarray, normH: float,
-                   cluster_rr: bool = True):
+                   cluster_rr: bool = True, rule: str = "pair"):
     """Refine columns `cols` of the full basis X; returns (X_W_new, lam_W).
 
     lam0 are the approximate eigenvalues that came with X; outside the window
@@ -100,14 +158,12 @@ def oa_step_window(H: np.ndarray, X: np.ndarray, lam0: np.ndarray, cols: np.ndar
     lam_all = np.array(lam0, dtype=np.float64, copy=True)
     lam_W = np.real(np.diag(Sw)) / (1.0 - np.real(np.diag(Rw)))
     lam_all[cols] = lam_W
-    delta = 2.0 * (np.linalg.norm(Sw - np.diag(lam_W), 2) + normH * np.linalg.norm(R, 2))
-    diff = lam_W[None, :] - lam_all[:, None]
-    num = S + lam_W[None, :] * R
-    with np.errstate(divide="ignore", invalid="ignore"):
-        E = np.where(np.abs(diff) > delta, num / diff, R / 2.0)
+    delta = None
+    if rule == "delta":
+        delta = 2.0 * (np.linalg.norm(Sw - np.diag(lam_W), 2) + normH * np.linalg.norm(R, 2))
+    E, cl = _correction(S, R, lam_all, lam_W, cols, rule, delta)
     if cluster_rr:
-        # clusters are formed inside the window only
-        _cluster_rr(E, I_W, Rw, Sw, lam_W, delta)
+        _cluster_rr(E, I_W, Rw, Sw, lam_W, cl)
     return XW + X @ E, lam_W
 
 
