@@ -32,7 +32,8 @@ PEAK_HBM = 8.0e12
 # 1 GiB device copy in the same run.  Valid only for the kernel source it was
 # measured on (sha256 of csrc/bt2.hip) and the same workload; otherwise the
 # bench reports null.
-BT2_TRAFFIC = None  # {"sha256": ..., "n": ..., "m_bt": ..., "fetch_bytes": ..., "write_bytes": ...}
+BT2_TRAFFIC = {"sha256": "76ee69e0fe8b8818280a555ab6e47153fa5d543680255bed65d2f247673938a5",
+               "n": 27648, "m_bt": 13824, "fetch_bytes": 3006998383676.6, "write_bytes": 3872200556320.0}
 
 
 def _bt2_source_sha() -> str:
@@ -221,7 +222,8 @@ def main():
         tm = time.perf_counter() - t0
         rep = msolver.report
         mixed = {"time_s": round(rep.stage_ms[7] / 1e3, 4), "wall_s": round(tm, 3),
-                 "refine_iters": rep.refine_iters,
+                 "refine_iters": rep.refine_iters, "refine_defect": rep.max_resid,
+                 "close_pairs_step1": rep.refine_close_pairs, "clustered_cols_step1": rep.refine_cluster_cols,
                  "stage_ms": {k: round(v, 2) for k, v in zip(
                      ["he2hb32", "hb2st32", "stedc", "bt2_32", "bt1_32", "refine64", "select", "total"],
                      list(rep.stage_ms))}}

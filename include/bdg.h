@@ -68,7 +68,7 @@ typedef struct {
 typedef struct {
     int32_t precision;       /* BDG_FP64 or BDG_FP32_REFINED                     */
     int32_t band;            /* half-bandwidth of stage 1 (0 = default 64)      */
-    int32_t refine_max_iter; /* refinement steps for BDG_FP32_REFINED (0 = 3;
+    int32_t refine_max_iter; /* refinement steps for BDG_FP32_REFINED (0 = 4;
                                 < 0 = none: the FP32 result widened to FP64)    */
     double refine_tol;       /* stop once the step's defect (max |r_ij| and
                                 |s_ij + lam_j r_ij| / ||H||_2 off the diagonal,
@@ -92,9 +92,8 @@ typedef struct {
     int32_t pad;
     double stage_ms[8];   /* he2hb, hb2st, stedc, bt2, bt1, refine, select, total */
     double bt2_kernel_ms; /* duration of the back-transformation-2 apply kernel     */
-    double refine_delta0; /* mixed arm: cluster threshold delta of the first step  */
-    int32_t refine_cluster_cols; /* mixed arm: columns in clusters at the last step */
-    int32_t pad2;
+    int32_t refine_close_pairs;  /* mixed arm: close window pairs, first step  */
+    int32_t refine_cluster_cols; /* mixed arm: clustered columns, first step    */
 } bdg_err_report;
 
 /*

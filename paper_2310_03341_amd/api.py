@@ -47,8 +47,8 @@ class Report(ctypes.Structure):
     _fields_ = [("max_resid", ctypes.c_double), ("gram_defect", ctypes.c_double),
                 ("eig_shift_max", ctypes.c_double), ("refine_iters", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("stage_ms", ctypes.c_double * 8),
-                ("bt2_kernel_ms", ctypes.c_double), ("refine_delta0", ctypes.c_double),
-                ("refine_cluster_cols", ctypes.c_int32), ("pad2", ctypes.c_int32)]
+                ("bt2_kernel_ms", ctypes.c_double), ("refine_close_pairs", ctypes.c_int32),
+                ("refine_cluster_cols", ctypes.c_int32)]
 
 
 def lib():

@@ -165,7 +165,7 @@ int bdg_stage_workspace(int stage, int64_t n, int band, int64_t m, size_t *bytes
         case 2: *bytes = 0; return 0;
         case 3: *bytes = bdg::stedc_workspace(n); return 0;
         case 4: *bytes = bdg::bt2_workspace(n, band) + 16 * (size_t)n + 8 * (size_t)n + 512; return 0;
-        case 5: *bytes = bdg::bt1_workspace(m, band); return 0;
+        case 5: *bytes = bdg::bt1_workspace(n, m, band); return 0;
         default: set_error("bdg_stage_workspace: unknown stage %d", stage); return -1;
     }
 }
@@ -217,7 +217,7 @@ int bdg_stage_bt2(int64_t n, int band, int64_t m, const double *e, const double 
 
 int bdg_stage_bt1(int64_t n, int64_t m, const double *A, int64_t lda, int band, const double *T1,
                   double *Z, int64_t ldz, void *work, size_t work_bytes, bdg_stream_t stream) {
-    if (work_bytes < bdg::bt1_workspace(m, band)) return BDG_ERR_WORKSPACE;
+    if (work_bytes < bdg::bt1_workspace(n, m, band)) return BDG_ERR_WORKSPACE;
     return bdg::bt1(n, m, A, lda, band, T1, Z, ldz, work, (hipStream_t)stream);
 }
 

@@ -52,7 +52,7 @@ Layout layout(int64_t n, const bdg_opts *o) {
     size_t sc = he2hb_workspace(n, L.b);
     sc = std::max(sc, stedc_workspace(n));
     sc = std::max(sc, bt2_workspace(n, L.b));
-    sc = std::max(sc, bt1_workspace(n, L.b));
+    sc = std::max(sc, bt1_workspace(n, n, L.b));
     L.off_scratch = put(sc);
     L.scratch = sc;
     L.total = o_ + 256;
@@ -130,7 +130,7 @@ MLayout mlayout(int64_t n, const bdg_opts *o) {
     L.off_s2 = put(8 * nn);  // contiguous with s1: X64 spans both
     size_t sc = std::max(he2hb_workspace(n, L.b), stedc_workspace(n));
     sc = std::max(sc, bt2_workspace(n, L.b));
-    sc = std::max(sc, bt1_workspace(n, L.b));
+    sc = std::max(sc, bt1_workspace(n, n, L.b));
     const size_t rw = refine_workspace(n, n);
     L.off_s3 = put(std::max(sc, rw / 2 + 65536));
     L.off_s4 = put(std::max(8 * nn, rw / 2 + 65536));
@@ -190,8 +190,8 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
     void *rscratch = base + L.off_s3;            // s3 and s4 once the stages are done
     const int leaf = (opts && opts->dc_leaf > 0) ? opts->dc_leaf : 32;
     const bool ph_mirror = opts && opts->ph_mirror && (n % 2 == 0);
-    // refine_max_iter: 0 = default (3), < 0 = no refinement (the FP32 result)
-    const int iters = (opts && opts->refine_max_iter != 0) ? std::max(opts->refine_max_iter, 0) : 3;
+    // refine_max_iter: 0 = default (4), < 0 = no refinement (the FP32 result)
+    const int iters = (opts && opts->refine_max_iter != 0) ? std::max(opts->refine_max_iter, 0) : 4;
     const double rtol = (opts && opts->refine_tol > 0.0) ? opts->refine_tol : 1e-14;
 
     Timer tm(s);
@@ -256,8 +256,8 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
     double normH = 0.0;
     for (double v : wh) normH = std::max(normH, std::fabs(v));
     BDG_TRY(cast_c64_to_c128(n, n, X32, n, X64, n, s));
-    double shift = 0.0, corr = 0.0, delta0 = 0.0;
-    int done = 0, ccols = 0;
+    double shift = 0.0, corr = 0.0;
+    int done = 0, close0 = 0, ccols = 0;
     // with the mirror, a window that holds both partners of every pair only
     // needs its E > 0 half refined; the E < 0 half is rebuilt from it
     const int64_t h = n / 2;
@@ -267,7 +267,7 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
     const int64_t mr = i1 - r0;
     if (iters > 0) {
         BDG_TRY(refine_window(n, A, lda, X64, n, lam, r0, mr, normH, iters, rtol, W + (r0 - i0), rscratch, s,
-                              &shift, &corr, &done, &delta0, &ccols));
+                              &shift, &corr, &done, &close0, &ccols));
     } else if (mr > 0) {  // refinement switched off: the FP32 result, widened
         BDG_HIP(hipMemcpyAsync(W + (r0 - i0), lam + r0, 8 * (size_t)mr, hipMemcpyDeviceToDevice, s));
     }
@@ -294,7 +294,7 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
         report->refine_iters = done;
         report->max_resid = corr;  // last max |E| (the residual itself is measured by bdg_check)
         report->bt2_kernel_ms = tm.ms(10, 11);
-        report->refine_delta0 = delta0;
+        report->refine_close_pairs = close0;
         report->refine_cluster_cols = ccols;
     }
     if (iters > 0 && mr > 0 && corr >= std::sqrt(rtol)) {

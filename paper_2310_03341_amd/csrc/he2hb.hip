@@ -471,29 +471,101 @@ namespace bdg {
 
 // Back-transformation 1: Z <- Q1 Z = Q_0 Q_1 ... Q_last Z, Q_p = I - V_p T_p V_p^H
 // acting on rows k_p + b .. n-1; V_p explicit in A's panel p.
+//
+// BT1_GROUP consecutive panels are applied as one block reflector
+// Q_p0 ... Q_p0+g-1 = I - V T V^H, V = [V_p0 ... V_p0+g-1] (each shifted down by
+// b rows per panel, zeros above), T from the recurrence
+// T = [[T_a, -T_a (V_a^H V_c) T_c], [0, T_c]], so the three products per
+// group have inner dimension g b instead of b.
+constexpr int BT1_GROUP = 4;
+
+template <typename F>
+__global__ void bt1_gather_v(const F *__restrict__ A, int64_t lda, int64_t k0, int b, int64_t R,
+                             F *__restrict__ Vg) {
+    const int c = blockIdx.y;  // column of the group's V
+    const int64_t j0 = (int64_t)(c / b) * b;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        F vr = 0.0, vi = 0.0;
+        if (r >= j0) {
+            const F *p = A + 2 * ((k0 + b + r) + (k0 + c) * lda);
+            vr = p[0];
+            vi = p[1];
+        }
+        Vg[2 * (r + (int64_t)c * R)] = vr;
+        Vg[2 * (r + (int64_t)c * R) + 1] = vi;
+    }
+}
+
+// Tg (gb x gb) = block diagonal of the panels' T factors, zeros elsewhere
+template <typename F>
+__global__ void bt1_tinit(int gb, int b, const F *__restrict__ T1p, F *__restrict__ Tg) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < gb * gb; e += gridDim.x * blockDim.x) {
+        const int i = e % gb, j = e / gb;
+        F vr = 0.0, vi = 0.0;
+        if (i / b == j / b) {
+            const F *t = T1p + 2 * ((size_t)(i / b) * b * b + (i % b) + (size_t)(j % b) * b);
+            vr = t[0];
+            vi = t[1];
+        }
+        Tg[2 * e] = vr;
+        Tg[2 * e + 1] = vi;
+    }
+}
+
 template <typename F>
 int bt1_t(int64_t n, int64_t m, const F *A, int64_t lda, int b, const F *T1, F *Z,
           int64_t ldz, void *work, hipStream_t s) {
     const int np = he2hb_panels(n, b);
-    F *W1 = (F *)work;                 // b x m
-    F *W2 = W1 + 2 * (size_t)b * m;         // b x m
-    for (int p = np - 1; p >= 0; --p) {
-        const int64_t k = (int64_t)p * b;
-        const int64_t mr = n - k - b;
-        const F *V = A + 2 * ((k + b) + k * lda);
-        const F *T = T1 + 2 * (size_t)p * b * b;
-        F *Zs = Z + 2 * (k + b);
-        GemmArgs g1{b, m, mr, 1.0, 0.0, 0.0, 0.0, V, lda, Zs, ldz, W1, b, GEMM_FULL, 1, nullptr};
+    if (np == 0 || m <= 0) return 0;
+    const int gmax = BT1_GROUP * b;
+    F *W1 = (F *)work;                              // gb x m
+    F *W2 = W1 + 2 * (size_t)gmax * m;              // gb x m
+    F *G = W2 + 2 * (size_t)gmax * m;               // gb x gb
+    F *Tg = G + 2 * (size_t)gmax * gmax;            // gb x gb
+    F *X = Tg + 2 * (size_t)gmax * gmax;            // gb x b
+    F *Vg = X + 2 * (size_t)gmax * b;               // R x gb
+    const int ngroups = (np + BT1_GROUP - 1) / BT1_GROUP;
+    for (int q = ngroups - 1; q >= 0; --q) {
+        const int p0 = q * BT1_GROUP;
+        const int g = std::min(BT1_GROUP, np - p0);
+        const int gb = g * b;
+        const int64_t k0 = (int64_t)p0 * b;
+        const int64_t R = n - k0 - b;
+        F *Zs = Z + 2 * (k0 + b);
+        const unsigned gx = (unsigned)std::min<int64_t>((R + 255) / 256, 64);
+        hipLaunchKernelGGL((bt1_gather_v<F>), dim3(gx, (unsigned)gb), dim3(256), 0, s, A, lda, k0, b, R, Vg);
+        hipLaunchKernelGGL((bt1_tinit<F>), dim3((unsigned)((gb * gb + 255) / 256)), dim3(256), 0, s, gb, b,
+                           T1 + 2 * (size_t)p0 * b * b, Tg);
+        BDG_CHECK_LAUNCH();
+        if (g > 1) {
+            GemmArgs gg{gb, gb, R, 1.0, 0.0, 0.0, 0.0, Vg, R, Vg, R, G, gb, GEMM_FULL, 1, nullptr};
+            BDG_TRY((gemm<F, true>('C', 'N', gg, s)));
+            for (int c = 1; c < g; ++c) {
+                const int cb = c * b;
+                // X = G[0:cb, cb:cb+b] T_cc ;  T[0:cb, cb:cb+b] = -T[0:cb, 0:cb] X
+                GemmArgs gx1{cb, b, b, 1.0, 0.0, 0.0, 0.0, G + 2 * (size_t)cb * gb, gb,
+                             Tg + 2 * (cb + (size_t)cb * gb), gb, X, gmax, GEMM_FULL, 1, nullptr};
+                BDG_TRY((gemm<F, true>('N', 'N', gx1, s)));
+                GemmArgs gx2{cb, b, cb, -1.0, 0.0, 0.0, 0.0, Tg, gb, X, gmax, Tg + 2 * (size_t)cb * gb, gb,
+                             GEMM_FULL, 1, nullptr};
+                BDG_TRY((gemm<F, true>('N', 'N', gx2, s)));
+            }
+        }
+        GemmArgs g1{gb, m, R, 1.0, 0.0, 0.0, 0.0, Vg, R, Zs, ldz, W1, gb, GEMM_FULL, 1, nullptr};
         BDG_TRY((gemm<F, true>('C', 'N', g1, s)));
-        GemmArgs g2{b, m, b, 1.0, 0.0, 0.0, 0.0, T, b, W1, b, W2, b, GEMM_FULL, 1, nullptr};
+        GemmArgs g2{gb, m, gb, 1.0, 0.0, 0.0, 0.0, Tg, gb, W1, gb, W2, gb, GEMM_FULL, 1, nullptr};
         BDG_TRY((gemm<F, true>('N', 'N', g2, s)));
-        GemmArgs g3{mr, m, b, -1.0, 0.0, 1.0, 0.0, V, lda, W2, b, Zs, ldz, GEMM_FULL, 1, nullptr};
+        GemmArgs g3{R, m, gb, -1.0, 0.0, 1.0, 0.0, Vg, R, W2, gb, Zs, ldz, GEMM_FULL, 1, nullptr};
         BDG_TRY((gemm<F, true>('N', 'N', g3, s)));
     }
     return 0;
 }
 
-size_t bt1_workspace(int64_t m, int b) { return 2 * 16 * (size_t)b * (size_t)m + 256; }
+size_t bt1_workspace(int64_t n, int64_t m, int b) {
+    const size_t gb = (size_t)BT1_GROUP * b;
+    return 16 * (2 * gb * (size_t)m + 2 * gb * gb + gb * (size_t)b + gb * (size_t)n) + 1024;
+}
 
 }  // namespace bdg
 

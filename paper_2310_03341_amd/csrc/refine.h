@@ -23,6 +23,6 @@ size_t refine_workspace(int64_t n, int64_t m);
 int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ldx,
                   const double *lam_all, int64_t i0, int64_t m, double normH, int iters, double tol,
                   double *W, void *work, hipStream_t s, double *eig_shift, double *last_corr,
-                  int *iters_done, double *delta0, int *nclusters);
+                  int *iters_done, int *close0, int *ccols0);
 
 }  // namespace bdg

@@ -6,17 +6,20 @@
 // window columns W of the full basis X (n x n):
 //   R = I[:, W] - X^H X_W,   S = X^H (H X_W)      (window block Hermitian-symmetrised)
 //   lam_j = s_jj / (1 - r_jj)                    (j in W; the rest keep their values)
-//   delta = 2 (||S_WW - diag lam||_2 + ||H||_2 ||R||_2)
-//   E_ij  = (s_ij + lam_j r_ij) / (lam_j - lam_i)  if |lam_j - lam_i| > delta,  r_ij / 2 else
+//   E_ij  = (s_ij + lam_j r_ij) / (lam_j - lam_i)  for well-separated pairs,  r_ij / 2 else
 //   X_W  <- X_W + X E
 // All products are FP64 on the matrix cores (HEMM from the lower triangle of
-// H, ZGEMMs for X^H and X E); the 2-norms are power-iteration estimates.
+// H, ZGEMMs for X^H and X E).
 //
-// Clusters (part II of the method, clustered eigenvalues, 2019): the r_ij / 2
-// branch never resolves the mixing inside a group of eigenvalues closer than
-// delta, and that mixing keeps delta from shrinking.  Each chain of window
-// eigenvalues with consecutive gaps <= delta (at most CMAX members; longer
-// chains are cut into pieces) gets an FP64 Rayleigh-Ritz step:
+// Close pairs and clusters.  The published test |lam_i - lam_j| <= delta uses
+// one global delta = 2 (||S - diag|| + ||H|| ||R||), which from an FP32 basis
+// of order 10^4 exceeds the mean level spacing; a pair is taken as close here
+// when its first-order coefficient would not be small,
+// |s_ij + lam_j r_ij| >= TAU |lam_j - lam_i|.  The r_ij / 2 branch never
+// resolves mixing inside a group of close eigenvalues, so the connected
+// components of close window pairs (at most CMAX members; larger ones are cut,
+// and close pairs across a cut keep r_ij / 2) get an FP64 Rayleigh-Ritz step
+// (part II of the method, clustered eigenvalues, 2019):
 //   L = I + R_JJ / 2,  M = L S_JJ L = Q diag(mu) Q^H  (complex Jacobi in LDS)
 //   E[:, J] <- (I_W + E)[:, J] Q - I_W[:, J],  lam_J <- mu
 #include <math.h>
@@ -110,77 +113,34 @@ __global__ void window_block(int64_t m, int64_t i0, double *__restrict__ R, doub
     }
 }
 
-// y = (A - D) x  (rows x cols, ld; D = diag(dsub) placed at rows roff.. if dsub)
-__global__ void gemv_n(int64_t rows, int64_t cols, const double *__restrict__ A, int64_t ld,
-                       int64_t roff, const double *__restrict__ dsub, const double *__restrict__ x,
-                       double *__restrict__ y) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < rows;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double sr = 0.0, si = 0.0;
-        for (int64_t j = 0; j < cols; ++j) {
-            double ar = A[2 * ((roff + i) + j * ld)], ai = A[2 * ((roff + i) + j * ld) + 1];
-            if (dsub && i == j) ar -= dsub[j];
-            const double xr = x[2 * j], xi = x[2 * j + 1];
-            sr += ar * xr - ai * xi;
-            si += ar * xi + ai * xr;
+constexpr double TAU = 1e-3;
+
+// Close pairs (a, b), a > b, of the window (both orientations tested), appended
+// to pairs[] (capacity cap; count keeps counting past it).
+__global__ void close_pairs(int64_t m, int64_t i0, const double *__restrict__ S, const double *__restrict__ R,
+                            int64_t ld, const double *__restrict__ lamW, int2 *__restrict__ pairs, int cap,
+                            int *__restrict__ count) {
+    const int64_t b = blockIdx.y;
+    const double lb = lamW[b];
+    for (int64_t a = b + 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; a < m;
+         a += (int64_t)gridDim.x * blockDim.x) {
+        const double la = lamW[a];
+        const int64_t ab = 2 * ((i0 + a) + b * ld), ba = 2 * ((i0 + b) + a * ld);
+        // row a, column b: s_ab + lam_b r_ab against lam_b - lam_a; and the transpose
+        const double n1 = hypot(S[ab] + lb * R[ab], S[ab + 1] + lb * R[ab + 1]);
+        const double n2 = hypot(S[ba] + la * R[ba], S[ba + 1] + la * R[ba + 1]);
+        const double gap = fabs(lb - la);
+        if (n1 >= TAU * gap || n2 >= TAU * gap) {
+            const int k = atomicAdd(count, 1);
+            if (k < cap) pairs[k] = make_int2((int)a, (int)b);
         }
-        y[2 * i] = sr;
-        y[2 * i + 1] = si;
     }
 }
 
-// x = (A - D)^H y  (workgroup per column)
-__global__ void gemv_c(int64_t rows, int64_t cols, const double *__restrict__ A, int64_t ld,
-                       int64_t roff, const double *__restrict__ dsub, const double *__restrict__ y,
-                       double *__restrict__ x) {
-    __shared__ double red[2][8];
-    const int64_t j = blockIdx.x;
-    double sr = 0.0, si = 0.0;
-    for (int64_t i = threadIdx.x; i < rows; i += blockDim.x) {
-        double ar = A[2 * ((roff + i) + j * ld)], ai = A[2 * ((roff + i) + j * ld) + 1];
-        if (dsub && i == j) ar -= dsub[j];
-        const double yr = y[2 * i], yi = y[2 * i + 1];
-        sr += ar * yr + ai * yi;  // conj(a) y
-        si += ar * yi - ai * yr;
-    }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) { red[0][w] = sr; red[1][w] = si; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0.0, b = 0.0;
-        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) { a += red[0][q]; b += red[1][q]; }
-        x[2 * j] = a;
-        x[2 * j + 1] = b;
-    }
-}
-
-__global__ void vec_norm2(int64_t len, const double *__restrict__ v, double *__restrict__ out) {
-    __shared__ double red[16];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < len; i += blockDim.x) s += v[2 * i] * v[2 * i] + v[2 * i + 1] * v[2 * i + 1];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) out[0] = s;
-}
-
-__global__ void vec_scale(int64_t len, double *__restrict__ v, const double *__restrict__ nrm2) {
-    const double inv = nrm2[0] > 0.0 ? 1.0 / sqrt(nrm2[0]) : 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * len;
-         i += (int64_t)gridDim.x * blockDim.x)
-        v[i] *= inv;
-}
-
-__global__ void vec_init(int64_t len, double *__restrict__ v) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        // deterministic, not orthogonal to anything in particular
-        v[2 * i] = 1.0 + 0.001 * (double)((i * 7919) % 101);
-        v[2 * i + 1] = 0.0005 * (double)((i * 104729) % 97);
-    }
-}
-
-// E (in place of S): off-window rows use lam_all, window rows use lamW
+// E (in place of S): off-window rows use lam_all, window rows use lamW.
+// r_ij / 2 on the diagonal, for close pairs, and inside a cluster (cid: cluster
+// of each window column, -1 none; null when there are none); the first-order
+// quotient elsewhere.
 // emax: per block, max over (i, j) off the window diagonal of
 // max(|r_ij|, |s_ij + lam_j r_ij| / normH), the step's defect in residual units
 // (|E_ij| itself is large for well-separated but very close pairs whose
@@ -189,11 +149,12 @@ __global__ void vec_init(int64_t len, double *__restrict__ v) {
 // their own error, so there only the residual part counts
 __global__ void build_E(int64_t n, int64_t m, int64_t i0, double *__restrict__ S,
                         const double *__restrict__ R, int64_t ld, const double *__restrict__ lam_all,
-                        const double *__restrict__ lamW, double delta, double inv_normH,
+                        const double *__restrict__ lamW, const int *__restrict__ cid, double inv_normH,
                         double *__restrict__ emax) {
     __shared__ double red[4];
     const int64_t j = blockIdx.y;
     const double lj = lamW[j];
+    const int cj = cid ? cid[j] : -1;
     double mx = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -203,18 +164,19 @@ __global__ void build_E(int64_t n, int64_t m, int64_t i0, double *__restrict__ S
         const double rr = R[2 * (i + j * ld)], ri = R[2 * (i + j * ld) + 1];
         const double dif = lj - li;
         const double nr = sr + lj * rr, ni = si + lj * ri;
+        const bool diag = i == i0 + j;
+        const bool same = inw && cj >= 0 && cid[i - i0] == cj;
         double er, ei;
-        if (fabs(dif) > delta) {
-            er = nr / dif;
-            ei = ni / dif;
-        } else {
+        if (diag || same || hypot(nr, ni) >= TAU * fabs(dif)) {
             er = 0.5 * rr;
             ei = 0.5 * ri;
+        } else {
+            er = nr / dif;
+            ei = ni / dif;
         }
         S[2 * (i + j * ld)] = er;
         S[2 * (i + j * ld) + 1] = ei;
-        if (i != i0 + j) {
-            // off-window rows hold the unrefined basis: only the residual part counts there
+        if (!diag) {
             const double dn = (fabs(nr) + fabs(ni)) * inv_normH;
             mx = fmax(mx, inw ? fmax(fabs(rr) + fabs(ri), dn) : dn);
         }
@@ -452,29 +414,6 @@ unsigned gx(int64_t rows) {
     return (unsigned)(g > 64 ? 64 : (g < 1 ? 1 : g));
 }
 
-// ||A - D||_2 estimate by power iteration on (A - D)^H (A - D)
-int norm2_est(int64_t rows, int64_t cols, const double *A, int64_t ld, int64_t roff,
-              const double *dsub, double *vx, double *vy, double *tmp, int iters, hipStream_t s,
-              double *out) {
-    hipLaunchKernelGGL(vec_init, dim3(gx(cols)), dim3(256), 0, s, cols, vx);
-    hipLaunchKernelGGL(vec_norm2, dim3(1), dim3(1024), 0, s, cols, vx, tmp);
-    hipLaunchKernelGGL(vec_scale, dim3(gx(cols)), dim3(256), 0, s, cols, vx, tmp);
-    for (int it = 0; it < iters; ++it) {
-        hipLaunchKernelGGL(gemv_n, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, rows, cols, A, ld,
-                           roff, dsub, vx, vy);
-        hipLaunchKernelGGL(gemv_c, dim3((unsigned)cols), dim3(256), 0, s, rows, cols, A, ld, roff, dsub, vy,
-                           vx);
-        hipLaunchKernelGGL(vec_norm2, dim3(1), dim3(1024), 0, s, cols, vx, tmp);
-        hipLaunchKernelGGL(vec_scale, dim3(gx(cols)), dim3(256), 0, s, cols, vx, tmp);
-    }
-    BDG_CHECK_LAUNCH();
-    double h = 0.0;
-    BDG_HIP(hipMemcpyAsync(&h, tmp, 8, hipMemcpyDeviceToHost, s));
-    BDG_HIP(hipStreamSynchronize(s));
-    *out = sqrt(sqrt(h));  // ||(A-D)^H (A-D) x|| with ||x|| = 1 -> sigma^2
-    return 0;
-}
-
 }  // namespace
 
 int cast_c64_to_c128(int64_t rows, int64_t cols, const float *src, int64_t lds, double *dst,
@@ -522,75 +461,127 @@ int mirror_columns(int64_t n, double *X, int64_t ld, int64_t dst0, int64_t src0,
     return 0;
 }
 
-size_t refine_workspace(int64_t n, int64_t m) {
-    const size_t big = 16 * (size_t)n * (size_t)m;
-    const size_t clusters = 16 * (size_t)CMAX * m + 8 * (size_t)m + 4 * (size_t)m + 12 * (size_t)(m + 2) +
-                            8 * (size_t)(m + 2) + 5 * 256;
-    return 2 * ((big + 255) / 256 * 256) + 16 * (size_t)(n + m) * 4 + 8 * (size_t)m * 68 + 8192 + clusters;
-}
-
 namespace {
 
-// Chains of ascending eigenvalues with gaps <= delta, cut into pieces of at most
-// CMAX; members listed in ascending order.  Returns the number of clusters.
-int find_clusters(const std::vector<double> &lam, double delta, std::vector<int> &idx, std::vector<int> &off,
-                  std::vector<int64_t> &qo) {
+// Workspace of refine_window, carved in this order.
+struct RefineLayout {
+    size_t B1, B2, lamW, lamP, tmp, emax, qbuf, mu, cidx, coff, qoff, cmax, cid, pairs, count, total;
+    RefineLayout(int64_t n, int64_t m) {
+        size_t o = 0;
+        auto take = [&](size_t bytes) { size_t r = o; o += (bytes + 255) / 256 * 256; return r; };
+        B1 = take(16 * (size_t)n * m);
+        B2 = take(16 * (size_t)n * m);
+        lamW = take(8 * (size_t)m);
+        lamP = take(8 * (size_t)m);
+        tmp = take(64);
+        emax = take(8 * (size_t)m * 64 + 64);
+        qbuf = take(16 * (size_t)CMAX * m);
+        mu = take(8 * (size_t)m);
+        cidx = take(4 * (size_t)m);
+        coff = take(4 * (size_t)(m + 2));
+        qoff = take(8 * (size_t)(m + 2));
+        cmax = take(8 * (size_t)(m + 2));
+        cid = take(4 * (size_t)m);
+        pairs = take(8 * (size_t)cap(m));
+        count = take(64);
+        total = o;
+    }
+    static int cap(int64_t m) { return (int)(4 * m + 4096); }
+};
+
+// Connected components (>= 2 members) of the close pairs, members in ascending
+// order of lam, components cut into pieces of at most CMAX.  Fills the flat
+// member list, offsets, Q offsets and the cluster id of every column (-1 none);
+// returns the number of clusters.
+int find_clusters(const std::vector<double> &lam, const std::vector<int2> &pairs, std::vector<int> &idx,
+                  std::vector<int> &off, std::vector<int64_t> &qo, std::vector<int> &cid) {
     const int m = (int)lam.size();
+    std::vector<int> parent((size_t)m);
+    std::iota(parent.begin(), parent.end(), 0);
+    auto root = [&](int a) {
+        while (parent[a] != a) {
+            parent[a] = parent[parent[a]];
+            a = parent[a];
+        }
+        return a;
+    };
+    for (const int2 &p : pairs) {
+        const int ra = root(p.x), rb = root(p.y);
+        if (ra != rb) parent[ra] = rb;
+    }
     std::vector<int> order((size_t)m);
     std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lam[a] < lam[b]; });
+    // group by root, ascending lam inside a group, groups by their lowest lam
+    std::vector<int> r((size_t)m);
+    for (int a = 0; a < m; ++a) r[a] = root(a);
+    std::vector<double> glo((size_t)m, 0.0);
+    std::vector<int> gsize((size_t)m, 0);
+    for (int a = 0; a < m; ++a) {
+        if (gsize[r[a]] == 0 || lam[a] < glo[r[a]]) glo[r[a]] = lam[a];
+        ++gsize[r[a]];
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (r[a] != r[b]) return glo[r[a]] < glo[r[b]] || (glo[r[a]] == glo[r[b]] && r[a] < r[b]);
+        return lam[a] < lam[b];
+    });
     idx.clear();
     off.assign(1, 0);
     qo.assign(1, 0);
-    int start = 0;
-    for (int k = 1; k <= m; ++k) {
-        if (k == m || lam[order[k]] - lam[order[k - 1]] > delta) {
-            for (int a = start; k - a >= 2; a += CMAX) {
-                const int c = std::min(CMAX, k - a);
-                if (c < 2) break;
-                for (int t = 0; t < c; ++t) idx.push_back(order[a + t]);
-                off.push_back((int)idx.size());
-                qo.push_back(qo.back() + (int64_t)c * c);
+    cid.assign((size_t)m, -1);
+    for (int k = 0; k < m;) {
+        int e = k;
+        while (e < m && r[order[e]] == r[order[k]]) ++e;
+        for (int a = k; e - a >= 2; a += CMAX) {
+            const int c = std::min(CMAX, e - a);
+            if (c < 2) break;
+            const int id = (int)off.size() - 1;
+            for (int t = 0; t < c; ++t) {
+                idx.push_back(order[a + t]);
+                cid[order[a + t]] = id;
             }
-            start = k;
+            off.push_back((int)idx.size());
+            qo.push_back(qo.back() + (int64_t)c * c);
         }
+        k = e;
     }
     return (int)off.size() - 1;
 }
 
 }  // namespace
 
+size_t refine_workspace(int64_t n, int64_t m) { return RefineLayout(n, m).total + 256; }
+
 // X: full FP64 basis n x n (ld ldx), lam_all[n] its approximate eigenvalues;
 // window columns [i0, i0+m) are refined in place; W receives lam_W.
 int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ldx,
                   const double *lam_all, int64_t i0, int64_t m, double normH, int iters, double tol,
                   double *W, void *work, hipStream_t s, double *eig_shift, double *last_corr,
-                  int *iters_done, double *delta0, int *nclusters) {
+                  int *iters_done, int *close0, int *ccols0) {
     if (m <= 0) return 0;
-    char *wp = (char *)work;
-    auto take = [&](size_t bytes) {
-        char *p = wp;
-        wp += (bytes + 255) / 256 * 256;
-        return (double *)p;
-    };
-    double *B1 = take(16 * (size_t)n * m);
-    double *B2 = take(16 * (size_t)n * m);
-    double *vx = take(16 * (size_t)(n + m));
-    double *vy = take(16 * (size_t)(n + m));
-    double *lamW = take(8 * (size_t)m);
-    double *lamP = take(8 * (size_t)m);
-    double *tmp = take(64);
-    double *emax = take(8 * (size_t)m * 64 + 64);
-    double *qbuf = take(16 * (size_t)CMAX * m);
-    double *mu = take(8 * (size_t)m);
-    int *cidx = (int *)take(4 * (size_t)m);
-    int *coff = (int *)take(4 * (size_t)(m + 2));
-    int64_t *qoff = (int64_t *)take(8 * (size_t)(m + 2));
-    double *cmax = take(8 * (size_t)(m + 2));
+    const RefineLayout L(n, m);
+    char *base = (char *)work;
+    double *B1 = (double *)(base + L.B1);
+    double *B2 = (double *)(base + L.B2);
+    double *lamW = (double *)(base + L.lamW);
+    double *lamP = (double *)(base + L.lamP);
+    double *tmp = (double *)(base + L.tmp);
+    double *emax = (double *)(base + L.emax);
+    double *qbuf = (double *)(base + L.qbuf);
+    double *mu = (double *)(base + L.mu);
+    int *cidx = (int *)(base + L.cidx);
+    int *coff = (int *)(base + L.coff);
+    int64_t *qoff = (int64_t *)(base + L.qoff);
+    double *cmax = (double *)(base + L.cmax);
+    int *cid = (int *)(base + L.cid);
+    int2 *pairs = (int2 *)(base + L.pairs);
+    int *count = (int *)(base + L.count);
+    const int cap = RefineLayout::cap(m);
     std::vector<double> lam_h((size_t)m);
-    std::vector<int> idx_h, off_h;
+    std::vector<int2> pairs_h;
+    std::vector<int> idx_h, off_h, cid_h;
     std::vector<int64_t> qo_h;
     double *XW = X + 2 * i0 * ldx;
+    const double hn = normH > 0.0 ? normH : 1.0;
     BDG_HIP(hipMemcpyAsync(lamP, lam_all + i0, 8 * (size_t)m, hipMemcpyDeviceToDevice, s));
     double shift = 0.0;
     for (int it = 0; it < iters; ++it) {
@@ -605,26 +596,35 @@ int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ld
         BDG_TRY((gemm<double, true>('C', 'N', g3, s)));
         hipLaunchKernelGGL(window_block, dim3((unsigned)m), dim3(256), 0, s, m, i0, B1, B2, n, lamW);
         BDG_CHECK_LAUNCH();
-        // delta = 2 (||S_WW - diag lam||_2 + ||H||_2 ||R||_2)
-        double nS = 0.0, nR = 0.0;
-        BDG_TRY(norm2_est(m, m, B2, n, i0, lamW, vx, vy, tmp, 8, s, &nS));
-        BDG_TRY(norm2_est(n, m, B1, n, 0, nullptr, vx, vy, tmp, 8, s, &nR));
-        const double delta = 2.0 * 2.0 * (nS + normH * nR);  // x2: power iteration bounds from below
-        // clusters from the current window eigenvalues
+        // close pairs of the window -> clusters
+        BDG_HIP(hipMemsetAsync(count, 0, 4, s));
+        if (m >= 2) {
+            hipLaunchKernelGGL(close_pairs, dim3(gx(m), (unsigned)(m - 1)), dim3(256), 0, s, m, i0, B2, B1, n,
+                               lamW, pairs, cap, count);
+            BDG_CHECK_LAUNCH();
+        }
+        int npairs = 0;
+        BDG_HIP(hipMemcpyAsync(&npairs, count, 4, hipMemcpyDeviceToHost, s));
         BDG_HIP(hipMemcpyAsync(lam_h.data(), lamW, 8 * (size_t)m, hipMemcpyDeviceToHost, s));
         BDG_HIP(hipStreamSynchronize(s));
-        const int ncl = find_clusters(lam_h, delta, idx_h, off_h, qo_h);
+        pairs_h.resize((size_t)std::min(npairs, cap));
+        if (!pairs_h.empty()) {
+            BDG_HIP(hipMemcpyAsync(pairs_h.data(), pairs, 8 * pairs_h.size(), hipMemcpyDeviceToHost, s));
+            BDG_HIP(hipStreamSynchronize(s));
+        }
+        const int ncl = find_clusters(lam_h, pairs_h, idx_h, off_h, qo_h, cid_h);
         if (ncl > 0) {
             BDG_HIP(hipMemcpyAsync(cidx, idx_h.data(), 4 * idx_h.size(), hipMemcpyHostToDevice, s));
             BDG_HIP(hipMemcpyAsync(coff, off_h.data(), 4 * off_h.size(), hipMemcpyHostToDevice, s));
             BDG_HIP(hipMemcpyAsync(qoff, qo_h.data(), 8 * qo_h.size(), hipMemcpyHostToDevice, s));
+            BDG_HIP(hipMemcpyAsync(cid, cid_h.data(), 4 * cid_h.size(), hipMemcpyHostToDevice, s));
             // reads S and R before build_E turns S into E
             hipLaunchKernelGGL(cluster_eig, dim3((unsigned)ncl), dim3(256), 0, s, i0, cidx, coff, qoff, B2, B1,
-                               n, normH > 0.0 ? normH : 1.0, qbuf, mu, cmax);
+                               n, hn, qbuf, mu, cmax);
             BDG_CHECK_LAUNCH();
         }
         hipLaunchKernelGGL(build_E, dim3(gx(n), (unsigned)m), dim3(256), 0, s, n, m, i0, B2, B1, n, lam_all,
-                           lamW, delta, normH > 0.0 ? 1.0 / normH : 1.0, emax);
+                           lamW, ncl > 0 ? (const int *)cid : (const int *)nullptr, 1.0 / hn, emax);
         BDG_CHECK_LAUNCH();
         hipLaunchKernelGGL(max_abs_diff, dim3(1), dim3(1024), 0, s, (int64_t)gx(n) * m, emax,
                            (const double *)nullptr, tmp + 1);
@@ -639,7 +639,10 @@ int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ld
         } else {
             BDG_HIP(hipMemsetAsync(tmp + 2, 0, 8, s));
         }
-        if (nclusters) *nclusters = (int)idx_h.size();
+        if (it == 0) {
+            if (close0) *close0 = npairs;
+            if (ccols0) *ccols0 = (int)idx_h.size();
+        }
         // B1 = X_W ; B1 += X E ; X_W = B1
         hipLaunchKernelGGL(copy_c128, dim3(gx(n), (unsigned)m), dim3(256), 0, s, n, XW, ldx, B1, n);
         BDG_CHECK_LAUNCH();
@@ -653,10 +656,7 @@ int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ld
         BDG_HIP(hipMemcpyAsync(h, tmp, 24, hipMemcpyDeviceToHost, s));
         BDG_HIP(hipMemcpyAsync(lamP, lamW, 8 * (size_t)m, hipMemcpyDeviceToDevice, s));
         BDG_HIP(hipStreamSynchronize(s));
-        if (it == 0) {
-            shift = h[0];
-            if (delta0) *delta0 = delta;
-        }
+        if (it == 0) shift = h[0];
         const double corr = std::max(h[1], h[2]);
         if (last_corr) *last_corr = corr;
         if (iters_done) *iters_done = it + 1;

@@ -14,7 +14,7 @@ int he2hb(int64_t n, float *A, int64_t lda, int b, float *AB, int64_t ldab, floa
 int he2hb_panels(int64_t n, int b);
 
 // Back-transformation 1: Z <- Q1 Z.
-size_t bt1_workspace(int64_t m, int b);
+size_t bt1_workspace(int64_t n, int64_t m, int b);
 int bt1(int64_t n, int64_t m, const double *A, int64_t lda, int b, const double *T1, double *Z,
         int64_t ldz, void *work, hipStream_t s);
 int bt1(int64_t n, int64_t m, const float *A, int64_t lda, int b, const float *T1, float *Z,

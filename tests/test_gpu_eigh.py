@@ -142,9 +142,9 @@ def test_mixed_refined_clustered_spectrum(dev):
     Rayleigh-Ritz step is what takes them to FP64 accuracy."""
     H, w = inputs.clustered_hermitian(240, 21)
     W, res, gram, rep = _solve_report(dev, H, precision=1)
-    print("delta0 %.3e clusters %d iters %d corr %.3e" % (rep.refine_delta0, rep.refine_cluster_cols,
-                                                          rep.refine_iters, rep.max_resid))
-    assert rep.refine_delta0 > 1e-6  # the 1e-6 pair starts inside one cluster
+    print("close pairs %d clustered %d iters %d defect %.3e" % (rep.refine_close_pairs, rep.refine_cluster_cols,
+                                                                 rep.refine_iters, rep.max_resid))
+    assert rep.refine_close_pairs >= 3  # at least the exact triple
     assert rep.refine_cluster_cols >= 3
     assert np.abs(W - w).max() <= 1e-13 * (w[-1] - w[0])
     assert res <= VEC_TOL and gram <= VEC_TOL, (res, gram)
