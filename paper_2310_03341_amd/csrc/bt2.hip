@@ -129,6 +129,35 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const F *_
         *(CV *)(TF + 2 * (blk * NBK * NBK + e)) = Ts[e];
 }
 
+// One 16-row tile of the Z window (rows rs + 16 rt + ...) in accumulator layout.
+template <typename F>
+__device__ __forceinline__ void load_tile(const F *__restrict__ Z, int64_t ldz, int64_t rs, int rt, int lane,
+                                          int h, bool colok, int64_t col, typename acc4<F>::type &zr,
+                                          typename acc4<F>::type &zi) {
+    typedef typename v2t<F>::type CV;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        // unconditional load (entry 0 outside the matrix) so that all loads of
+        // a window are in flight together
+        const int row = rt * 16 + mfma_row((F)0, lane, q);
+        const bool ok = (row < h) & colok;
+        const CV z = *(const CV *)(Z + (int64_t)ok * (2 * ((rs + row) + col * ldz)));
+        zr[q] = ok ? z.x : (F)0;
+        zi[q] = ok ? z.y : (F)0;
+    }
+}
+
+template <typename F>
+__device__ __forceinline__ void store_tile(F *__restrict__ Z, int64_t ldz, int64_t rs, int rt, int lane, int h,
+                                           bool colok, int64_t col, const typename acc4<F>::type &zr,
+                                           const typename acc4<F>::type &zi) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int row = rt * 16 + mfma_row((F)0, lane, q);
+        if (row < h && colok) *(typename v2t<F>::type *)(Z + 2 * ((rs + row) + col * ldz)) = mk2<F>(zr[q], zi[q]);
+    }
+}
+
 // Apply every block to a slab of SLAB columns on the FP64 matrix cores.
 // Each wave keeps its 96 x 16 window of Z in MFMA accumulator layout
 // (element r of lane l = row (l/16) + 4 r of a 16-row tile, column l%16).
@@ -136,14 +165,17 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const F *_
 // index permuted accordingly (a sum over k does not depend on its order).
 //   W  = V^H Z   (32 x 16)     W2 = T W     Z -= V W2
 // Tiles of the parallelogram V that are zero by construction are skipped.
-template <typename F>
-__global__ __launch_bounds__(256, 2) void bt2_apply(int64_t n, int b, int64_t m,
+template <typename F, int BB, int OCC>
+__global__ __launch_bounds__(256, OCC) void bt2_apply(int64_t n, int b_rt, int64_t m,
                                                  const F *__restrict__ V2,
                                                  const int64_t *__restrict__ voff, int64_t nsb,
                                                  int64_t tmax, const F *__restrict__ TF,
                                                  F *__restrict__ Z, int64_t ldz) {
     typedef typename v2t<F>::type CV;
     typedef typename acc4<F>::type A4;
+    // BB > 0: the band width is a compile-time constant, so the tile-skip tests
+    // fold and the product loops become straight-line code
+    const int b = BB > 0 ? BB : b_rt;
     __shared__ CV Vs[VLD * NBK];
     __shared__ CV Ts[NBK * NBK];
     __shared__ int64_t vb[NBK];  // reflector base of each sweep of the block
@@ -170,21 +202,24 @@ __global__ __launch_bounds__(256, 2) void bt2_apply(int64_t n, int b, int64_t m,
             const int h = (int)min((int64_t)(HT * 16), n - rs);
             __syncthreads();
             {
-                // parallelogram: 96 x 32 entries, 12 per thread, loads issued first
-                CV rv[HT * 16 * NBK / 256];
-#pragma unroll
-                for (int i = 0; i < HT * 16 * NBK / 256; ++i) {
-                    const int e = tid + 256 * i;
-                    const int r = e % (HT * 16), j = e / (HT * 16);
-                    const int o = r - j;
-                    rv[i] = mk2<F>(0.0, 0.0);
-                    if (r < h && o >= 0 && o < b && t < vt[j])
-                        rv[i] = *(const CV *)(V2 + 2 * ((vb[j] + t) * b + o));
-                }
                 CV rt4[NBK * NBK / 256];
 #pragma unroll
                 for (int i = 0; i < NBK * NBK / 256; ++i)
                     rt4[i] = *(const CV *)(TF + 2 * ((S * tmax + t) * NBK * NBK + tid + 256 * i));
+                // parallelogram: 96 x 32 entries, 12 per thread, loads issued first
+                CV rv[HT * 16 * NBK / 256];
+#pragma unroll
+                for (int i = 0; i < HT * 16 * NBK / 256; ++i) {
+                    // unconditional loads (from entry 0 when outside the
+                    // parallelogram) so that all of them are in flight at once
+                    const int e = tid + 256 * i;
+                    const int r = e % (HT * 16), j = e / (HT * 16);
+                    const int o = r - j;
+                    const int64_t vbj = vb[j], vtj = vt[j];
+                    const bool ok = (r < h) & (o >= 0) & (o < b) & (t < vtj);
+                    const CV v = *(const CV *)(V2 + (int64_t)ok * (2 * ((vbj + t) * b + o)));
+                    rv[i] = ok ? v : mk2<F>(0.0, 0.0);
+                }
 #pragma unroll
                 for (int i = 0; i < HT * 16 * NBK / 256; ++i) {
                     const int e = tid + 256 * i;
@@ -201,10 +236,10 @@ __global__ __launch_bounds__(256, 2) void bt2_apply(int64_t n, int b, int64_t m,
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int row = rt * 16 + mfma_row((F)0, lane, q);
-                    CV z = mk2<F>(0.0, 0.0);
-                    if (row < h && colok) z = *(const CV *)(Z + 2 * ((rs + row) + col * ldz));
-                    zr[rt][q] = z.x;
-                    zi[rt][q] = z.y;
+                    const bool ok = row < h && colok;
+                    const CV z = *(const CV *)(Z + (ok ? 2 * ((rs + row) + col * ldz) : 0));
+                    zr[rt][q] = ok ? z.x : (F)0;
+                    zi[rt][q] = ok ? z.y : (F)0;
                 }
             }
             __syncthreads();
@@ -276,6 +311,194 @@ __global__ __launch_bounds__(256, 2) void bt2_apply(int64_t n, int b, int64_t m,
     }
 }
 
+// Pipelined variant (FP64, b a multiple of 16, SHIFT = b / 16 tiles): while
+// the matrix cores work on block t, the loads for block t + 1 are in flight:
+// its V and T go to the other half of a double LDS buffer, and its SHIFT new
+// Z tiles (rows the current block does not touch) to registers; the window
+// rows shared by consecutive blocks stay in registers.
+template <typename F, int SHIFT>
+__global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, int64_t m,
+                                                         const F *__restrict__ V2,
+                                                         const int64_t *__restrict__ voff, int64_t nsb,
+                                                         int64_t tmax, const F *__restrict__ TF,
+                                                         F *__restrict__ Z, int64_t ldz) {
+    typedef typename v2t<F>::type CV;
+    typedef typename acc4<F>::type A4;
+    constexpr int NV = HT * 16 * NBK / 256, NT = NBK * NBK / 256;
+    constexpr int b = 16 * SHIFT;  // the launcher guarantees b_rt == 16 SHIFT
+    (void)b_rt;
+    __shared__ CV Vs[2][VLD * NBK];
+    __shared__ CV Ts[2][NBK * NBK];
+    __shared__ int64_t vb[NBK];
+    __shared__ int64_t vt[NBK];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15;
+    const int64_t j0 = (int64_t)blockIdx.x * SLAB;
+    const int64_t col = j0 + wave * 16 + li;
+    const bool colok = col < m;
+    const int64_t nsw = n - 2;
+    // V (parallelogram) and T of block (S, t) into registers.  The loads are
+    // unconditional (entry 0 outside the parallelogram) and the zeroing waits
+    // for publish(), so nothing consumes them before the products of the
+    // current block have been issued.
+    auto fetch = [&](int64_t S, int64_t t, int h, CV *rv, CV *rt, unsigned &vmask) {
+        vmask = 0;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e % (HT * 16), j = e / (HT * 16);
+            const int o = r - j;
+            const int64_t vbj = vb[j], vtj = vt[j];
+            const bool ok = (r < h) & (o >= 0) & (o < b) & (t < vtj);
+            rv[i] = *(const CV *)(V2 + (int64_t)ok * (2 * ((vbj + t) * b + o)));
+            vmask |= (unsigned)ok << i;
+        }
+#pragma unroll
+        for (int i = 0; i < NT; ++i) rt[i] = *(const CV *)(TF + 2 * ((S * tmax + t) * NBK * NBK + tid + 256 * i));
+    };
+    auto publish = [&](int buf, const CV *rv, const CV *rt, unsigned vmask) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const int e = tid + 256 * i;
+            Vs[buf][(e % (HT * 16)) + (e / (HT * 16)) * VLD] = ((vmask >> i) & 1u) ? rv[i] : mk2<F>(0.0, 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < NT; ++i) Ts[buf][tid + 256 * i] = rt[i];
+    };
+    // raw loads of one Z tile; ok bits for its 4 entries in zmask
+    auto fetch_tile = [&](int64_t rs1, int rtl, int h1, CV *raw, unsigned &zmask, int bit0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = rtl * 16 + mfma_row((F)0, lane, q);
+            const bool ok = (row < h1) & colok;
+            raw[q] = *(const CV *)(Z + (int64_t)ok * (2 * ((rs1 + row) + col * ldz)));
+            zmask |= (unsigned)ok << (bit0 + q);
+        }
+    };
+    for (int64_t S = nsb - 1; S >= 0; --S) {
+        const int64_t s0 = S * NBK;
+        const int64_t T0 = (n - 2 - s0) / b + 1;
+        if (s0 + 1 >= n) continue;
+        __syncthreads();
+        if (tid < NBK) {
+            const int64_t sw = s0 + tid;
+            vb[tid] = sw < nsw ? voff[sw] : 0;
+            vt[tid] = sw < nsw ? (n - 2 - sw) / b + 1 : 0;
+        }
+        __syncthreads();
+        A4 zr[HT], zi[HT];
+        {
+            CV rv[NV], rt[NT];
+            unsigned vmask;
+            const int h0 = (int)min((int64_t)(HT * 16), n - (s0 + 1));
+            fetch(S, 0, h0, rv, rt, vmask);
+#pragma unroll
+            for (int rtl = 0; rtl < HT; ++rtl) load_tile<F>(Z, ldz, s0 + 1, rtl, lane, h0, colok, col, zr[rtl], zi[rtl]);
+            publish(0, rv, rt, vmask);
+        }
+        __syncthreads();
+        for (int64_t t = 0; t < T0; ++t) {
+            const int64_t rs = s0 + 1 + t * b;
+            const int h = (int)min((int64_t)(HT * 16), n - rs);
+            const int buf = (int)(t & 1);
+            const bool more = t + 1 < T0 && rs + b < n;
+            CV rv[NV], rt[NT];
+            CV zraw[SHIFT][4];
+            unsigned vmask = 0, zmask = 0;
+            if (more) {
+                const int h1 = (int)min((int64_t)(HT * 16), n - (rs + b));
+                fetch(S, t + 1, h1, rv, rt, vmask);
+#pragma unroll
+                for (int k = 0; k < SHIFT; ++k) fetch_tile(rs + b, HT - SHIFT + k, h1, zraw[k], zmask, 4 * k);
+            }
+            const CV *V = Vs[buf];
+            const CV *T = Ts[buf];
+            // W = V^H Z
+            A4 wr[2], wi[2];
+#pragma unroll
+            for (int it = 0; it < 2; ++it) {
+                wr[it] = A4{0, 0, 0, 0};
+                wi[it] = A4{0, 0, 0, 0};
+#pragma unroll
+                for (int kt = 0; kt < HT; ++kt) {
+                    if (16 * kt + 15 < 16 * it || 16 * kt > 16 * it + 14 + b) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const CV v = V[(16 * kt + mfma_row((F)0, lane, q)) + (16 * it + li) * VLD];
+                        wr[it] = mfma16(v.x, zr[kt][q], wr[it]);
+                        wi[it] = mfma16(v.x, zi[kt][q], wi[it]);
+                        wr[it] = mfma16(v.y, zi[kt][q], wr[it]);
+                        wi[it] = mfma16(-v.y, zr[kt][q], wi[it]);
+                    }
+                }
+            }
+            // W2 = T W (T upper triangular), stored negated
+            A4 ur[2], ui[2];
+#pragma unroll
+            for (int it = 0; it < 2; ++it) {
+                ur[it] = A4{0, 0, 0, 0};
+                ui[it] = A4{0, 0, 0, 0};
+#pragma unroll
+                for (int kt = it; kt < 2; ++kt) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const CV tv = T[(16 * it + li) + (16 * kt + mfma_row((F)0, lane, q)) * NBK];
+                        ur[it] = mfma16(tv.x, wr[kt][q], ur[it]);
+                        ui[it] = mfma16(tv.x, wi[kt][q], ui[it]);
+                        ur[it] = mfma16(-tv.y, wi[kt][q], ur[it]);
+                        ui[it] = mfma16(tv.y, wr[kt][q], ui[it]);
+                    }
+                }
+                ur[it] = -ur[it];
+                ui[it] = -ui[it];
+            }
+            // Z += V (-W2)
+#pragma unroll
+            for (int rtl = 0; rtl < HT; ++rtl) {
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt) {
+                    if (16 * rtl + 15 < 16 * kt || 16 * rtl > 16 * kt + 14 + b) continue;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const CV v = V[(16 * rtl + li) + (16 * kt + mfma_row((F)0, lane, q)) * VLD];
+                        zr[rtl] = mfma16(v.x, ur[kt][q], zr[rtl]);
+                        zi[rtl] = mfma16(v.x, ui[kt][q], zi[rtl]);
+                        zr[rtl] = mfma16(-v.y, ui[kt][q], zr[rtl]);
+                        zi[rtl] = mfma16(v.y, ur[kt][q], zi[rtl]);
+                    }
+                }
+            }
+            if (more) {
+#pragma unroll
+                for (int k = 0; k < SHIFT; ++k) store_tile<F>(Z, ldz, rs, k, lane, h, colok, col, zr[k], zi[k]);
+#pragma unroll
+                for (int k = 0; k + SHIFT < HT; ++k) {
+                    zr[k] = zr[k + SHIFT];
+                    zi[k] = zi[k + SHIFT];
+                }
+#pragma unroll
+                for (int k = 0; k < SHIFT; ++k) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bool ok = (zmask >> (4 * k + q)) & 1u;
+                        zr[HT - SHIFT + k][q] = ok ? zraw[k][q].x : (F)0;
+                        zi[HT - SHIFT + k][q] = ok ? zraw[k][q].y : (F)0;
+                    }
+                }
+                // the other buffer was last read in block t - 1, before the
+                // barrier that closed it
+                publish(buf ^ 1, rv, rt, vmask);
+                __syncthreads();
+            } else {
+#pragma unroll
+                for (int k = 0; k < HT; ++k) store_tile<F>(Z, ldz, rs, k, lane, h, colok, col, zr[k], zi[k]);
+                break;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 int64_t bt2_nblocks(int64_t n, int b) {
@@ -325,8 +548,31 @@ int bt2_apply_t(int64_t n, int b, int64_t m, const F *V2, const int64_t *voff, F
     const int64_t nsw = n - 2;
     const int64_t nsb = (nsw + NBK - 1) / NBK;
     const int64_t tmax = (n - 2) / b + 1;
-    hipLaunchKernelGGL((bt2_apply<F>), dim3((unsigned)((m + SLAB - 1) / SLAB)), dim3(256), 0, s, n, b, m,
-                       V2, voff, nsb, tmax, (const F *)work, Z, ldz);
+    const dim3 grid((unsigned)((m + SLAB - 1) / SLAB));
+    // one workgroup per CU (all 512 registers) while the slabs fit the chip in
+    // one round, two per CU beyond
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+    }
+    const bool one = (int64_t)grid.x <= ncu;
+    const F *TFw = (const F *)work;
+    if (sizeof(F) == 8 && one && b % 16 == 0) {
+        switch (b / 16) {
+            case 1: hipLaunchKernelGGL((bt2_apply_pipe<F, 1>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
+            case 2: hipLaunchKernelGGL((bt2_apply_pipe<F, 2>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
+            case 3: hipLaunchKernelGGL((bt2_apply_pipe<F, 3>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
+            default: hipLaunchKernelGGL((bt2_apply_pipe<F, 4>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
+        }
+    } else if (b == 64 && one)
+        hipLaunchKernelGGL((bt2_apply<F, 64, 1>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz);
+    else if (b == 64)
+        hipLaunchKernelGGL((bt2_apply<F, 64, 2>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz);
+    else
+        hipLaunchKernelGGL((bt2_apply<F, 0, 2>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz);
     BDG_CHECK_LAUNCH();
     return 0;
 }

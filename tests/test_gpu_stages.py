@@ -116,7 +116,7 @@ def random_band(n, band, seed):
     return AB
 
 
-@pytest.mark.parametrize("n,band", [(5, 4), (64, 8), (200, 16), (301, 64), (130, 64), (513, 32)])
+@pytest.mark.parametrize("n,band", [(5, 4), (64, 8), (200, 16), (301, 64), (130, 64), (513, 32), (250, 48)])
 def test_hb2st_and_bt2(dev, n, band):
     import torch
     from paper_2310_03341_amd import api
