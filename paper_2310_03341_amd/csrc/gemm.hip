@@ -26,12 +26,19 @@ struct Cfg {
 // diagonal tile (i-fast layout only).
 template <typename T, bool CPLX, bool KFAST, bool CONJ>
 __device__ inline void load_tile(const T *__restrict__ P, int64_t ld, int64_t r0, int64_t k0,
-                                 int64_t MN, int64_t K, T (&reg)[Cfg<T, CPLX>::PER_THREAD][2],
-                                 bool hemm_diag, const int *__restrict__ kmap = nullptr) {
+                                 int64_t MN, int64_t K, typename v2t<T>::type (&v)[Cfg<T, CPLX>::PER_THREAD],
+                                 unsigned &okm, unsigned &cjm, bool hemm_diag,
+                                 const int *__restrict__ kmap = nullptr) {
     typedef Cfg<T, CPLX> C;
+    constexpr int PT = C::PER_THREAD;
     const int t = threadIdx.x;
+    // all loads of the tile are issued before any is used: unconditional (from
+    // element 0 outside the range) and zeroed by select afterwards.  A guarded
+    // load compiles to branch + load + wait, which would serialise them.
+    int64_t gi[PT], gk[PT], kk[PT];
+    bool ok[PT];
 #pragma unroll
-    for (int j = 0; j < C::PER_THREAD; ++j) {
+    for (int j = 0; j < PT; ++j) {
         int i, k;
         if (KFAST) {
             k = t % C::BK;
@@ -40,36 +47,59 @@ __device__ inline void load_tile(const T *__restrict__ P, int64_t ld, int64_t r0
             i = t % BM;
             k = t / BM + (NT / BM) * j;
         }
-        const int64_t gi = r0 + i, gk = k0 + k;
-        T re = 0, im = 0;
-        if (gi < MN && gk < K) {
-            int64_t off;
-            bool cj = CONJ;
-            if (KFAST) {
-                off = (kmap ? (int64_t)kmap[gk] : gk) + gi * ld;
-            } else if (hemm_diag && gk > gi) {
-                off = gk + gi * ld;  // upper element of a Hermitian tile: conj of lower
-                cj = true;
-            } else {
-                off = gi + (kmap ? (int64_t)kmap[gk] : gk) * ld;
-            }
-            if (CPLX) {
-                re = P[2 * off];
-                im = P[2 * off + 1];
-                if (cj) im = -im;
-            } else {
-                re = P[off];
-            }
+        gi[j] = r0 + i;
+        gk[j] = k0 + k;
+        ok[j] = (gi[j] < MN) & (gk[j] < K);
+        kk[j] = ok[j] ? gk[j] : 0;
+    }
+    if (kmap) {
+#pragma unroll
+        for (int j = 0; j < PT; ++j) kk[j] = kmap[kk[j]];
+    }
+    bool cj[PT];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+        int64_t off;
+        cj[j] = CONJ;
+        if (KFAST) {
+            off = kk[j] + gi[j] * ld;
+        } else if (hemm_diag && gk[j] > gi[j]) {
+            off = gk[j] + gi[j] * ld;  // upper element of a Hermitian tile: conj of lower
+            cj[j] = true;
+        } else {
+            off = gi[j] + kk[j] * ld;
         }
-        reg[j][0] = re;
-        reg[j][1] = im;
+        off = ok[j] ? off : 0;
+        if (CPLX) {
+            v[j] = *(const typename v2t<T>::type *)(P + 2 * off);
+        } else {
+            v[j].x = P[off];
+            v[j].y = 0;
+        }
+    }
+    // the values are only selected when they go to LDS (store_tile), so the
+    // products of the current tile run while these loads are in flight
+    okm = 0;
+    cjm = 0;
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+        okm |= (unsigned)ok[j] << j;
+        cjm |= (unsigned)cj[j] << j;
     }
 }
 
 template <typename T, bool CPLX, bool KFAST>
-__device__ inline void store_tile(T *__restrict__ S, const T (&reg)[Cfg<T, CPLX>::PER_THREAD][2]) {
+__device__ inline void store_tile(T *__restrict__ S, const typename v2t<T>::type (&v)[Cfg<T, CPLX>::PER_THREAD],
+                                  unsigned okm, unsigned cjm) {
     typedef Cfg<T, CPLX> C;
     const int t = threadIdx.x;
+    T reg[C::PER_THREAD][2];
+#pragma unroll
+    for (int j = 0; j < C::PER_THREAD; ++j) {
+        const bool ok = (okm >> j) & 1u, cj = (cjm >> j) & 1u;
+        reg[j][0] = ok ? v[j].x : (T)0;
+        reg[j][1] = (ok && CPLX) ? (cj ? -v[j].y : v[j].y) : (T)0;
+    }
 #pragma unroll
     for (int j = 0; j < C::PER_THREAD; ++j) {
         int i, k;
@@ -131,40 +161,41 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs g, int64_t kchunk) {
             accI[a][b] = A4{0, 0, 0, 0};
         }
 
-    T ra[C::PER_THREAD][2], rb[C::PER_THREAD][2];
+    typename v2t<T>::type ra[C::PER_THREAD], rb[C::PER_THREAD];
+    unsigned aok = 0, acj = 0, bok = 0, bcj = 0;
 
     // A operand: 'N' -> i-fast, 'C' -> k-fast.  HEMM_L: per tile choice.
     auto loadA = [&](int64_t k0) {
         if (MODE == GEMM_HEMM_L) {
             // block column of A holding k0 (tiles aligned to BM)
             if (k0 + C::BK <= m0) {
-                load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, false);
+                load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false);
             } else if (k0 >= m0 + BM) {
-                load_tile<T, CPLX, true, true>(A, g.lda, m0, k0, g.M, kend, ra, false);
+                load_tile<T, CPLX, true, true>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false);
             } else {
-                load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, true);
+                load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, true);
             }
         } else if (CA) {
-            load_tile<T, CPLX, true, true>(A, g.lda, m0, k0, g.M, kend, ra, false);
+            load_tile<T, CPLX, true, true>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false);
         } else {
-            load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, false, g.acol);
+            load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false, g.acol);
         }
     };
     auto storeA = [&](int buf, int64_t k0) {
         bool kf;
         if (MODE == GEMM_HEMM_L) kf = (k0 >= m0 + BM);
         else kf = CA;
-        if (kf) store_tile<T, CPLX, true>(As[buf], ra);
-        else store_tile<T, CPLX, false>(As[buf], ra);
+        if (kf) store_tile<T, CPLX, true>(As[buf], ra, aok, acj);
+        else store_tile<T, CPLX, false>(As[buf], ra, aok, acj);
     };
     // B operand: 'N' -> k-fast (B stored K x N), 'C' -> i-fast (B stored N x K).
     auto loadB = [&](int64_t k0) {
-        if (CB) load_tile<T, CPLX, false, true>(B, g.ldb, n0, k0, g.N, kend, rb, false);
-        else load_tile<T, CPLX, true, false>(B, g.ldb, n0, k0, g.N, kend, rb, false, g.brow);
+        if (CB) load_tile<T, CPLX, false, true>(B, g.ldb, n0, k0, g.N, kend, rb, bok, bcj, false);
+        else load_tile<T, CPLX, true, false>(B, g.ldb, n0, k0, g.N, kend, rb, bok, bcj, false, g.brow);
     };
     auto storeB = [&](int buf) {
-        if (CB) store_tile<T, CPLX, false>(Bs[buf], rb);
-        else store_tile<T, CPLX, true>(Bs[buf], rb);
+        if (CB) store_tile<T, CPLX, false>(Bs[buf], rb, bok, bcj);
+        else store_tile<T, CPLX, true>(Bs[buf], rb, bok, bcj);
     };
 
     if (kbeg < kend) {
@@ -237,11 +268,14 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs g, int64_t kchunk) {
         }
     }
 
-    // epilogue
+    // epilogue: the 16 entries of C this thread owns are read (when beta != 0)
+    // in one batch before any of them is written
     const bool to_part = g.splitk > 1;
     T *__restrict__ P = (T *)g.part;
     const T ar = (T)g.alpha_re, ai = (T)g.alpha_im, br = (T)g.beta_re, bi = (T)g.beta_im;
     const bool beta0 = (br == (T)0 && bi == (T)0);
+    int64_t coff[2][2][4];
+    bool cok[2][2][4];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -250,10 +284,40 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs g, int64_t kchunk) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int64_t row = m0 + wm * 32 + a * 16 + mfma_row((T)0, lane, q);
-                if (row >= g.M || col >= g.N) continue;
+                const bool ok = (row < g.M) & (col < g.N);
+                cok[a][b][q] = ok;
+                if (to_part) coff[a][b][q] = (int64_t)blockIdx.z * g.M * g.N + row + col * g.M;
+                else coff[a][b][q] = ok ? row + (g.ccol ? (int64_t)g.ccol[col] : col) * g.ldc : 0;
+            }
+        }
+    T oldr[2][2][4], oldi[2][2][4];
+    if (!to_part && !beta0) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (CPLX) {
+                        const typename v2t<T>::type v = *(const typename v2t<T>::type *)(Cm + 2 * coff[a][b][q]);
+                        oldr[a][b][q] = v.x;
+                        oldi[a][b][q] = v.y;
+                    } else {
+                        oldr[a][b][q] = Cm[coff[a][b][q]];
+                        oldi[a][b][q] = 0;
+                    }
+                }
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (!cok[a][b][q]) continue;
                 const T vr = accR[a][b][q], vi = CPLX ? accI[a][b][q] : (T)0;
+                const int64_t off = coff[a][b][q];
                 if (to_part) {
-                    const int64_t off = (int64_t)blockIdx.z * g.M * g.N + row + col * g.M;
                     if (CPLX) {
                         P[2 * off] = vr;
                         P[2 * off + 1] = vi;
@@ -262,19 +326,17 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs g, int64_t kchunk) {
                     }
                     continue;
                 }
-                const int64_t off = row + (g.ccol ? (int64_t)g.ccol[col] : col) * g.ldc;
                 if (CPLX) {
                     T cr = ar * vr - ai * vi, ci = ar * vi + ai * vr;
                     if (!beta0) {
-                        const T orr = Cm[2 * off], oi = Cm[2 * off + 1];
+                        const T orr = oldr[a][b][q], oi = oldi[a][b][q];
                         cr += br * orr - bi * oi;
                         ci += br * oi + bi * orr;
                     }
-                    Cm[2 * off] = cr;
-                    Cm[2 * off + 1] = ci;
+                    *(typename v2t<T>::type *)(Cm + 2 * off) = mk2<T>(cr, ci);
                 } else {
                     T cr = ar * vr;
-                    if (!beta0) cr += br * Cm[off];
+                    if (!beta0) cr += br * oldr[a][b][q];
                     Cm[off] = cr;
                 }
             }

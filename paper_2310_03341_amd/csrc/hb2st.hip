@@ -59,20 +59,29 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
     // global loads are issued before their LDS stores.
     {
         CV rb[16], rd[16];
+        // unconditional loads (entry 0 outside the block), zeroed by select:
+        // guarded loads compile to branch + load + wait and run one by one
+        unsigned okb = 0, okd = 0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int e = tid + 256 * i;
             const int r = e & 63, c = e >> 6;
-            rb[i] = mk2<F>(0.0, 0.0);
-            if (t > 0 && r < Lr && c < b) rb[i] = ld2<F>(AB + 2 * ((b + r - c) + (c0 + c) * ldab));
-            rd[i] = mk2<F>(0.0, 0.0);
-            if (r < Lr && c < Lr) {
-                if (r >= c) rd[i] = ld2<F>(AB + 2 * ((r - c) + (r0 + c) * ldab));
-                else {
-                    rd[i] = ld2<F>(AB + 2 * ((c - r) + (r0 + r) * ldab));
-                    rd[i].y = -rd[i].y;
-                }
-            }
+            const bool ob = (t > 0) & (r < Lr) & (c < b);
+            const bool od = (r < Lr) & (c < Lr);
+            const int64_t offb = ob ? 2 * ((b + r - c) + (c0 + c) * ldab) : 0;
+            const int64_t offd = od ? 2 * (r >= c ? (r - c) + (r0 + c) * ldab : (c - r) + (r0 + r) * ldab) : 0;
+            rb[i] = ld2<F>(AB + offb);
+            rd[i] = ld2<F>(AB + offd);
+            okb |= (unsigned)ob << i;
+            okd |= (unsigned)od << i;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e & 63, c = e >> 6;
+            if (!((okb >> i) & 1u)) rb[i] = mk2<F>(0.0, 0.0);
+            if (!((okd >> i) & 1u)) rd[i] = mk2<F>(0.0, 0.0);
+            else if (r < c) rd[i].y = -rd[i].y;  // upper entry: conj of the stored lower one
         }
         if (t > 0) {
             if (tid < b) vp[tid] = ld2<F>(V2 + 2 * ((ridx - 1) * b + tid));
