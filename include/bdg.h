@@ -82,6 +82,10 @@ typedef struct {
                                 Delta); 0: back-transform every vector          */
 } bdg_opts;
 
+/* Progress: when the environment variable BDG_VERBOSE is set (and not "0"),
+ * bdg_eigh waits for each stage and prints one line per finished stage and
+ * per refinement step to stderr.  Off by default (no extra synchronisation). */
+
 /* Per-call accuracy and timing report (filled when non-NULL). */
 typedef struct {
     double max_resid;     /* mixed arm: defect measured by the last refinement

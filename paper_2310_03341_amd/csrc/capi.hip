@@ -1,4 +1,5 @@
 // C-ABI entry points of libbdg.so (declared in include/bdg.h).
+#include <stdlib.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -17,6 +18,14 @@ void set_error(const char *fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
+}
+
+bool verbose() {
+    static const bool v = [] {
+        const char *e = getenv("BDG_VERBOSE");
+        return e && e[0] && e[0] != '0';
+    }();
+    return v;
 }
 
 int hip_fail(hipError_t e, const char *what, const char *file, int line) {

@@ -97,6 +97,8 @@ __device__ inline T block_sum(T v, T* red /* >= blockDim.x/64 */) {
 // ---- host-side error plumbing -------------------------------------------------
 namespace bdg {
 void set_error(const char* fmt, ...);
+// true when the environment sets BDG_VERBOSE (progress lines on stderr)
+bool verbose();
 int hip_fail(hipError_t e, const char* what, const char* file, int line);
 }  // namespace bdg
 

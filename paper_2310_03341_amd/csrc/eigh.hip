@@ -6,6 +6,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
 #include <vector>
 
 #include "refine.h"
@@ -73,6 +75,7 @@ struct Timer {
     hipStream_t s;
     hipEvent_t ev[12];
     bool ok = false;
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
     explicit Timer(hipStream_t st) : s(st) {
         ok = true;
         for (int i = 0; i < 12; ++i)
@@ -81,8 +84,16 @@ struct Timer {
     ~Timer() {
         for (int i = 0; i < 12; ++i) (void)hipEventDestroy(ev[i]);
     }
-    void mark(int i) {
+    // what: stage just finished; with BDG_VERBOSE set, waits for it and prints
+    // the elapsed wall time to stderr (long solves report their own progress)
+    void mark(int i, const char *what = nullptr) {
         if (ok) (void)hipEventRecord(ev[i], s);
+        if (what && verbose()) {
+            (void)hipStreamSynchronize(s);
+            const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            fprintf(stderr, "[bdg] %s done, %.2f s\n", what, sec);
+            fflush(stderr);
+        }
     }
     double ms(int a, int b) {
         float t = 0.f;
@@ -207,9 +218,9 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
         return BDG_ERR_NONFINITE;
     }
     BDG_TRY(cast_c128_to_c64(n, n, A, lda, A32, n, s));
-    tm.mark(1);
+    tm.mark(1, "input check + cast to FP32");
     BDG_TRY(he2hb(n, A32, n, b, AB, L.ldab, T1, scratch, s));
-    tm.mark(2);
+    tm.mark(2, "he2hb");
     if (n >= 3) {
         std::vector<int64_t> vh((size_t)(n - 2));
         hb2st_offsets(n, b, vh.data());
@@ -218,19 +229,19 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
     }
     BDG_TRY(hb2st(n, b, AB, L.ldab, V2, tau2, voff, d, ec, s));
     BDG_TRY(phases(n, ec, ph, ea, s));
-    tm.mark(3);
+    tm.mark(3, "hb2st");
     BDG_TRY(stedc(n, d, ea, W2, Y, n, scratch, s, leaf));
-    tm.mark(4);
+    tm.mark(4, "stedc");
     // FP32 basis: all columns, or the E >= 0 half and its particle-hole partners
     const int64_t c0 = ph_mirror ? n / 2 : 0;
     const int64_t nc = n - c0;
     BDG_TRY(phase_scale(n, nc, Y, c0, ph, X32 + 2 * c0 * n, n, s));
-    tm.mark(5);
+    tm.mark(5, "phase scaling");
     BDG_TRY(bt2_prepare(n, b, V2, tau2, voff, scratch, s));
     tm.mark(10);
     BDG_TRY(bt2_apply_blocks(n, b, nc, V2, voff, X32 + 2 * c0 * n, n, scratch, s));
     tm.mark(11);
-    tm.mark(6);
+    tm.mark(6, "bt2");
     BDG_TRY(bt1(n, nc, A32, n, b, T1, X32 + 2 * c0 * n, n, scratch, s));
     if (ph_mirror) {
         BDG_TRY(mirror_half(n, X32, n, s));
@@ -239,7 +250,7 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
     } else {
         BDG_HIP(hipMemcpyAsync(lam, W2, 8 * (size_t)n, hipMemcpyDeviceToDevice, s));
     }
-    tm.mark(7);
+    tm.mark(7, "bt1");
     // window on the FP64 eigenvalues of the FP32-reduced tridiagonal
     std::vector<double> wh((size_t)n);
     BDG_HIP(hipMemcpyAsync(wh.data(), lam, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
@@ -278,7 +289,7 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
         hipLaunchKernelGGL(neg_reverse_w, dim3(64), dim3(256), 0, s, h - i0, W, (n - 1 - i0) - i0);
         BDG_CHECK_LAUNCH();
     }
-    tm.mark(8);
+    tm.mark(8, "refinement");
     BDG_HIP(hipStreamSynchronize(s));
     if (report) {
         memset(report, 0, sizeof(*report));
@@ -345,10 +356,10 @@ int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
         set_error("bdg_eigh: the input matrix holds NaN or Inf");
         return BDG_ERR_NONFINITE;
     }
-    tm.mark(1);
+    tm.mark(1, "input check");
     // ---- stage 1: dense -> band
     BDG_TRY(he2hb(n, A, lda, b, AB, L.ldab, T1, scratch, s));
-    tm.mark(2);
+    tm.mark(2, "he2hb");
     // ---- stage 2: band -> tridiagonal
     if (n >= 3) {
         std::vector<int64_t> vh((size_t)(n - 2));
@@ -358,10 +369,10 @@ int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
     }
     BDG_TRY(hb2st(n, b, AB, L.ldab, V2, tau2, voff, d, ec, s));
     BDG_TRY(phases(n, ec, ph, ea, s));
-    tm.mark(3);
+    tm.mark(3, "hb2st");
     // ---- tridiagonal divide and conquer
     BDG_TRY(stedc(n, d, ea, W2, Y, n, scratch, s, leaf));
-    tm.mark(4);
+    tm.mark(4, "stedc");
     // ---- window
     std::vector<double> wh((size_t)n);
     BDG_HIP(hipMemcpyAsync(wh.data(), W2, 8 * (size_t)n, hipMemcpyDeviceToHost, s));
@@ -389,16 +400,16 @@ int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
     const int64_t mb = bt_hi - bt_lo;
     double *Zb = Z + 2 * (bt_lo - i0) * ldz;
     BDG_TRY(phase_scale(n, mb, Y, bt_lo, ph, Zb, ldz, s));
-    tm.mark(5);
+    tm.mark(5, "window + phase scaling");
     // ---- back-transformation 2 (band <- tridiagonal), then 1 (dense <- band)
     BDG_TRY(bt2_prepare(n, b, V2, tau2, voff, scratch, s));
     tm.mark(8);
     BDG_TRY(bt2_apply_blocks(n, b, mb, V2, voff, Zb, ldz, scratch, s));
     tm.mark(9);
-    tm.mark(6);
+    tm.mark(6, "bt2");
     BDG_TRY(bt1(n, mb, A, lda, b, T1, Zb, ldz, scratch, s));
     if (mirror) BDG_TRY(mirror_columns(n, Z, ldz, 0, (n - 1 - i0) - i0, h - i0, s));
-    tm.mark(7);
+    tm.mark(7, "bt1");
     BDG_HIP(hipStreamSynchronize(s));
     if (report) {
         memset(report, 0, sizeof(*report));

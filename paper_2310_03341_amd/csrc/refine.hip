@@ -25,6 +25,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <numeric>
 #include <vector>
 
@@ -660,6 +661,11 @@ int refine_window(int64_t n, const double *H, int64_t ldh, double *X, int64_t ld
         const double corr = std::max(h[1], h[2]);
         if (last_corr) *last_corr = corr;
         if (iters_done) *iters_done = it + 1;
+        if (verbose()) {
+            fprintf(stderr, "[bdg] refinement step %d: defect %.3e, %d close pairs, %d clustered columns\n",
+                    it + 1, corr, npairs, (int)idx_h.size());
+            fflush(stderr);
+        }
         // the defect shrinks quadratically; stop once it (and the in-cluster
         // coupling) is at rounding level
         if (corr < tol) break;
