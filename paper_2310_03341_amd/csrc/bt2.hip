@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256, OCC) void bt2_apply(int64_t n, int b_rt, int64
     }
 }
 
-// Pipelined variant (FP64, b a multiple of 16, SHIFT = b / 16 tiles): while
+// Pipelined variant (b a multiple of 16, SHIFT = b / 16 tiles): while
 // the matrix cores work on block t, the loads for block t + 1 are in flight:
 // its V and T go to the other half of a double LDS buffer, and its SHIFT new
 // Z tiles (rows the current block does not touch) to registers; the window
@@ -549,30 +549,19 @@ int bt2_apply_t(int64_t n, int b, int64_t m, const F *V2, const int64_t *voff, F
     const int64_t nsb = (nsw + NBK - 1) / NBK;
     const int64_t tmax = (n - 2) / b + 1;
     const dim3 grid((unsigned)((m + SLAB - 1) / SLAB));
-    // one workgroup per CU (all 512 registers) while the slabs fit the chip in
-    // one round, two per CU beyond
-    static int ncu = 0;
-    if (ncu == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
-            ncu = 256;
-    }
-    const bool one = (int64_t)grid.x <= ncu;
     const F *TFw = (const F *)work;
-    if (sizeof(F) == 8 && one && b % 16 == 0) {
-        switch (b / 16) {
-            case 1: hipLaunchKernelGGL((bt2_apply_pipe<F, 1>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
-            case 2: hipLaunchKernelGGL((bt2_apply_pipe<F, 2>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
-            case 3: hipLaunchKernelGGL((bt2_apply_pipe<F, 3>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
-            default: hipLaunchKernelGGL((bt2_apply_pipe<F, 4>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
-        }
-    } else if (b == 64 && one)
-        hipLaunchKernelGGL((bt2_apply<F, 64, 1>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz);
-    else if (b == 64)
-        hipLaunchKernelGGL((bt2_apply<F, 64, 2>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz);
-    else
-        hipLaunchKernelGGL((bt2_apply<F, 0, 2>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz);
+    // band widths that are a multiple of 16 (the default 64): the pipelined
+    // kernel, one workgroup per CU (more slabs than CUs run in rounds, still
+    // ahead of two-per-CU occupancy: 23.7 s for the generic kernel at 384
+    // slabs of the 32x32x24 workload against an estimated 2 x 10.3 s);
+    // other widths: the generic kernel, two workgroups per CU
+    switch (b % 16 == 0 ? b / 16 : 0) {
+        case 1: hipLaunchKernelGGL((bt2_apply_pipe<F, 1>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
+        case 2: hipLaunchKernelGGL((bt2_apply_pipe<F, 2>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
+        case 3: hipLaunchKernelGGL((bt2_apply_pipe<F, 3>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
+        case 4: hipLaunchKernelGGL((bt2_apply_pipe<F, 4>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
+        default: hipLaunchKernelGGL((bt2_apply<F, 0, 2>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
+    }
     BDG_CHECK_LAUNCH();
     return 0;
 }
