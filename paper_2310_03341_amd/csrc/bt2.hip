@@ -414,59 +414,87 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
             }
             const CV *V = Vs[buf];
             const CV *T = Ts[buf];
-            // W = V^H Z
+            // The three complex products use three real MFMAs each (Gauss'
+            // form: for (a + ib)(c + id), ac, bd and (a + b)(c + d)) instead of four.
+            // W = V^H Z:  Re = P1 + P2, Im = P3 + P1 - P2 with
+            // P1 = sum vr zr, P2 = sum vi zi, P3 = sum (vr + vi)(zi - zr)
             A4 wr[2], wi[2];
+            {
+                A4 p1[2], p2[2], p3[2];
 #pragma unroll
-            for (int it = 0; it < 2; ++it) {
-                wr[it] = A4{0, 0, 0, 0};
-                wi[it] = A4{0, 0, 0, 0};
+                for (int it = 0; it < 2; ++it) {
+                    p1[it] = A4{0, 0, 0, 0};
+                    p2[it] = A4{0, 0, 0, 0};
+                    p3[it] = A4{0, 0, 0, 0};
+                }
 #pragma unroll
                 for (int kt = 0; kt < HT; ++kt) {
-                    if (16 * kt + 15 < 16 * it || 16 * kt > 16 * it + 14 + b) continue;
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const CV v = V[(16 * kt + mfma_row((F)0, lane, q)) + (16 * it + li) * VLD];
-                        wr[it] = mfma16(v.x, zr[kt][q], wr[it]);
-                        wi[it] = mfma16(v.x, zi[kt][q], wi[it]);
-                        wr[it] = mfma16(v.y, zi[kt][q], wr[it]);
-                        wi[it] = mfma16(-v.y, zr[kt][q], wi[it]);
+                        const F d = zi[kt][q] - zr[kt][q];
+#pragma unroll
+                        for (int it = 0; it < 2; ++it) {
+                            if (16 * kt + 15 < 16 * it || 16 * kt > 16 * it + 14 + b) continue;
+                            const CV v = V[(16 * kt + mfma_row((F)0, lane, q)) + (16 * it + li) * VLD];
+                            p1[it] = mfma16(v.x, zr[kt][q], p1[it]);
+                            p2[it] = mfma16(v.y, zi[kt][q], p2[it]);
+                            p3[it] = mfma16(v.x + v.y, d, p3[it]);
+                        }
                     }
                 }
+#pragma unroll
+                for (int it = 0; it < 2; ++it) {
+                    wr[it] = p1[it] + p2[it];
+                    wi[it] = p3[it] + p1[it] - p2[it];
+                }
             }
-            // W2 = T W (T upper triangular), stored negated
+            // W2 = T W (T upper triangular), stored negated:
+            // Re = Q1 - Q2, Im = Q3 - Q1 - Q2, Q1 = sum tr wr, Q2 = sum ti wi,
+            // Q3 = sum (tr + ti)(wr + wi)
             A4 ur[2], ui[2];
+            {
+                A4 sw[2];
 #pragma unroll
-            for (int it = 0; it < 2; ++it) {
-                ur[it] = A4{0, 0, 0, 0};
-                ui[it] = A4{0, 0, 0, 0};
+                for (int kt = 0; kt < 2; ++kt) sw[kt] = wr[kt] + wi[kt];
 #pragma unroll
-                for (int kt = it; kt < 2; ++kt) {
+                for (int it = 0; it < 2; ++it) {
+                    A4 q1 = A4{0, 0, 0, 0}, q2 = A4{0, 0, 0, 0}, q3 = A4{0, 0, 0, 0};
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const CV tv = T[(16 * it + li) + (16 * kt + mfma_row((F)0, lane, q)) * NBK];
-                        ur[it] = mfma16(tv.x, wr[kt][q], ur[it]);
-                        ui[it] = mfma16(tv.x, wi[kt][q], ui[it]);
-                        ur[it] = mfma16(-tv.y, wi[kt][q], ur[it]);
-                        ui[it] = mfma16(tv.y, wr[kt][q], ui[it]);
+                    for (int kt = it; kt < 2; ++kt) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const CV tv = T[(16 * it + li) + (16 * kt + mfma_row((F)0, lane, q)) * NBK];
+                            q1 = mfma16(tv.x, wr[kt][q], q1);
+                            q2 = mfma16(tv.y, wi[kt][q], q2);
+                            q3 = mfma16(tv.x + tv.y, sw[kt][q], q3);
+                        }
                     }
+                    ur[it] = q2 - q1;
+                    ui[it] = q1 + q2 - q3;
                 }
-                ur[it] = -ur[it];
-                ui[it] = -ui[it];
             }
-            // Z += V (-W2)
+            // Z += V (-W2): per row tile, Re += Q1 - Q2, Im += Q3 - Q1 - Q2 with
+            // Q1 = sum vr ur, Q2 = sum vi ui, Q3 = sum (vr + vi)(ur + ui)
+            {
+                A4 su[2];
 #pragma unroll
-            for (int rtl = 0; rtl < HT; ++rtl) {
+                for (int kt = 0; kt < 2; ++kt) su[kt] = ur[kt] + ui[kt];
 #pragma unroll
-                for (int kt = 0; kt < 2; ++kt) {
-                    if (16 * rtl + 15 < 16 * kt || 16 * rtl > 16 * kt + 14 + b) continue;
+                for (int rtl = 0; rtl < HT; ++rtl) {
+                    A4 q1 = A4{0, 0, 0, 0}, q2 = A4{0, 0, 0, 0}, q3 = A4{0, 0, 0, 0};
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const CV v = V[(16 * rtl + li) + (16 * kt + mfma_row((F)0, lane, q)) * VLD];
-                        zr[rtl] = mfma16(v.x, ur[kt][q], zr[rtl]);
-                        zi[rtl] = mfma16(v.x, ui[kt][q], zi[rtl]);
-                        zr[rtl] = mfma16(-v.y, ui[kt][q], zr[rtl]);
-                        zi[rtl] = mfma16(v.y, ur[kt][q], zi[rtl]);
+                    for (int kt = 0; kt < 2; ++kt) {
+                        if (16 * rtl + 15 < 16 * kt || 16 * rtl > 16 * kt + 14 + b) continue;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const CV v = V[(16 * rtl + li) + (16 * kt + mfma_row((F)0, lane, q)) * VLD];
+                            q1 = mfma16(v.x, ur[kt][q], q1);
+                            q2 = mfma16(v.y, ui[kt][q], q2);
+                            q3 = mfma16(v.x + v.y, su[kt][q], q3);
+                        }
                     }
+                    zr[rtl] += q1 - q2;
+                    zi[rtl] += q3 - q1 - q2;
                 }
             }
             if (more) {
