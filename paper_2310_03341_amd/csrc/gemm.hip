@@ -122,7 +122,7 @@ __device__ inline void store_tile(T *__restrict__ S, const typename v2t<T>::type
 
 // opA: false = 'N', true = 'C'.  opB likewise.
 template <typename T, bool CPLX, bool CA, bool CB, int MODE>
-__global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs g, int64_t kchunk) {
+__global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk) {
     typedef Cfg<T, CPLX> C;
     typedef typename acc4<T>::type A4;
     constexpr int EW = C::EW;
@@ -152,13 +152,17 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs g, int64_t kchunk) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = wave & 1, wn = wave >> 1;
 
-    A4 accR[2][2], accI[2][2];
+    // complex: three real products per complex one (Gauss' form),
+    // P1 = sum ar br, P2 = sum ai bi, P3 = sum (ar + ai)(br + bi);
+    // Re = P1 - P2, Im = P3 - P1 - P2 (formed after the k loop).  Real: P1 only.
+    A4 accR[2][2], accI[2][2], acc3[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             accR[a][b] = A4{0, 0, 0, 0};
             accI[a][b] = A4{0, 0, 0, 0};
+            acc3[a][b] = A4{0, 0, 0, 0};
         }
 
     typename v2t<T>::type ra[C::PER_THREAD], rb[C::PER_THREAD];
@@ -245,18 +249,19 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs g, int64_t kchunk) {
 #pragma unroll
                     for (int b = 0; b < 2; ++b) accR[a][b] = mfma16(are[a], bre[b], accR[a][b]);
                 if (CPLX) {
+                    T as2[2], bs2[2];
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) as2[a] = are[a] + aim[a];
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) bs2[b] = bre[b] + bim[b];
 #pragma unroll
                     for (int a = 0; a < 2; ++a)
 #pragma unroll
-                        for (int b = 0; b < 2; ++b) accI[a][b] = mfma16(are[a], bim[b], accI[a][b]);
+                        for (int b = 0; b < 2; ++b) accI[a][b] = mfma16(aim[a], bim[b], accI[a][b]);
 #pragma unroll
                     for (int a = 0; a < 2; ++a)
 #pragma unroll
-                        for (int b = 0; b < 2; ++b) accR[a][b] = mfma16(-aim[a], bim[b], accR[a][b]);
-#pragma unroll
-                    for (int a = 0; a < 2; ++a)
-#pragma unroll
-                        for (int b = 0; b < 2; ++b) accI[a][b] = mfma16(aim[a], bre[b], accI[a][b]);
+                        for (int b = 0; b < 2; ++b) acc3[a][b] = mfma16(as2[a], bs2[b], acc3[a][b]);
                 }
             }
             if (more) {
@@ -268,6 +273,16 @@ __global__ __launch_bounds__(NT) void gemm_kernel(GemmArgs g, int64_t kchunk) {
         }
     }
 
+    if (CPLX) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const A4 p1 = accR[a][b], p2 = accI[a][b];
+                accR[a][b] = p1 - p2;
+                accI[a][b] = acc3[a][b] - p1 - p2;
+            }
+    }
     // epilogue: the 16 entries of C this thread owns are read (when beta != 0)
     // in one batch before any of them is written
     const bool to_part = g.splitk > 1;
