@@ -14,6 +14,8 @@
 // chunk of rows); a launch applies reflector j and, in the same pass, forms
 // the partial norms and inner products that define reflector j+1.  All the
 // O(n^3) work (HEMM, HER2K and small GEMMs) goes through the MFMA tile kernel.
+#include <mutex>
+
 #include "gemm.h"
 #include "stages.h"
 
@@ -21,6 +23,31 @@ namespace bdg {
 namespace {
 
 constexpr int PQ_ROWS = 256;  // rows per workgroup in the panel kernels
+
+// One non-blocking side stream per device for the look-ahead panel (default
+// priority), created on first use and kept for the life of the process.
+hipStream_t side_stream() {
+    static std::mutex mu;
+    static hipStream_t st[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!st[dev] && hipStreamCreateWithFlags(&st[dev], hipStreamNonBlocking) != hipSuccess) st[dev] = nullptr;
+    return st[dev];
+}
+
+struct Events {
+    hipEvent_t upd = nullptr, panel = nullptr;
+    bool ok = false;
+    Events() {
+        ok = hipEventCreateWithFlags(&upd, hipEventDisableTiming) == hipSuccess &&
+             hipEventCreateWithFlags(&panel, hipEventDisableTiming) == hipSuccess;
+    }
+    ~Events() {
+        if (upd) (void)hipEventDestroy(upd);
+        if (panel) (void)hipEventDestroy(panel);
+    }
+};
 constexpr int MAXB = 64;      // largest supported band
 
 // Partials layout per workgroup: [0..nb) complex s_c, [nb] (tail2, 0).
@@ -372,22 +399,41 @@ int he2hb_t(int64_t n, F *A, int64_t lda, int b, F *AB, int64_t ldab, F *T1,
     prow[1] = take(16 * (size_t)b);
     F *tau = take(8 * (size_t)b);
 
+    // QR of the panel below the band at column k (one launch per column)
+    auto factor_panel = [&](int64_t kp, hipStream_t st) -> int {
+        const int64_t mrp = n - kp - b;
+        F *Pp = A + 2 * ((kp + b) + kp * lda);
+        const int ncolp = (int)(mrp < b ? mrp : b);
+        const int Gp = (int)((mrp + PQ_ROWS - 1) / PQ_ROWS);
+        BDG_HIP(hipMemsetAsync(tau, 0, 8 * (size_t)b, st));
+        for (int j = -1; j < ncolp; ++j) {
+            const int ib = (j + 2) & 1;   // buffer read by step j
+            const int ob = (j + 3) & 1;   // buffer written for column j+1
+            hipLaunchKernelGGL((panel_step<F>), dim3(Gp), dim3(256), 0, st, Pp, lda, mrp, b, j, ncolp,
+                               ppart[ib], prow[ib], ppart[ob], prow[ob], tau, Gp);
+            BDG_CHECK_LAUNCH();
+        }
+        return 0;
+    };
+    // Look-ahead: once the trailing update has reached the next panel's
+    // columns, that panel is factored on a second stream while the rest of
+    // the trailing matrix is updated on the caller's stream (disjoint
+    // columns).  Its reflectors, tau and T are consumed on the caller's
+    // stream after an event wait.
+    hipStream_t s2 = side_stream();
+    Events ev;
+    if (!s2 || !ev.ok) {
+        set_error("he2hb: could not create the look-ahead stream or events");
+        return BDG_ERR_HIP;
+    }
+
     int64_t k = 0;
     int p = 0;
+    if (k + b + 1 < n) BDG_TRY(factor_panel(0, s));
     for (; k + b + 1 < n; k += b, ++p) {
         const int nb = b;
         const int64_t mr = n - k - b;
-        F *P = A + 2 * ((k + b) + k * lda);
-        const int ncol = (int)(mr < nb ? mr : nb);
-        const int G = (int)((mr + PQ_ROWS - 1) / PQ_ROWS);
-        BDG_HIP(hipMemsetAsync(tau, 0, 8 * (size_t)nb, s));
-        for (int j = -1; j < ncol; ++j) {
-            const int ib = (j + 2) & 1;   // buffer read by step j
-            const int ob = (j + 3) & 1;   // buffer written for column j+1
-            hipLaunchKernelGGL((panel_step<F>), dim3(G), dim3(256), 0, s, P, lda, mr, nb, j, ncol,
-                               ppart[ib], prow[ib], ppart[ob], prow[ob], tau, G);
-            BDG_CHECK_LAUNCH();
-        }
+        if (p > 0) BDG_HIP(hipStreamWaitEvent(s, ev.panel, 0));
         // band columns, then explicit V (overwrites R in A)
         hipLaunchKernelGGL((panel_band<F>), dim3(1, nb), dim3(256), 0, s, A, lda, n, k, b, AB, ldab);
         BDG_CHECK_LAUNCH();
@@ -444,10 +490,27 @@ int he2hb_t(int64_t n, F *A, int64_t lda, int b, F *AB, int64_t ldab, F *T1,
             BDG_CHECK_LAUNCH();
         }
         // A22 -= [V W] [W V]^H   (lower tiles)
-        {
+        const bool ahead = (k + b) + b + 1 < n && mr > nb;
+        if (ahead) {
+            // the next panel's columns first (all rows), then that panel's QR
+            // on the side stream, then the rest of A22
+            GemmArgs ga{mr, nb, 2 * (int64_t)nb, -1.0, 0.0, 1.0, 0.0, VW, ldw, WV, ldw, A22, lda,
+                        GEMM_FULL, 1, nullptr};
+            BDG_TRY((gemm<F, true>('N', 'C', ga, s)));
+            BDG_HIP(hipEventRecord(ev.upd, s));
+            BDG_HIP(hipStreamWaitEvent(s2, ev.upd, 0));
+            BDG_TRY(factor_panel(k + b, s2));
+            BDG_HIP(hipEventRecord(ev.panel, s2));
+            const int64_t mr2 = mr - nb;
+            GemmArgs gb{mr2, mr2, 2 * (int64_t)nb, -1.0, 0.0, 1.0, 0.0, VW + 2 * nb, ldw, WV + 2 * nb, ldw,
+                        A22 + 2 * (nb + (int64_t)nb * lda), lda, GEMM_LOWER, 1, nullptr};
+            BDG_TRY((gemm<F, true>('N', 'C', gb, s)));
+        } else {
             GemmArgs g{mr, mr, 2 * (int64_t)nb, -1.0, 0.0, 1.0, 0.0, VW, ldw, WV, ldw, A22, lda,
                        GEMM_LOWER, 1, nullptr};
             BDG_TRY((gemm<F, true>('N', 'C', g, s)));
+            // the next panel (if any) is factored in order on this stream
+            if ((k + b) + b + 1 < n) BDG_TRY(factor_panel(k + b, s));
         }
     }
     // remaining columns are already inside the band
