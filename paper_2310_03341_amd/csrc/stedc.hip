@@ -153,7 +153,6 @@ struct MergeScratch {
     int *posnd;     // k final positions
     int *posdf;     // K - k
     double *lamnd;  // k
-    int *mask;      // K: halves in which a block column is nonzero (1 top, 2 bottom)
     int *ctop;      // nondeflated columns touching the top half, and their rows in U
     int *rtop;
     int *cbot;      // ... touching the bottom half
@@ -161,17 +160,28 @@ struct MergeScratch {
     int *info;      // [0]=k [1]=ndef [2]=nrot [3]=error [4]=k_top [5]=k_bot
 };
 
-// z, sorted order and deflation (one workgroup; the scan runs on thread 0)
+// z, sorted order and deflation (one workgroup).  The rank merge, the gathers
+// and the final split of the kept columns by half run on all threads; the
+// deflation scan itself is serial (each test depends on the rotations before
+// it) and runs on thread 0 over chunks of sorted positions that the block
+// stages in LDS, so the scan never waits on global memory.
+constexpr int DCH = 2048;   // sorted positions staged per chunk
+constexpr int DWIN = 1024;  // tail of the deflated list mirrored in LDS (power of two)
 __global__ __launch_bounds__(1024) void merge_deflate(int64_t K, int64_t n1, double rho_in, double sgn,
                                                       const double *__restrict__ Qblk, int64_t ldq,
                                                       const double *__restrict__ lam, MergeScratch m,
                                                       double *__restrict__ rho_out) {
     __shared__ double red[32];
-    const int t = threadIdx.x;
+    __shared__ double sD[DCH], sZ[DCH];
+    __shared__ int sJ[DCH];
+    __shared__ double wD[DWIN];
+    __shared__ int wI[DWIN];
+    __shared__ int wcnt[2][16];
+    __shared__ int shk[3];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const double inv_sqrt2 = 0.70710678118654752440;
     // z from last row of Q1 / first row of Q2
     for (int64_t i = t; i < K; i += blockDim.x) {
-        m.mask[i] = (i < n1) ? 1 : 2;
         double zi;
         if (i < n1) zi = Qblk[(n1 - 1) + i * ldq];
         else zi = sgn * Qblk[n1 + i * ldq];
@@ -197,74 +207,113 @@ __global__ __launch_bounds__(1024) void merge_deflate(int64_t K, int64_t n1, dou
     double mx = 0.0;
     for (int64_t i = t; i < K; i += blockDim.x) mx = fmax(mx, fabs(lam[i]));
     for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-    if ((t & 63) == 0) red[t >> 6] = mx;
+    if (lane == 0) red[w] = mx;
     __syncthreads();
-    if (t != 0) return;
     double dmax = 0.0;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) dmax = fmax(dmax, red[w]);
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) dmax = fmax(dmax, red[q]);
     const double rho = 2.0 * rho_in;
     const double tol = 8.0 * 2.0 * EPS * fmax(dmax, rho);
-    int k = 0, ndef = 0, nrot = 0;
-    int pj = -1;
-    double Dpj = 0.0;
-    // insertion into the deflated list (kept sorted; values arrive nearly sorted)
+
+    // scan state (thread 0): pending column pj with value Dpj, weight zpj and
+    // the halves mpj its column is nonzero in (1 top, 2 bottom)
+    int k = 0, ndef = 0, nrot = 0, pj = -1, mpj = 0;
+    double Dpj = 0.0, zpj = 0.0;
+    // deflated list, kept sorted by insertion (values arrive nearly sorted);
+    // written through to global memory, its last DWIN entries also in LDS
+    auto put_def = [&](int p, double v, int col) {
+        if (p > ndef - DWIN) { wD[p & (DWIN - 1)] = v; wI[p & (DWIN - 1)] = col; }
+        m.Ddf[p] = v;
+        m.dfi[p] = col;
+    };
     auto add_def = [&](int col, double val) {
         int p = ndef;
-        while (p > 0 && m.Ddf[p - 1] > val) {
-            m.Ddf[p] = m.Ddf[p - 1];
-            m.dfi[p] = m.dfi[p - 1];
+        while (p > 0) {
+            const bool inl = p - 1 > ndef - DWIN;
+            const double prev = inl ? wD[(p - 1) & (DWIN - 1)] : m.Ddf[p - 1];
+            if (!(prev > val)) break;
+            put_def(p, prev, inl ? wI[(p - 1) & (DWIN - 1)] : m.dfi[p - 1]);
             --p;
         }
-        m.Ddf[p] = val;
-        m.dfi[p] = col;
+        put_def(p, val, col);
         ++ndef;
     };
-    for (int64_t s = 0; s < K; ++s) {
-        const int j = m.sidx[s];
-        const double Dj = m.Ds[s];
-        const double zj = m.z[j];
-        if (rho * fabs(zj) <= tol) {
-            add_def(j, Dj);
-            continue;
+    // kept column: its half mask goes to posnd, which merge_place overwrites later
+    auto emit = [&]() {
+        m.nd[k] = pj; m.Dnd[k] = Dpj; m.znd[k] = zpj; m.posnd[k] = mpj; ++k;
+    };
+    for (int64_t c0 = 0; c0 < K; c0 += DCH) {
+        const int cn = (int)((K - c0) < DCH ? (K - c0) : DCH);
+        for (int q = t; q < cn; q += blockDim.x) {
+            const int j = m.sidx[c0 + q];
+            sJ[q] = j;
+            sD[q] = m.Ds[c0 + q];
+            sZ[q] = m.z[j];
         }
-        if (pj < 0) { pj = j; Dpj = Dj; continue; }
-        const double zp = m.z[pj];
-        const double r = hypot(zj, zp);
-        const double cc = zj / r, ss = -zp / r;
-        const double tdiff = Dj - Dpj;
-        if (fabs(tdiff * cc * ss) <= tol) {
-            // rotate (pj, j): z_pj -> 0, z_j -> r
-            m.z[j] = r;
-            m.z[pj] = 0.0;
-            m.rotp[nrot] = pj; m.rotq[nrot] = j; m.rotc[nrot] = cc; m.rots[nrot] = ss; ++nrot;
-            const int mk = m.mask[pj] | m.mask[j];
-            m.mask[pj] = mk;
-            m.mask[j] = mk;
-            const double newp = Dpj * cc * cc + Dj * ss * ss;
-            const double newj = Dpj * ss * ss + Dj * cc * cc;
-            add_def(pj, newp);
-            pj = j;
-            Dpj = newj;
-        } else {
-            m.nd[k] = pj; m.Dnd[k] = Dpj; m.znd[k] = m.z[pj]; ++k;
-            pj = j;
-            Dpj = Dj;
+        __syncthreads();
+        if (t == 0) {
+            for (int q = 0; q < cn; ++q) {
+                const int j = sJ[q];
+                const double Dj = sD[q], zj = sZ[q];
+                const int mj = j < n1 ? 1 : 2;
+                if (rho * fabs(zj) <= tol) {
+                    add_def(j, Dj);
+                    continue;
+                }
+                if (pj < 0) { pj = j; Dpj = Dj; zpj = zj; mpj = mj; continue; }
+                // rotation test |(Dj - Dpj) c s| <= tol with c = zj/r, s = -zpj/r
+                const double r2 = zj * zj + zpj * zpj;
+                if (fabs((Dj - Dpj) * zj * zpj) <= tol * r2) {
+                    // rotate (pj, j): z_pj -> 0, z_j -> r
+                    const double r = sqrt(r2);
+                    const double cc = zj / r, ss = -zpj / r;
+                    m.rotp[nrot] = pj; m.rotq[nrot] = j; m.rotc[nrot] = cc; m.rots[nrot] = ss; ++nrot;
+                    const double newp = Dpj * cc * cc + Dj * ss * ss;
+                    const double newj = Dpj * ss * ss + Dj * cc * cc;
+                    add_def(pj, newp);
+                    pj = j; Dpj = newj; zpj = r; mpj |= mj;
+                } else {
+                    emit();
+                    pj = j; Dpj = Dj; zpj = zj; mpj = mj;
+                }
+            }
+            if (c0 + cn == K) {
+                if (pj >= 0) emit();
+                shk[0] = k; shk[1] = ndef; shk[2] = nrot;
+            }
         }
+        __syncthreads();
     }
-    if (pj >= 0) { m.nd[k] = pj; m.Dnd[k] = Dpj; m.znd[k] = m.z[pj]; ++k; }
-    // columns of each half for the split eigenvector product
-    int kt = 0, kb = 0;
-    for (int i = 0; i < k; ++i) {
-        const int mk = m.mask[m.nd[i]];
-        if (mk & 1) { m.ctop[kt] = m.nd[i]; m.rtop[kt] = i; ++kt; }
-        if (mk & 2) { m.cbot[kb] = m.nd[i]; m.rbot[kb] = i; ++kb; }
+    // kept columns of each half (order preserved) for the split eigenvector product
+    const int kk = K > 0 ? shk[0] : 0;
+    int bt = 0, bb = 0;
+    for (int c0 = 0; c0 < kk; c0 += (int)blockDim.x) {
+        const int i = c0 + t;
+        const int mk = i < kk ? m.posnd[i] : 0;
+        const unsigned long long vt = __ballot(mk & 1), vb = __ballot(mk & 2);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        if (lane == 0) { wcnt[0][w] = __popcll(vt); wcnt[1][w] = __popcll(vb); }
+        __syncthreads();
+        int ot = bt + __popcll(vt & below), ob = bb + __popcll(vb & below);
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) {
+            if (q < w) { ot += wcnt[0][q]; ob += wcnt[1][q]; }
+            bt += wcnt[0][q];
+            bb += wcnt[1][q];
+        }
+        if (mk) {
+            const int col = m.nd[i];
+            if (mk & 1) { m.ctop[ot] = col; m.rtop[ot] = i; }
+            if (mk & 2) { m.cbot[ob] = col; m.rbot[ob] = i; }
+        }
+        __syncthreads();
     }
-    m.info[4] = kt;
-    m.info[5] = kb;
-    m.info[0] = k;
-    m.info[1] = ndef;
-    m.info[2] = nrot;
-    *rho_out = rho;
+    if (t == 0) {
+        m.info[4] = bt;
+        m.info[5] = bb;
+        m.info[0] = kk;
+        m.info[1] = K > 0 ? shk[1] : 0;
+        m.info[2] = K > 0 ? shk[2] : 0;
+        *rho_out = rho;
+    }
 }
 
 // Apply the deflation rotations to the block columns (thread per row).
@@ -283,27 +332,31 @@ __global__ void merge_rotate(int64_t K, double *__restrict__ Qblk, int64_t ldq, 
     }
 }
 
-// Secular equation, one thread per root j of D + rho z z^T (rho > 0).
-__global__ void merge_secular(const double *__restrict__ rho_p, MergeScratch m) {
+// Secular equation, one wavefront per root j of D + rho z z^T (rho > 0): the
+// 64 lanes split every sum over the poles (wave reductions, fixed order), and
+// all lanes then take the same step, so the control flow stays uniform.
+__global__ __launch_bounds__(256) void merge_secular(const double *__restrict__ rho_p, MergeScratch m) {
     const int k = m.info[0];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= k) return;
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= k) return;  // the whole wave
     const double rho = *rho_p;
     const double *D = m.Dnd;
     const double *z = m.znd;
-    double ztz = 0.0;
-    // (only the last root needs z^T z; cheap enough to form for all)
-    if (j == k - 1) for (int i = 0; i < k; ++i) ztz += z[i] * z[i];
     int o;
     double lo, hi;  // bracket for tau relative to D[o]
     if (j < k - 1) {
         const double gap = D[j + 1] - D[j];
         const double mid = 0.5 * gap;
-        double f = 1.0;
-        for (int i = 0; i < k; ++i) f += rho * z[i] * z[i] / ((D[i] - D[j]) - mid);
+        double f = 0.0;
+        for (int i = lane; i < k; i += 64) f += rho * z[i] * z[i] / ((D[i] - D[j]) - mid);
+        f = 1.0 + wave_sum(f);
         if (f >= 0.0) { o = j; lo = 0.0; hi = mid; }
         else { o = j + 1; lo = -mid; hi = 0.0; }
     } else {
+        double ztz = 0.0;
+        for (int i = lane; i < k; i += 64) ztz += z[i] * z[i];
+        ztz = wave_sum(ztz);
         o = j;
         lo = 0.0;
         hi = rho * ztz;
@@ -313,7 +366,7 @@ __global__ void merge_secular(const double *__restrict__ rho_p, MergeScratch m) 
     bool conv = false;
     for (int it = 0; it < 100; ++it) {
         double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0, aerr = 0.0;
-        for (int i = 0; i < k; ++i) {
+        for (int i = lane; i < k; i += 64) {
             const double del = (D[i] - Do) - tau;
             const double q = z[i] / del;
             const double term = rho * z[i] * q;
@@ -321,6 +374,11 @@ __global__ void merge_secular(const double *__restrict__ rho_p, MergeScratch m) 
             else { phi += term; dphi += rho * q * q; }
             aerr += fabs(term);
         }
+        psi = wave_sum(psi);
+        dpsi = wave_sum(dpsi);
+        phi = wave_sum(phi);
+        dphi = wave_sum(dphi);
+        aerr = wave_sum(aerr);
         const double f = 1.0 + psi + phi;
         if (fabs(f) <= 8.0 * EPS * (1.0 + aerr) * (double)(k < 8 ? 8 : k) / 8.0 * 4.0) { conv = true; break; }
         if (f < 0.0) lo = tau; else hi = tau;
@@ -351,25 +409,35 @@ __global__ void merge_secular(const double *__restrict__ rho_p, MergeScratch m) 
         if (tn == tau) { conv = true; break; }
         tau = tn;
     }
+    if (lane != 0) return;
     if (!conv) atomicOr(&m.info[3], 1);
     m.orig[j] = o;
     m.tau[j] = tau;
     m.lamnd[j] = Do + tau;
 }
 
-// z-hat by the Loewner formula (thread per i).
-__global__ void merge_zhat(const double *__restrict__ rho_p, MergeScratch m) {
+// z-hat by the Loewner formula, one wavefront per i: every factor of the
+// product except lambda_{k-1}/rho lies in (0, 1) by interlacing, so the
+// lanes' partial products cannot overflow.
+__global__ __launch_bounds__(256) void merge_zhat(const double *__restrict__ rho_p, MergeScratch m) {
     const int k = m.info[0];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= k) return;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= k) return;  // the whole wave
     const double rho = *rho_p;
     const double *D = m.Dnd;
     const double Di = D[i];
     // lambda_j - D_i = (D[o_j] - D_i) + tau_j
     auto lmd = [&](int jj) { return (D[m.orig[jj]] - Di) + m.tau[jj]; };
-    double prod = lmd(k - 1) / rho;
-    for (int jj = 0; jj < i; ++jj) prod *= lmd(jj) / (D[jj] - Di);
-    for (int jj = i + 1; jj < k; ++jj) prod *= lmd(jj - 1) / (D[jj] - Di);
+    double prod = 1.0;
+    for (int jj = lane; jj < k; jj += 64) {
+        if (jj < i) prod *= lmd(jj) / (D[jj] - Di);
+        else if (jj > i) prod *= lmd(jj - 1) / (D[jj] - Di);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) prod *= __shfl_xor(prod, o, 64);
+    if (lane != 0) return;
+    prod *= lmd(k - 1) / rho;
     double zh = sqrt(fabs(prod));
     if (m.znd[i] < 0.0) zh = -zh;
     m.zhat[i] = zh;
@@ -481,7 +549,6 @@ int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *
     ms.posnd = (int *)take(4 * (size_t)n);
     ms.posdf = (int *)take(4 * (size_t)n);
     ms.lamnd = (double *)take(8 * (size_t)n);
-    ms.mask = (int *)take(4 * (size_t)n);
     ms.ctop = (int *)take(4 * (size_t)n);
     ms.rtop = (int *)take(4 * (size_t)n);
     ms.cbot = (int *)take(4 * (size_t)n);
@@ -562,9 +629,9 @@ int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *
                 BDG_CHECK_LAUNCH();
             }
             if (k > 0) {
-                hipLaunchKernelGGL(merge_secular, dim3((unsigned)((k + 63) / 64)), dim3(64), 0, s, rho_d, ms);
+                hipLaunchKernelGGL(merge_secular, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, s, rho_d, ms);
                 BDG_CHECK_LAUNCH();
-                hipLaunchKernelGGL(merge_zhat, dim3((unsigned)((k + 63) / 64)), dim3(64), 0, s, rho_d, ms);
+                hipLaunchKernelGGL(merge_zhat, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, s, rho_d, ms);
                 BDG_CHECK_LAUNCH();
                 hipLaunchKernelGGL(merge_vectors, dim3((unsigned)k), dim3(256), 0, s, ms, U);
                 BDG_CHECK_LAUNCH();

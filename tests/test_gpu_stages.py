@@ -52,6 +52,11 @@ def _tridiag_cases():
     cases.append(("decoupled_degenerate", d, e))
     e = np.full(199, 1e-12)
     cases.append(("tiny_coupling", rng.standard_normal(200), e))
+    # merges wider than one staged chunk of the deflation scan, and more
+    # deflated columns than its LDS window (many repeated diagonal values)
+    n = 4500
+    cases.append(("rand4500", rng.standard_normal(n), rng.standard_normal(n - 1)))
+    cases.append(("repeated4500", np.round(rng.uniform(0.0, 4.0, n), 1), 1e-3 * rng.standard_normal(n - 1)))
     return cases
 
 
