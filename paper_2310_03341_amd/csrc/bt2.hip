@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const F *_
         CV v = mk2<F>(0.0, 0.0);
         if (sw < nsw && t < (n - 2 - sw) / b + 1) {
             const int o = r - j;
-            if (o >= 0 && o < b) v = *(const CV *)(V2 + 2 * ((voff[sw] + t) * b + o));
+            if (o >= 0 && o < b) v = ld2<F>(V2 + 2 * ((voff[sw] + t) * b + o));
         }
         Vs[r + j * VLD] = v;
     }
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const F *_
         __syncthreads();
     }
     for (int e = tid; e < NBK * NBK; e += blockDim.x)
-        *(CV *)(TF + 2 * (blk * NBK * NBK + e)) = Ts[e];
+        st2<F>(TF + 2 * (blk * NBK * NBK + e), Ts[e]);
 }
 
 // One 16-row tile of the Z window (rows rs + 16 rt + ...) in accumulator layout.
@@ -141,7 +141,7 @@ __device__ __forceinline__ void load_tile(const F *__restrict__ Z, int64_t ldz, 
         // a window are in flight together
         const int row = rt * 16 + mfma_row((F)0, lane, q);
         const bool ok = (row < h) & colok;
-        const CV z = *(const CV *)(Z + (int64_t)ok * (2 * ((rs + row) + col * ldz)));
+        const CV z = ld2<F>(Z + (int64_t)ok * (2 * ((rs + row) + col * ldz)));
         zr[q] = ok ? z.x : (F)0;
         zi[q] = ok ? z.y : (F)0;
     }
@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256, OCC) void bt2_apply(int64_t n, int b_rt, int64
                 CV rt4[NBK * NBK / 256];
 #pragma unroll
                 for (int i = 0; i < NBK * NBK / 256; ++i)
-                    rt4[i] = *(const CV *)(TF + 2 * ((S * tmax + t) * NBK * NBK + tid + 256 * i));
+                    rt4[i] = ld2<F>(TF + 2 * ((S * tmax + t) * NBK * NBK + tid + 256 * i));
                 // parallelogram: 96 x 32 entries, 12 per thread, loads issued first
                 CV rv[HT * 16 * NBK / 256];
 #pragma unroll
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256, OCC) void bt2_apply(int64_t n, int b_rt, int64
                     const int o = r - j;
                     const int64_t vbj = vb[j], vtj = vt[j];
                     const bool ok = (r < h) & (o >= 0) & (o < b) & (t < vtj);
-                    const CV v = *(const CV *)(V2 + (int64_t)ok * (2 * ((vbj + t) * b + o)));
+                    const CV v = ld2<F>(V2 + (int64_t)ok * (2 * ((vbj + t) * b + o)));
                     rv[i] = ok ? v : mk2<F>(0.0, 0.0);
                 }
 #pragma unroll
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(256, OCC) void bt2_apply(int64_t n, int b_rt, int64
                 for (int q = 0; q < 4; ++q) {
                     const int row = rt * 16 + mfma_row((F)0, lane, q);
                     const bool ok = row < h && colok;
-                    const CV z = *(const CV *)(Z + (ok ? 2 * ((rs + row) + col * ldz) : 0));
+                    const CV z = ld2<F>(Z + (ok ? 2 * ((rs + row) + col * ldz) : 0));
                     zr[rt][q] = ok ? z.x : (F)0;
                     zi[rt][q] = ok ? z.y : (F)0;
                 }
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(256, OCC) void bt2_apply(int64_t n, int b_rt, int64
                 for (int q = 0; q < 4; ++q) {
                     const int row = rt * 16 + mfma_row((F)0, lane, q);
                     if (row < h && colok)
-                        *(CV *)(Z + 2 * ((rs + row) + col * ldz)) = mk2<F>(zr[rt][q], zi[rt][q]);
+                        st2<F>(Z + 2 * ((rs + row) + col * ldz), mk2<F>(zr[rt][q], zi[rt][q]));
                 }
             }
         }
@@ -351,11 +351,11 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
             const int o = r - j;
             const int64_t vbj = vb[j], vtj = vt[j];
             const bool ok = (r < h) & (o >= 0) & (o < b) & (t < vtj);
-            rv[i] = *(const CV *)(V2 + (int64_t)ok * (2 * ((vbj + t) * b + o)));
+            rv[i] = ld2<F>(V2 + (int64_t)ok * (2 * ((vbj + t) * b + o)));
             vmask |= (unsigned)ok << i;
         }
 #pragma unroll
-        for (int i = 0; i < NT; ++i) rt[i] = *(const CV *)(TF + 2 * ((S * tmax + t) * NBK * NBK + tid + 256 * i));
+        for (int i = 0; i < NT; ++i) rt[i] = ld2<F>(TF + 2 * ((S * tmax + t) * NBK * NBK + tid + 256 * i));
     };
     auto publish = [&](int buf, const CV *rv, const CV *rt, unsigned vmask) {
 #pragma unroll
@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
         for (int q = 0; q < 4; ++q) {
             const int row = rtl * 16 + mfma_row((F)0, lane, q);
             const bool ok = (row < h1) & colok;
-            raw[q] = *(const CV *)(Z + (int64_t)ok * (2 * ((rs1 + row) + col * ldz)));
+            raw[q] = ld2<F>(Z + (int64_t)ok * (2 * ((rs1 + row) + col * ldz)));
             zmask |= (unsigned)ok << (bit0 + q);
         }
     };
@@ -498,6 +498,26 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
                 }
             }
             if (more) {
+                // Consume every prefetched value before the first store of
+                // this block is issued: stores share the load counter, and a
+                // wait placed after (predicated) stores would also wait for
+                // them to reach memory.
+                A4 inr[SHIFT], ini[SHIFT];
+#pragma unroll
+                for (int k = 0; k < SHIFT; ++k) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const bool ok = (zmask >> (4 * k + q)) & 1u;
+                        F a = ok ? zraw[k][q].x : (F)0, c = ok ? zraw[k][q].y : (F)0;
+                        // pins the selects (and the wait for the loads) here
+                        asm volatile("" : "+v"(a), "+v"(c)::"memory");
+                        inr[k][q] = a;
+                        ini[k][q] = c;
+                    }
+                }
+                // the other buffer was last read in block t - 1, before the
+                // barrier that closed it
+                publish(buf ^ 1, rv, rt, vmask);
 #pragma unroll
                 for (int k = 0; k < SHIFT; ++k) store_tile<F>(Z, ldz, rs, k, lane, h, colok, col, zr[k], zi[k]);
 #pragma unroll
@@ -507,16 +527,9 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
                 }
 #pragma unroll
                 for (int k = 0; k < SHIFT; ++k) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const bool ok = (zmask >> (4 * k + q)) & 1u;
-                        zr[HT - SHIFT + k][q] = ok ? zraw[k][q].x : (F)0;
-                        zi[HT - SHIFT + k][q] = ok ? zraw[k][q].y : (F)0;
-                    }
+                    zr[HT - SHIFT + k] = inr[k];
+                    zi[HT - SHIFT + k] = ini[k];
                 }
-                // the other buffer was last read in block t - 1, before the
-                // barrier that closed it
-                publish(buf ^ 1, rv, rt, vmask);
                 __syncthreads();
             } else {
 #pragma unroll

@@ -198,7 +198,7 @@ int bdg_stage_hb2st(int64_t n, int band, double *AB, int64_t ldab, double *d, do
         BDG_HIP(hipMemcpyAsync(voff, vh.data(), 8 * (size_t)(n - 2), hipMemcpyHostToDevice, s));
         BDG_HIP(hipStreamSynchronize(s));
     }
-    return bdg::hb2st(n, band, AB, ldab, V2, tau2, voff, d, e, s);
+    return bdg::hb2st(n, band, AB, ldab, V2, tau2, d, e, s);
 }
 
 int bdg_stage_stedc(int64_t n, const double *d, const double *e, double *W, double *Q, int leaf,

@@ -64,10 +64,33 @@ __host__ __device__ inline typename v2t<T>::type mk2(T x, T y) {
     v.y = y;
     return v;
 }
+// 16-byte (8-byte for float) loads and stores of one complex element through
+// the native vector type: a copy of the HIP vector struct is a memcpy that
+// keeps arrays of such values out of registers.
+template <typename T> struct nv2;
+template <> struct nv2<double> { typedef double __attribute__((ext_vector_type(2))) type; };
+template <> struct nv2<float> { typedef float __attribute__((ext_vector_type(2))) type; };
 template <typename T>
-__device__ inline typename v2t<T>::type ld2(const T *p) { return *(const typename v2t<T>::type *)p; }
+__device__ inline typename v2t<T>::type ld2(const T *p) {
+    const typename nv2<T>::type v = *(const typename nv2<T>::type *)p;
+    return mk2<T>(v.x, v.y);
+}
 template <typename T>
-__device__ inline void st2(T *p, typename v2t<T>::type v) { *(typename v2t<T>::type *)p = v; }
+__device__ inline void st2(T *p, typename v2t<T>::type v) {
+    typename nv2<T>::type w;
+    w.x = v.x;
+    w.y = v.y;
+    *(typename nv2<T>::type *)p = w;
+}
+
+// c ? a : b per component (a select of whole structs goes through memory)
+template <typename V>
+__device__ inline V sel2(bool c, V a, V b) {
+    V r;
+    r.x = c ? a.x : b.x;
+    r.y = c ? a.y : b.y;
+    return r;
+}
 
 // Wave-level reductions (64 lanes).
 template <typename T>

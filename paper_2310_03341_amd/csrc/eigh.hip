@@ -227,7 +227,7 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
         BDG_HIP(hipMemcpyAsync(voff, vh.data(), 8 * (size_t)(n - 2), hipMemcpyHostToDevice, s));
         BDG_HIP(hipStreamSynchronize(s));
     }
-    BDG_TRY(hb2st(n, b, AB, L.ldab, V2, tau2, voff, d, ec, s));
+    BDG_TRY(hb2st(n, b, AB, L.ldab, V2, tau2, d, ec, s));
     BDG_TRY(phases(n, ec, ph, ea, s));
     tm.mark(3, "hb2st");
     BDG_TRY(stedc(n, d, ea, W2, Y, n, scratch, s, leaf));
@@ -367,7 +367,7 @@ int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
         BDG_HIP(hipMemcpyAsync(voff, vh.data(), 8 * (size_t)(n - 2), hipMemcpyHostToDevice, s));
         BDG_HIP(hipStreamSynchronize(s));  // vh goes out of scope
     }
-    BDG_TRY(hb2st(n, b, AB, L.ldab, V2, tau2, voff, d, ec, s));
+    BDG_TRY(hb2st(n, b, AB, L.ldab, V2, tau2, d, ec, s));
     BDG_TRY(phases(n, ec, ph, ea, s));
     tm.mark(3, "hb2st");
     // ---- tridiagonal divide and conquer

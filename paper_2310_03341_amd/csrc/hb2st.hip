@@ -29,18 +29,33 @@ constexpr int LDS = BMAX + 1;
 constexpr int LAG = 2;  // task t of sweep s runs in step t + LAG s
 
 
-template <typename F>
-__global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restrict__ AB,
-                                                  int64_t ldab, F *__restrict__ V2,
-                                                  F *__restrict__ tau2,
-                                                  const int64_t *__restrict__ voff, int64_t g,
+// Offset of sweep s's first reflector, sum over s' < s of T_s' with
+// T_s = (n - 2 - s) / b + 1, in closed form: with m = n - 2 and
+// P(N) = sum_{j <= N} floor(j / b), it is s + P(m) - P(m - s).  Computed in
+// the kernel so that loading the previous reflector waits on no other load.
+__host__ __device__ inline int64_t sweep_offset(int64_t n, int b, int64_t s) {
+    auto P = [b](int64_t N) {
+        const int64_t q = N / b, r = N - q * b;
+        return (int64_t)b * q * (q - 1) / 2 + q * (r + 1);
+    };
+    return s + P(n - 2) - P(n - 2 - s);
+}
+
+// One task per workgroup; BT (16, 32 or 64) bounds the band width b so that
+// every loop has a fixed trip count.  All global loads are issued at once,
+// the reflector scalars are computed by every thread (no broadcast step), and
+// the task takes four block barriers.
+template <typename F, int BT>
+__global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restrict__ AB, int64_t ldab,
+                                                  F *__restrict__ V2, F *__restrict__ tau2, int64_t g,
                                                   int64_t s_lo) {
     typedef typename v2t<F>::type CV;
-    __shared__ CV Bs[BMAX * LDS];
-    __shared__ CV Ds[BMAX * LDS];
-    __shared__ CV vp[BMAX], vn[BMAX], yv[BMAX], pv[BMAX], wb[BMAX];
+    constexpr int NE = BT * BT / 256;  // matrix elements per thread
+    constexpr int LD = BT + 1;
+    __shared__ CV Bs[BT * LD];
+    __shared__ CV Ds[BT * LD];
+    __shared__ CV vp[BT], xv[BT], vn[BT], yv[BT], pv[BT], wb[BT];
     __shared__ F red[4][4];
-    __shared__ F sc[8];
     const int64_t s = s_lo + blockIdx.x;
     const int64_t t = g - LAG * s;
     if (s > n - 3 || t < 0) return;
@@ -50,22 +65,21 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
     const int w = tid >> 6, l = tid & 63;
     const int64_t r0 = s + 1 + t * b;
     const int Lr = (int)min((int64_t)b, n - r0);
-    const int64_t ridx = voff[s] + t;
+    const int64_t ridx = sweep_offset(n, b, s) + t;
     const int64_t c0 = r0 - b;
-    F tp = 0.0;
+    const CV zero = mk2<F>(0.0, 0.0);
 
-    // ---- phase 0: load B = A[R, C] (t > 0), D = A[R, R] (full Hermitian), previous v.
-    // Fixed trip counts (64 x 64 tiles, 16 elements per thread) so that all
-    // global loads are issued before their LDS stores.
+    // ---- phase 0: B = A[R, C] (t > 0), D = A[R, R] (full Hermitian), the
+    // previous reflector (t > 0) or the column being removed (t = 0).
+    // Unconditional loads (entry 0 outside the block), zeroed by select.
+    CV rb[NE], rd[NE];
+    F tp = 0.0;
     {
-        CV rb[16], rd[16];
-        // unconditional loads (entry 0 outside the block), zeroed by select:
-        // guarded loads compile to branch + load + wait and run one by one
         unsigned okb = 0, okd = 0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < NE; ++i) {
             const int e = tid + 256 * i;
-            const int r = e & 63, c = e >> 6;
+            const int r = e % BT, c = e / BT;
             const bool ob = (t > 0) & (r < Lr) & (c < b);
             const bool od = (r < Lr) & (c < Lr);
             const int64_t offb = ob ? 2 * ((b + r - c) + (c0 + c) * ldab) : 0;
@@ -75,220 +89,204 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
             okb |= (unsigned)ob << i;
             okd |= (unsigned)od << i;
         }
+        const bool ov = (t > 0) & (tid < b);
+        const bool ox = (t == 0) & (tid < Lr);
+        const CV pv0 = ld2<F>(V2 + (ov ? 2 * ((ridx - 1) * b + tid) : 0));
+        const CV xc0 = ld2<F>(AB + (ox ? 2 * ((1 + tid) + s * ldab) : 0));
+        const F tp0 = tau2[t > 0 ? ridx - 1 : 0];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
+        for (int i = 0; i < NE; ++i) {
             const int e = tid + 256 * i;
-            const int r = e & 63, c = e >> 6;
-            if (!((okb >> i) & 1u)) rb[i] = mk2<F>(0.0, 0.0);
-            if (!((okd >> i) & 1u)) rd[i] = mk2<F>(0.0, 0.0);
+            const int r = e % BT, c = e / BT;
+            if (!((okb >> i) & 1u)) rb[i] = zero;
+            if (!((okd >> i) & 1u)) rd[i] = zero;
             else if (r < c) rd[i].y = -rd[i].y;  // upper entry: conj of the stored lower one
+            Bs[r + c * LD] = rb[i];
+            Ds[r + c * LD] = rd[i];
         }
-        if (t > 0) {
-            if (tid < b) vp[tid] = ld2<F>(V2 + 2 * ((ridx - 1) * b + tid));
-            tp = tau2[ridx - 1];
+        if (tid < BT) {
+            vp[tid] = sel2(ov, pv0, zero);
+            xv[tid] = sel2(ox, xc0, zero);
         }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int e = tid + 256 * i;
-            const int r = e & 63, c = e >> 6;
-            Bs[r + c * LDS] = rb[i];
-            Ds[r + c * LDS] = rd[i];
-        }
+        tp = t > 0 ? tp0 : (F)0.0;
     }
     __syncthreads();
 
-    // ---- phase 1: y = tp * B vp  (row sums, 4 threads per row)
-    if (t > 0) {
-        for (int base = 0; base < Lr * 4; base += blockDim.x) {
-            const int e = base + tid;
-            const int r = e >> 2, q = e & 3;
-            F yr = 0.0, yi = 0.0;
-            if (r < Lr && tp != 0.0) {
-                for (int c = q; c < b; c += 4) {
-                    const CV a = Bs[r + c * LDS], v = vp[c];
-                    yr += a.x * v.x - a.y * v.y;
-                    yi += a.x * v.y + a.y * v.x;
-                }
-            }
-            yr += __shfl_xor(yr, 1, 64); yi += __shfl_xor(yi, 1, 64);
-            yr += __shfl_xor(yr, 2, 64); yi += __shfl_xor(yi, 2, 64);
-            if (r < Lr && q == 0) yv[r] = mk2<F>(tp * yr, tp * yi);
-        }
-        __syncthreads();
-    }
-
-    // ---- phase 2: x (first bulge column after the right update), reflector
+    // ---- phase 1: y = tp B vp and the first bulge column x = B[:, 0] - y
+    // (vp_0 = 1) for t > 0; quads of threads per row.
+    const int qr = tid >> 2, q = tid & 3;
+    CV yr = zero, xr = zero;
     {
-        F t2 = 0.0;
-        for (int r = tid; r < Lr; r += blockDim.x) {
-            CV x;
+        F sr = 0.0, si = 0.0;
+        if (qr < BT) {
+#pragma unroll
+            for (int j = 0; j < BT / 4; ++j) {
+                const int c = q + 4 * j;
+                const CV a = Bs[qr + c * LD], v = vp[c];
+                sr += a.x * v.x - a.y * v.y;
+                si += a.x * v.y + a.y * v.x;
+            }
+        }
+        sr += __shfl_xor(sr, 1, 64); si += __shfl_xor(si, 1, 64);
+        sr += __shfl_xor(sr, 2, 64); si += __shfl_xor(si, 2, 64);
+        F n2 = 0.0;
+        if (qr < BT) {
+            yr = mk2<F>(tp * sr, tp * si);
             if (t > 0) {
-                const CV a = Bs[r], y = yv[r];
-                x = mk2<F>(a.x - y.x, a.y - y.y);  // vp_0 = 1
+                const CV a = Bs[qr];
+                xr = sel2(qr < Lr, mk2<F>(a.x - yr.x, a.y - yr.y), zero);
             } else {
-                x = ld2<F>(AB + 2 * ((1 + r) + s * ldab));
+                xr = xv[qr];
             }
-            vn[r] = x;
-            if (r > 0) t2 += x.x * x.x + x.y * x.y;
+            if (q == 0 && qr > 0) n2 = xr.x * xr.x + xr.y * xr.y;
         }
-        t2 = wave_sum(t2);
-        if (l == 0) red[w][0] = t2;
-        __syncthreads();
-        if (tid == 0) {
-            const F tail2 = red[0][0] + red[1][0] + red[2][0] + red[3][0];
-            const F ar = vn[0].x, ai = vn[0].y;
-            const F aa = sqrt(ar * ar + ai * ai);
-            if (tail2 == 0.0) {
-                sc[0] = 0.0; sc[1] = 0.0; sc[2] = 0.0; sc[3] = ar; sc[4] = ai;
-            } else {
-                const F xn = sqrt(aa * aa + tail2);
-                F sr = 1.0, si = 0.0;
-                if (aa > 0.0) { sr = ar / aa; si = ai / aa; }
-                const F den = aa + xn;
-                sc[0] = sr / den;     // 1/u0 = conj(sgn)/(|a| + |x|)
-                sc[1] = -si / den;
-                sc[2] = den / xn;     // tau
-                sc[3] = -sr * xn;     // beta
-                sc[4] = -si * xn;
-            }
+        n2 = wave_sum(n2);
+        if (qr < BT && q == 0) {
+            yv[qr] = yr;
+            if (t > 0) xv[qr] = xr;  // for t = 0, xv already holds x (read above)
         }
-        __syncthreads();
+        if (l == 0) red[w][0] = n2;
     }
-    const F tj = sc[2];
-    const CV beta = mk2<F>(sc[3], sc[4]);
-    {
-        const F ur = sc[0], ui = sc[1];
-        CV vr0 = mk2<F>(0.0, 0.0);
-        if (tid < b) {
-            CV v;
-            if (tid == 0) v = mk2<F>(1.0, 0.0);
-            else if (tid < Lr && tj != 0.0) {
-                const CV x = vn[tid];
-                v = mk2<F>(x.x * ur - x.y * ui, x.x * ui + x.y * ur);
-            } else v = mk2<F>(0.0, 0.0);
-            vr0 = v;
-            st2<F>(V2 + 2 * (ridx * b + tid), v);
-        }
-        if (tid == 0) tau2[ridx] = tj;
-        __syncthreads();
-        if (tid < b) vn[tid] = vr0;
-        __syncthreads();
-    }
+    __syncthreads();
 
-    // ---- phase 3: wB = v^H B (column sums, original B), gamma = v^H y, p = tau D v
-    if (tj != 0.0) {
+    // ---- phase 2: reflector H = I - tau v v^H with H^H x = beta e_0 (every
+    // thread computes the scalars), v = x / u_0 with v_0 = 1.
+    F tj, ur, ui;
+    CV beta;
+    {
+        const F tail2 = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+        const CV x0 = xv[0];
+        const F aa = sqrt(x0.x * x0.x + x0.y * x0.y);
+        if (tail2 == 0.0) {
+            tj = 0.0; ur = 0.0; ui = 0.0;
+            beta = x0;
+        } else {
+            const F xn = sqrt(aa * aa + tail2);
+            F sgr = 1.0, sgi = 0.0;
+            if (aa > 0.0) { sgr = x0.x / aa; sgi = x0.y / aa; }
+            const F den = aa + xn;
+            ur = sgr / den;  // 1/u0 = conj(sgn)/(|a| + |x|)
+            ui = -sgi / den;
+            tj = den / xn;
+            beta = mk2<F>(-sgr * xn, -sgi * xn);
+        }
+    }
+    if (qr < BT && q == 0) {
+        CV v;
+        if (qr == 0) v = mk2<F>(1.0, 0.0);
+        else if (qr < Lr && tj != 0.0) v = mk2<F>(xr.x * ur - xr.y * ui, xr.x * ui + xr.y * ur);
+        else v = zero;
+        vn[qr] = v;
+        if (qr < b) st2<F>(V2 + 2 * (ridx * b + qr), v);
+    }
+    if (tid == 0) tau2[ridx] = tj;
+    __syncthreads();
+    if (tj == 0.0) {
+        // H = I: only the right update of B remains (t > 0)
         if (t > 0) {
-            for (int base = 0; base < b * 4; base += blockDim.x) {
-                const int e = base + tid;
-                const int c = e >> 2, q = e & 3;
-                F sr = 0.0, si = 0.0;
-                if (c < b) {
-                    for (int r = q; r < Lr; r += 4) {
-                        const CV v = vn[r], a = Bs[r + c * LDS];
-                        sr += v.x * a.x + v.y * a.y;
-                        si += v.x * a.y - v.y * a.x;
-                    }
-                }
-                sr += __shfl_xor(sr, 1, 64); si += __shfl_xor(si, 1, 64);
-                sr += __shfl_xor(sr, 2, 64); si += __shfl_xor(si, 2, 64);
-                if (c < b && q == 0) wb[c] = mk2<F>(sr, si);
+#pragma unroll
+            for (int i = 0; i < NE; ++i) {
+                const int e = tid + 256 * i;
+                const int r = e % BT, c = e / BT;
+                if (r >= Lr || c >= b) continue;
+                CV a = rb[i];
+                const CV vpc = vp[c], y = yv[r];
+                a.x -= y.x * vpc.x + y.y * vpc.y;
+                a.y -= y.y * vpc.x - y.x * vpc.y;
+                st2<F>(AB + 2 * ((b + r - c) + (c0 + c) * ldab), a);
             }
         }
-        for (int base = 0; base < Lr * 4; base += blockDim.x) {
-            const int e = base + tid;
-            const int r = e >> 2, q = e & 3;
-            F pr = 0.0, pi = 0.0;
-            if (r < Lr) {
-                for (int c = q; c < Lr; c += 4) {
-                    const CV a = Ds[r + c * LDS], v = vn[c];
-                    pr += a.x * v.x - a.y * v.y;
-                    pi += a.x * v.y + a.y * v.x;
-                }
+        return;
+    }
+
+    // ---- phase 3: p = tau D v (rows), wB = v^H B (columns, t > 0),
+    // K = (tau/2) v^H p and gamma = v^H y.
+    {
+        F pr = 0.0, pi = 0.0, wr = 0.0, wi = 0.0;
+        if (qr < BT) {
+#pragma unroll
+            for (int j = 0; j < BT / 4; ++j) {
+                const int c = q + 4 * j;
+                const CV a = Ds[qr + c * LD], v = vn[c];
+                pr += a.x * v.x - a.y * v.y;
+                pi += a.x * v.y + a.y * v.x;
             }
-            pr += __shfl_xor(pr, 1, 64); pi += __shfl_xor(pi, 1, 64);
-            pr += __shfl_xor(pr, 2, 64); pi += __shfl_xor(pi, 2, 64);
-            if (r < Lr && q == 0) pv[r] = mk2<F>(tj * pr, tj * pi);
-        }
-        __syncthreads();
-        // K = (tau/2) v^H p  and  gamma = v^H y
-        F kr = 0.0, ki = 0.0, gr = 0.0, gi = 0.0;
-        for (int r = tid; r < Lr; r += blockDim.x) {
-            const CV v = vn[r], p = pv[r];
-            kr += v.x * p.x + v.y * p.y;
-            ki += v.x * p.y - v.y * p.x;
             if (t > 0) {
-                const CV y = yv[r];
-                gr += v.x * y.x + v.y * y.y;
-                gi += v.x * y.y - v.y * y.x;
+#pragma unroll
+                for (int j = 0; j < BT / 4; ++j) {
+                    const int r = q + 4 * j;
+                    const CV v = vn[r], a = Bs[r + qr * LD];
+                    wr += v.x * a.x + v.y * a.y;
+                    wi += v.x * a.y - v.y * a.x;
+                }
             }
+        }
+        pr += __shfl_xor(pr, 1, 64); pi += __shfl_xor(pi, 1, 64);
+        pr += __shfl_xor(pr, 2, 64); pi += __shfl_xor(pi, 2, 64);
+        wr += __shfl_xor(wr, 1, 64); wi += __shfl_xor(wi, 1, 64);
+        wr += __shfl_xor(wr, 2, 64); wi += __shfl_xor(wi, 2, 64);
+        F kr = 0.0, ki = 0.0, gr = 0.0, gi = 0.0;
+        if (qr < BT && q == 0) {
+            const CV p = mk2<F>(tj * pr, tj * pi);
+            pv[qr] = p;
+            wb[qr] = mk2<F>(wr, wi);
+            const CV v = vn[qr];
+            kr = v.x * p.x + v.y * p.y;
+            ki = v.x * p.y - v.y * p.x;
+            gr = v.x * yr.x + v.y * yr.y;
+            gi = v.x * yr.y - v.y * yr.x;
         }
         kr = wave_sum(kr); ki = wave_sum(ki); gr = wave_sum(gr); gi = wave_sum(gi);
         if (l == 0) { red[w][0] = kr; red[w][1] = ki; red[w][2] = gr; red[w][3] = gi; }
-        __syncthreads();
-        if (tid == 0) {
-            sc[5] = 0.5 * tj * (red[0][0] + red[1][0] + red[2][0] + red[3][0]);
-            sc[6] = 0.5 * tj * (red[0][1] + red[1][1] + red[2][1] + red[3][1]);
-            sc[7] = 0.0;
-            red[0][2] = red[0][2] + red[1][2] + red[2][2] + red[3][2];
-            red[0][3] = red[0][3] + red[1][3] + red[2][3] + red[3][3];
-        }
-        __syncthreads();
     }
+    __syncthreads();
 
-    // ---- phase 4: write B and D
+    // ---- phase 4: write B (t > 0) or the removed column (t = 0), and D
+    const F Kr = 0.5 * tj * (red[0][0] + red[1][0] + red[2][0] + red[3][0]);
+    const F Ki = 0.5 * tj * (red[0][1] + red[1][1] + red[2][1] + red[3][1]);
+    const F gmr = red[0][2] + red[1][2] + red[2][2] + red[3][2];
+    const F gmi = red[0][3] + red[1][3] + red[2][3] + red[3][3];
     if (t > 0) {
-        const F gmr = red[0][2], gmi = red[0][3];
-#pragma unroll 4
-        for (int i = 0; i < 16; ++i) {
+#pragma unroll
+        for (int i = 0; i < NE; ++i) {
             const int e = tid + 256 * i;
-            const int r = e & 63, c = e >> 6;
+            const int r = e % BT, c = e / BT;
             if (r >= Lr || c >= b) continue;
             CV a;
             if (c == 0) {
-                a = (tj == 0.0) ? mk2<F>(vn[0].x * 0 + Bs[r].x - yv[r].x, Bs[r].y - yv[r].y)
-                                : (r == 0 ? beta : mk2<F>(0.0, 0.0));
+                a = sel2(r == 0, beta, zero);
             } else {
-                a = Bs[r + c * LDS];
+                a = rb[i];
                 const CV vpc = vp[c], y = yv[r];
                 // right update: - y conj(vp_c)
                 a.x -= y.x * vpc.x + y.y * vpc.y;
                 a.y -= y.y * vpc.x - y.x * vpc.y;
-                if (tj != 0.0) {
-                    // left update: - tau v_r (wB_c - gamma conj(vp_c)),  gamma = v^H y (y holds tp)
-                    const CV wbc = wb[c];
-                    const F qr = wbc.x - (gmr * vpc.x + gmi * vpc.y);
-                    const F qi = wbc.y - (gmi * vpc.x - gmr * vpc.y);
-                    const CV v = vn[r];
-                    a.x -= tj * (v.x * qr - v.y * qi);
-                    a.y -= tj * (v.x * qi + v.y * qr);
-                }
+                // left update: - tau v_r (wB_c - gamma conj(vp_c)),  gamma = v^H y (y holds tp)
+                const CV wbc = wb[c];
+                const F qre = wbc.x - (gmr * vpc.x + gmi * vpc.y);
+                const F qim = wbc.y - (gmi * vpc.x - gmr * vpc.y);
+                const CV v = vn[r];
+                a.x -= tj * (v.x * qre - v.y * qim);
+                a.y -= tj * (v.x * qim + v.y * qre);
             }
             st2<F>(AB + 2 * ((b + r - c) + (c0 + c) * ldab), a);
         }
-    } else {
-        for (int r = tid; r < Lr; r += blockDim.x) {
-            const CV a = (tj == 0.0) ? vn[r] : (r == 0 ? beta : mk2<F>(0.0, 0.0));
-            // when tj == 0 the column is unchanged (vn was overwritten by v; reload)
-            if (tj == 0.0) continue;
-            st2<F>(AB + 2 * ((1 + r) + s * ldab), a);
-        }
+    } else if (tid < Lr) {
+        st2<F>(AB + 2 * ((1 + tid) + s * ldab), sel2(tid == 0, beta, zero));
     }
-    if (tj != 0.0) {
-        const F Kr = sc[5], Ki = sc[6];
-#pragma unroll 4
-        for (int i = 0; i < 16; ++i) {
-            const int e = tid + 256 * i;
-            const int r = e & 63, c = e >> 6;
-            if (r >= Lr || c >= Lr || r < c) continue;
-            const CV vr = vn[r], vc = vn[c], pr = pv[r], pc = pv[c];
-            const CV wr = mk2<F>(pr.x - (Kr * vr.x - Ki * vr.y), pr.y - (Kr * vr.y + Ki * vr.x));
-            const CV wc = mk2<F>(pc.x - (Kr * vc.x - Ki * vc.y), pc.y - (Kr * vc.y + Ki * vc.x));
-            CV a = Ds[r + c * LDS];
-            a.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
-            a.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
-            if (r == c) a.y = 0.0;
-            st2<F>(AB + 2 * ((r - c) + (r0 + c) * ldab), a);
-        }
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+        const int e = tid + 256 * i;
+        const int r = e % BT, c = e / BT;
+        if (r >= Lr || c >= Lr || r < c) continue;
+        const CV vr = vn[r], vc = vn[c], pr = pv[r], pc = pv[c];
+        const CV wr = mk2<F>(pr.x - (Kr * vr.x - Ki * vr.y), pr.y - (Kr * vr.y + Ki * vr.x));
+        const CV wc = mk2<F>(pc.x - (Kr * vc.x - Ki * vc.y), pc.y - (Kr * vc.y + Ki * vc.x));
+        CV a = rd[i];
+        a.x -= (vr.x * wc.x + vr.y * wc.y) + (wr.x * vc.x + wr.y * vc.y);
+        a.y -= (vr.y * wc.x - vr.x * wc.y) + (wr.y * vc.x - wr.x * vc.y);
+        if (r == c) a.y = 0.0;
+        st2<F>(AB + 2 * ((r - c) + (r0 + c) * ldab), a);
     }
 }
 
@@ -322,8 +320,8 @@ void hb2st_offsets(int64_t n, int b, int64_t *voff_host) {
 }
 
 template <typename F>
-int hb2st_t(int64_t n, int b, F *AB, int64_t ldab, F *V2, F *tau2, const int64_t *voff_dev,
-            double *d, double *e_cplx, hipStream_t s) {
+int hb2st_t(int64_t n, int b, F *AB, int64_t ldab, F *V2, F *tau2, double *d, double *e_cplx,
+            hipStream_t s) {
     if (b > BMAX) {
         set_error("hb2st: band %d > %d", b, BMAX);
         return BDG_ERR_NOT_IMPLEMENTED;
@@ -340,8 +338,13 @@ int hb2st_t(int64_t n, int b, F *AB, int64_t ldab, F *V2, F *tau2, const int64_t
             int64_t s_hi = g / LAG;
             if (s_hi > nsw - 1) s_hi = nsw - 1;
             if (s_hi < s_lo) continue;
-            hipLaunchKernelGGL((hb2st_step<F>), dim3((unsigned)(s_hi - s_lo + 1)), dim3(256), 0, s, n, b,
-                               AB, ldab, V2, tau2, voff_dev, g, s_lo);
+            const dim3 grid((unsigned)(s_hi - s_lo + 1));
+            if (b <= 16)
+                hipLaunchKernelGGL((hb2st_step<F, 16>), grid, dim3(256), 0, s, n, b, AB, ldab, V2, tau2, g, s_lo);
+            else if (b <= 32)
+                hipLaunchKernelGGL((hb2st_step<F, 32>), grid, dim3(256), 0, s, n, b, AB, ldab, V2, tau2, g, s_lo);
+            else
+                hipLaunchKernelGGL((hb2st_step<F, 64>), grid, dim3(256), 0, s, n, b, AB, ldab, V2, tau2, g, s_lo);
         }
         BDG_CHECK_LAUNCH();
     }
@@ -355,13 +358,13 @@ int hb2st_t(int64_t n, int b, F *AB, int64_t ldab, F *V2, F *tau2, const int64_t
 
 namespace bdg {
 
-int hb2st(int64_t n, int b, double *AB, int64_t ldab, double *V2, double *tau2,
-          const int64_t *voff_dev, double *d, double *e_cplx, hipStream_t s) {
-    return hb2st_t<double>(n, b, AB, ldab, V2, tau2, voff_dev, d, e_cplx, s);
+int hb2st(int64_t n, int b, double *AB, int64_t ldab, double *V2, double *tau2, double *d,
+          double *e_cplx, hipStream_t s) {
+    return hb2st_t<double>(n, b, AB, ldab, V2, tau2, d, e_cplx, s);
 }
-int hb2st(int64_t n, int b, float *AB, int64_t ldab, float *V2, float *tau2,
-          const int64_t *voff_dev, double *d, double *e_cplx, hipStream_t s) {
-    return hb2st_t<float>(n, b, AB, ldab, V2, tau2, voff_dev, d, e_cplx, s);
+int hb2st(int64_t n, int b, float *AB, int64_t ldab, float *V2, float *tau2, double *d,
+          double *e_cplx, hipStream_t s) {
+    return hb2st_t<float>(n, b, AB, ldab, V2, tau2, d, e_cplx, s);
 }
 
 }  // namespace bdg

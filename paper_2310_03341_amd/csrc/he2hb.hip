@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void panel_step(F *__restrict__ P, int64_t ld,
 #pragma unroll
                     for (int q = 0; q < 16; ++q) {
                         const int c = c0 + q;
-                        pv[q] = (c < nb) ? *(const CV *)(P + 2 * (r + (int64_t)c * ld))
+                        pv[q] = (c < nb) ? ld2<F>(P + 2 * (r + (int64_t)c * ld))
                                          : mk2<F>(0.0, 0.0);
                     }
 #pragma unroll
@@ -173,8 +173,8 @@ __global__ __launch_bounds__(256) void panel_step(F *__restrict__ P, int64_t ld,
                         const int c = c0 + q;
                         if (c >= nb) break;
                         const F wr = wc[2 * c], wi = wc[2 * c + 1];
-                        *(CV *)(P + 2 * (r + (int64_t)c * ld)) =
-                            mk2<F>(pv[q].x - (vr * wr - vi * wi), pv[q].y - (vr * wi + vi * wr));
+                        st2<F>(P + 2 * (r + (int64_t)c * ld),
+                               mk2<F>(pv[q].x - (vr * wr - vi * wi), pv[q].y - (vr * wi + vi * wr)));
                     }
                 }
             }
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void panel_step(F *__restrict__ P, int64_t ld,
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int c = c0 + q;
-                pv[q] = (in && c < nb) ? *(const CV *)(P + 2 * (r + (int64_t)c * ld))
+                pv[q] = (in && c < nb) ? ld2<F>(P + 2 * (r + (int64_t)c * ld))
                                        : mk2<F>(0.0, 0.0);
             }
 #pragma unroll

@@ -27,10 +27,11 @@ namespace bdg {
 // Stage 2: band -> real tridiagonal (d real, e complex before phase scaling).
 int64_t hb2st_nrefl(int64_t n, int b);
 void hb2st_offsets(int64_t n, int b, int64_t *voff_host);
-int hb2st(int64_t n, int b, double *AB, int64_t ldab, double *V2, double *tau2,
-          const int64_t *voff_dev, double *d, double *e_cplx, hipStream_t s);
-int hb2st(int64_t n, int b, float *AB, int64_t ldab, float *V2, float *tau2,
-          const int64_t *voff_dev, double *d, double *e_cplx, hipStream_t s);
+// Reflector (s, t) lands at V2 + b (voff[s] + t), voff as hb2st_offsets gives.
+int hb2st(int64_t n, int b, double *AB, int64_t ldab, double *V2, double *tau2, double *d,
+          double *e_cplx, hipStream_t s);
+int hb2st(int64_t n, int b, float *AB, int64_t ldab, float *V2, float *tau2, double *d,
+          double *e_cplx, hipStream_t s);
 
 // Tridiagonal divide and conquer (FP64): eigenvalues ascending, Q (ld n).
 size_t stedc_workspace(int64_t n);
