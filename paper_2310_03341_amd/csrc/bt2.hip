@@ -63,6 +63,48 @@ __global__ void scale_phase(int64_t n, int64_t m, const double *__restrict__ Y, 
     }
 }
 
+// Row-major copy with the phase scaling folded in:
+// Zrm[r ldr + j] = ph[r] Y[r + (i0 + j) n]  (Y real, ld n); 32 x 32 tiles through LDS.
+template <typename F>
+__global__ __launch_bounds__(256) void scale_phase_rm(int64_t n, int64_t m, const double *__restrict__ Y,
+                                                      int64_t i0, const double *__restrict__ ph,
+                                                      F *__restrict__ Zrm, int64_t ldr) {
+    __shared__ double tile[32][33];
+    const int64_t r0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {  // row r0 + tx of column j0 + k
+        const int64_t r = r0 + tx, j = j0 + k;
+        tile[k][tx] = (r < n && j < m) ? Y[r + (i0 + j) * n] : 0.0;
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {  // column j0 + tx of row r0 + k
+        const int64_t r = r0 + k, j = j0 + tx;
+        if (r < n && j < m) {
+            const double y = tile[tx][k];
+            st2<F>(Zrm + 2 * (r * ldr + j), mk2<F>((F)(ph[2 * r] * y), (F)(ph[2 * r + 1] * y)));
+        }
+    }
+}
+
+// Z[r + j ldz] = Zrm[r ldr + j]; 32 x 32 tiles through LDS.
+template <typename F>
+__global__ __launch_bounds__(256) void rm_to_cm_kernel(int64_t n, int64_t m, const F *__restrict__ Zrm,
+                                                       int64_t ldr, F *__restrict__ Z, int64_t ldz) {
+    typedef typename v2t<F>::type CV;
+    __shared__ CV tile[32][33];
+    const int64_t r0 = (int64_t)blockIdx.x * 32, j0 = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = ty; k < 32; k += 8) {  // column j0 + tx of row r0 + k
+        const int64_t r = r0 + k, j = j0 + tx;
+        tile[k][tx] = (r < n && j < m) ? ld2<F>(Zrm + 2 * (r * ldr + j)) : mk2<F>(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int k = ty; k < 32; k += 8) {  // row r0 + tx of column j0 + k
+        const int64_t r = r0 + tx, j = j0 + k;
+        if (r < n && j < m) st2<F>(Z + 2 * (r + j * ldz), tile[tx][k]);
+    }
+}
+
 // T factor of every block G(S, t): forward column-wise recurrence from
 // V^H V over the parallelogram and the scales tau.  One workgroup per block.
 template <typename F>
@@ -154,7 +196,7 @@ __device__ __forceinline__ void store_tile(F *__restrict__ Z, int64_t ldz, int64
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int row = rt * 16 + mfma_row((F)0, lane, q);
-        if (row < h && colok) *(typename v2t<F>::type *)(Z + 2 * ((rs + row) + col * ldz)) = mk2<F>(zr[q], zi[q]);
+        if (row < h && colok) st2<F>(Z + 2 * ((rs + row) + col * ldz), mk2<F>(zr[q], zi[q]));
     }
 }
 
@@ -311,12 +353,42 @@ __global__ __launch_bounds__(256, OCC) void bt2_apply(int64_t n, int b_rt, int64
     }
 }
 
-// Pipelined variant (b a multiple of 16, SHIFT = b / 16 tiles): while
+// Copy cnt complex entries from global memory to LDS with direct loads
+// (no registers): lane l of each instruction fills the next 16 bytes (FP64)
+// or 4 bytes (FP32) after the wave-uniform LDS base.  One wave.  Issued as
+// inline assembly so that the compiler does not make the next LDS read wait
+// for these loads (it cannot tell that they fill the other buffer); the
+// caller waits for them (vmcnt) before the barrier that publishes the data.
+template <typename F>
+__device__ inline void wave_copy_to_lds(const F *g, typename v2t<F>::type *l, int cnt, int lane) {
+    const unsigned lbase = (unsigned)(size_t)(__attribute__((address_space(3))) void *)l;
+    if constexpr (sizeof(F) == 8) {
+        for (int base = 0; base < cnt; base += 64) {
+            const unsigned m0v = __builtin_amdgcn_readfirstlane(lbase + 16u * (unsigned)base);
+            if (base + lane < cnt)
+                asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                             :: "v"(g + 2 * (base + lane)), "s"(m0v) : "memory", "m0");
+        }
+    } else {
+        for (int base = 0; base < 2 * cnt; base += 64) {
+            const unsigned m0v = __builtin_amdgcn_readfirstlane(lbase + 4u * (unsigned)base);
+            if (base + lane < 2 * cnt)
+                asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dword %0, off"
+                             :: "v"(g + base + lane), "s"(m0v) : "memory", "m0");
+        }
+    }
+}
+
+// Wait for every vector memory operation of this wave.
+__device__ inline void wait_vm_all() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Pipelined variant (b a multiple of 16, SHIFT = b / 16 tiles; Z column-major
+// with leading dimension ldz, or row-major (RM) with row stride ldz): while
 // the matrix cores work on block t, the loads for block t + 1 are in flight:
-// its V and T go to the other half of a double LDS buffer, and its SHIFT new
-// Z tiles (rows the current block does not touch) to registers; the window
-// rows shared by consecutive blocks stay in registers.
-template <typename F, int SHIFT>
+// its V and T go straight to the other half of a double LDS buffer, and its
+// SHIFT new Z tiles (rows the current block does not touch) to registers; the
+// window rows shared by consecutive blocks stay in registers.
+template <typename F, int SHIFT, bool RM>
 __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, int64_t m,
                                                          const F *__restrict__ V2,
                                                          const int64_t *__restrict__ voff, int64_t nsb,
@@ -324,7 +396,6 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
                                                          F *__restrict__ Z, int64_t ldz) {
     typedef typename v2t<F>::type CV;
     typedef typename acc4<F>::type A4;
-    constexpr int NV = HT * 16 * NBK / 256, NT = NBK * NBK / 256;
     constexpr int b = 16 * SHIFT;  // the launcher guarantees b_rt == 16 SHIFT
     (void)b_rt;
     __shared__ CV Vs[2][VLD * NBK];
@@ -338,42 +409,41 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
     const int64_t col = j0 + wave * 16 + li;
     const bool colok = col < m;
     const int64_t nsw = n - 2;
-    // V (parallelogram) and T of block (S, t) into registers.  The loads are
-    // unconditional (entry 0 outside the parallelogram) and the zeroing waits
-    // for publish(), so nothing consumes them before the products of the
-    // current block have been issued.
-    auto fetch = [&](int64_t S, int64_t t, int h, CV *rv, CV *rt, unsigned &vmask) {
-        vmask = 0;
+    const CV zero = mk2<F>(0.0, 0.0);
+    // Column j of the V parallelogram of block (S, t) is reflector (s0 + j, t),
+    // rows j .. j + b - 1 (stored zero-padded past the matrix end); nothing
+    // ever writes the rows outside that range, which stay zero from the start.
+    // T is the block's 32 x 32 factor, contiguous.  Wave w fills columns
+    // w, w + 4, ... and a quarter of T.
+    for (int i = tid; i < 2 * VLD * NBK; i += 256) (&Vs[0][0])[i] = zero;
+    auto fetch = [&](int64_t S, int64_t t, int bufn) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const int e = tid + 256 * i;
-            const int r = e % (HT * 16), j = e / (HT * 16);
-            const int o = r - j;
-            const int64_t vbj = vb[j], vtj = vt[j];
-            const bool ok = (r < h) & (o >= 0) & (o < b) & (t < vtj);
-            rv[i] = ld2<F>(V2 + (int64_t)ok * (2 * ((vbj + t) * b + o)));
-            vmask |= (unsigned)ok << i;
+        for (int k = 0; k < NBK / 4; ++k) {
+            const int j = wave + 4 * k;
+            CV *dst = &Vs[bufn][j + j * VLD];
+            if (t < vt[j]) wave_copy_to_lds<F>(V2 + 2 * (vb[j] + t) * b, dst, b, lane);
+            else if (lane < b) dst[lane] = zero;  // no such reflector
         }
-#pragma unroll
-        for (int i = 0; i < NT; ++i) rt[i] = ld2<F>(TF + 2 * ((S * tmax + t) * NBK * NBK + tid + 256 * i));
+        constexpr int TQ = NBK * NBK / 4;
+        wave_copy_to_lds<F>(TF + 2 * ((S * tmax + t) * NBK * NBK + wave * TQ), &Ts[bufn][wave * TQ], TQ, lane);
     };
-    auto publish = [&](int buf, const CV *rv, const CV *rt, unsigned vmask) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            const int e = tid + 256 * i;
-            Vs[buf][(e % (HT * 16)) + (e / (HT * 16)) * VLD] = ((vmask >> i) & 1u) ? rv[i] : mk2<F>(0.0, 0.0);
-        }
-#pragma unroll
-        for (int i = 0; i < NT; ++i) Ts[buf][tid + 256 * i] = rt[i];
-    };
+    // complex offset of Z entry (row, this lane's column)
+    auto zoff = [&](int64_t row) -> int64_t { return RM ? row * ldz + col : row + col * ldz; };
     // raw loads of one Z tile; ok bits for its 4 entries in zmask
     auto fetch_tile = [&](int64_t rs1, int rtl, int h1, CV *raw, unsigned &zmask, int bit0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int row = rtl * 16 + mfma_row((F)0, lane, q);
             const bool ok = (row < h1) & colok;
-            raw[q] = ld2<F>(Z + (int64_t)ok * (2 * ((rs1 + row) + col * ldz)));
+            raw[q] = ld2<F>(Z + (int64_t)ok * (2 * zoff(rs1 + row)));
             zmask |= (unsigned)ok << (bit0 + q);
+        }
+    };
+    auto put_tile = [&](int64_t rs1, int rtl, int h1, const A4 &tr, const A4 &ti) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = rtl * 16 + mfma_row((F)0, lane, q);
+            if (row < h1 && colok) st2<F>(Z + 2 * zoff(rs1 + row), mk2<F>(tr[q], ti[q]));
         }
     };
     for (int64_t S = nsb - 1; S >= 0; --S) {
@@ -389,13 +459,22 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
         __syncthreads();
         A4 zr[HT], zi[HT];
         {
-            CV rv[NV], rt[NT];
-            unsigned vmask;
             const int h0 = (int)min((int64_t)(HT * 16), n - (s0 + 1));
-            fetch(S, 0, h0, rv, rt, vmask);
+            fetch(S, 0, 0);
+            CV raw[HT][4];
+            unsigned zm = 0;
 #pragma unroll
-            for (int rtl = 0; rtl < HT; ++rtl) load_tile<F>(Z, ldz, s0 + 1, rtl, lane, h0, colok, col, zr[rtl], zi[rtl]);
-            publish(0, rv, rt, vmask);
+            for (int rtl = 0; rtl < HT; ++rtl) fetch_tile(s0 + 1, rtl, h0, raw[rtl], zm, 4 * rtl);
+            wait_vm_all();
+#pragma unroll
+            for (int rtl = 0; rtl < HT; ++rtl) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const bool ok = (zm >> (4 * rtl + q)) & 1u;
+                    zr[rtl][q] = ok ? raw[rtl][q].x : (F)0;
+                    zi[rtl][q] = ok ? raw[rtl][q].y : (F)0;
+                }
+            }
         }
         __syncthreads();
         for (int64_t t = 0; t < T0; ++t) {
@@ -403,21 +482,29 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
             const int h = (int)min((int64_t)(HT * 16), n - rs);
             const int buf = (int)(t & 1);
             const bool more = t + 1 < T0 && rs + b < n;
-            CV rv[NV], rt[NT];
             CV zraw[SHIFT][4];
-            unsigned vmask = 0, zmask = 0;
+            unsigned zmask = 0;
             if (more) {
+                // the other buffer was last read in block t - 1, before the
+                // barrier that closed it
+                fetch(S, t + 1, buf ^ 1);
                 const int h1 = (int)min((int64_t)(HT * 16), n - (rs + b));
-                fetch(S, t + 1, h1, rv, rt, vmask);
 #pragma unroll
                 for (int k = 0; k < SHIFT; ++k) fetch_tile(rs + b, HT - SHIFT + k, h1, zraw[k], zmask, 4 * k);
             }
             const CV *V = Vs[buf];
             const CV *T = Ts[buf];
             // The three complex products use three real MFMAs each (Gauss'
-            // form: for (a + ib)(c + id), ac, bd and (a + b)(c + d)) instead of four.
+            // form: for (a + ib)(c + id), ac, bd and (a + b)(c + d)) instead of
+            // four.  Each product is a fixed sequence of steps whose LDS
+            // operands are read one step ahead into a second register set;
+            // the scheduling barriers keep those reads ahead of the previous
+            // step's MFMAs, so LDS latency hides behind them (one wave per SIMD).
+            //
             // W = V^H Z:  Re = P1 + P2, Im = P3 + P1 - P2 with
-            // P1 = sum vr zr, P2 = sum vi zi, P3 = sum (vr + vi)(zi - zr)
+            // P1 = sum vr zr, P2 = sum vi zi, P3 = sum (vr + vi)(zi - zr);
+            // step (kt, q) reads V rows 16 kt + .. for column tiles it = 0, 1.
+            auto wvalid = [](int kt, int it) { return !(16 * kt + 15 < 16 * it || 16 * kt > 16 * it + 14 + b); };
             A4 wr[2], wi[2];
             {
                 A4 p1[2], p2[2], p3[2];
@@ -427,20 +514,31 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
                     p2[it] = A4{0, 0, 0, 0};
                     p3[it] = A4{0, 0, 0, 0};
                 }
+                constexpr int NS = HT * 4;
+                CV vc[2], vn[2];
+                auto wload = [&](int st, CV *dst) {
+                    const int kt = st >> 2, q = st & 3;
 #pragma unroll
-                for (int kt = 0; kt < HT; ++kt) {
+                    for (int it = 0; it < 2; ++it)
+                        if (wvalid(kt, it)) dst[it] = V[(16 * kt + mfma_row((F)0, lane, q)) + (16 * it + li) * VLD];
+                };
+                wload(0, vc);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const F d = zi[kt][q] - zr[kt][q];
+                for (int st = 0; st < NS; ++st) {
+                    if (st + 1 < NS) wload(st + 1, vn);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int kt = st >> 2, q = st & 3;
+                    const F d = zi[kt][q] - zr[kt][q];
 #pragma unroll
-                        for (int it = 0; it < 2; ++it) {
-                            if (16 * kt + 15 < 16 * it || 16 * kt > 16 * it + 14 + b) continue;
-                            const CV v = V[(16 * kt + mfma_row((F)0, lane, q)) + (16 * it + li) * VLD];
-                            p1[it] = mfma16(v.x, zr[kt][q], p1[it]);
-                            p2[it] = mfma16(v.y, zi[kt][q], p2[it]);
-                            p3[it] = mfma16(v.x + v.y, d, p3[it]);
-                        }
+                    for (int it = 0; it < 2; ++it) {
+                        if (!wvalid(kt, it)) continue;
+                        p1[it] = mfma16(vc[it].x, zr[kt][q], p1[it]);
+                        p2[it] = mfma16(vc[it].y, zi[kt][q], p2[it]);
+                        p3[it] = mfma16(vc[it].x + vc[it].y, d, p3[it]);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
+                    vc[0] = vn[0];
+                    vc[1] = vn[1];
                 }
 #pragma unroll
                 for (int it = 0; it < 2; ++it) {
@@ -450,58 +548,103 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
             }
             // W2 = T W (T upper triangular), stored negated:
             // Re = Q1 - Q2, Im = Q3 - Q1 - Q2, Q1 = sum tr wr, Q2 = sum ti wi,
-            // Q3 = sum (tr + ti)(wr + wi)
+            // Q3 = sum (tr + ti)(wr + wi); steps (it, kt >= it, q).
             A4 ur[2], ui[2];
             {
                 A4 sw[2];
 #pragma unroll
                 for (int kt = 0; kt < 2; ++kt) sw[kt] = wr[kt] + wi[kt];
+                A4 q1[2], q2[2], q3[2];
 #pragma unroll
                 for (int it = 0; it < 2; ++it) {
-                    A4 q1 = A4{0, 0, 0, 0}, q2 = A4{0, 0, 0, 0}, q3 = A4{0, 0, 0, 0};
+                    q1[it] = A4{0, 0, 0, 0};
+                    q2[it] = A4{0, 0, 0, 0};
+                    q3[it] = A4{0, 0, 0, 0};
+                }
+                // step st: (it, kt, q) = (0, 0, st) for st < 4, (0, 1, st - 4) for st < 8, (1, 1, st - 8)
+                auto tload = [&](int st) {
+                    const int it = st >= 8 ? 1 : 0, kt = st >= 4 ? 1 : 0, q = st & 3;
+                    return T[(16 * it + li) + (16 * kt + mfma_row((F)0, lane, q)) * NBK];
+                };
+                CV tc = tload(0), tn;
 #pragma unroll
-                    for (int kt = it; kt < 2; ++kt) {
+                for (int st = 0; st < 12; ++st) {
+                    if (st + 1 < 12) tn = tload(st + 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int it = st >= 8 ? 1 : 0, kt = st >= 4 ? 1 : 0, q = st & 3;
+                    q1[it] = mfma16(tc.x, wr[kt][q], q1[it]);
+                    q2[it] = mfma16(tc.y, wi[kt][q], q2[it]);
+                    q3[it] = mfma16(tc.x + tc.y, sw[kt][q], q3[it]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    tc = tn;
+                }
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const CV tv = T[(16 * it + li) + (16 * kt + mfma_row((F)0, lane, q)) * NBK];
-                            q1 = mfma16(tv.x, wr[kt][q], q1);
-                            q2 = mfma16(tv.y, wi[kt][q], q2);
-                            q3 = mfma16(tv.x + tv.y, sw[kt][q], q3);
-                        }
-                    }
-                    ur[it] = q2 - q1;
-                    ui[it] = q1 + q2 - q3;
+                for (int it = 0; it < 2; ++it) {
+                    ur[it] = q2[it] - q1[it];
+                    ui[it] = q1[it] + q2[it] - q3[it];
                 }
             }
             // Z += V (-W2): per row tile, Re += Q1 - Q2, Im += Q3 - Q1 - Q2 with
-            // Q1 = sum vr ur, Q2 = sum vi ui, Q3 = sum (vr + vi)(ur + ui)
+            // Q1 = sum vr ur, Q2 = sum vi ui, Q3 = sum (vr + vi)(ur + ui);
+            // steps (rtl, kt, q) over the tiles the parallelogram meets.
             {
                 A4 su[2];
 #pragma unroll
                 for (int kt = 0; kt < 2; ++kt) su[kt] = ur[kt] + ui[kt];
+                constexpr int NS = HT * 8;
+                auto uvalid = [&](int st) { return wvalid(st >> 3, (st >> 2) & 1); };
+                auto uload = [&](int st) {
+                    const int rtl = st >> 3, kt = (st >> 2) & 1, q = st & 3;
+                    return V[(16 * rtl + li) + (16 * kt + mfma_row((F)0, lane, q)) * VLD];
+                };
+                // first valid step, and the valid step after each one
+                auto nextv = [&](int st) {
+                    int x = st + 1;
+                    while (x < NS && !uvalid(x)) ++x;
+                    return x;
+                };
+                // two accumulator sets by row-tile parity: tile rtl - 1 is
+                // folded into Z while the MFMAs of tile rtl run
+                A4 acc[2][3];
 #pragma unroll
-                for (int rtl = 0; rtl < HT; ++rtl) {
-                    A4 q1 = A4{0, 0, 0, 0}, q2 = A4{0, 0, 0, 0}, q3 = A4{0, 0, 0, 0};
+                for (int p = 0; p < 2; ++p)
 #pragma unroll
-                    for (int kt = 0; kt < 2; ++kt) {
-                        if (16 * rtl + 15 < 16 * kt || 16 * rtl > 16 * kt + 14 + b) continue;
+                    for (int c = 0; c < 3; ++c) acc[p][c] = A4{0, 0, 0, 0};
+                auto fold = [&](int rtl) {
+                    A4 *a = acc[rtl & 1];
+                    zr[rtl] += a[0] - a[1];
+                    zi[rtl] += a[2] - a[0] - a[1];
+                    a[0] = A4{0, 0, 0, 0};
+                    a[1] = A4{0, 0, 0, 0};
+                    a[2] = A4{0, 0, 0, 0};
+                };
+                CV uc = uload(nextv(-1)), un;
+                int last_rtl = -1;
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) {
-                            const CV v = V[(16 * rtl + li) + (16 * kt + mfma_row((F)0, lane, q)) * VLD];
-                            q1 = mfma16(v.x, ur[kt][q], q1);
-                            q2 = mfma16(v.y, ui[kt][q], q2);
-                            q3 = mfma16(v.x + v.y, su[kt][q], q3);
-                        }
+                for (int st = 0; st < NS; ++st) {
+                    if (!uvalid(st)) continue;
+                    const int nx = nextv(st);
+                    if (nx < NS) un = uload(nx);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int rtl = st >> 3, kt = (st >> 2) & 1, q = st & 3;
+                    A4 *a = acc[rtl & 1];
+                    a[0] = mfma16(uc.x, ur[kt][q], a[0]);
+                    a[1] = mfma16(uc.y, ui[kt][q], a[1]);
+                    a[2] = mfma16(uc.x + uc.y, su[kt][q], a[2]);
+                    if (rtl != last_rtl) {  // first step of row tile rtl
+                        if (last_rtl >= 0) fold(last_rtl);
+                        last_rtl = rtl;
                     }
-                    zr[rtl] += q1 - q2;
-                    zi[rtl] += q3 - q1 - q2;
+                    __builtin_amdgcn_sched_barrier(0);
+                    uc = un;
                 }
+                fold(last_rtl);
             }
             if (more) {
-                // Consume every prefetched value before the first store of
-                // this block is issued: stores share the load counter, and a
-                // wait placed after (predicated) stores would also wait for
-                // them to reach memory.
+                // Consume every prefetched value (the direct LDS loads were
+                // issued before them) ahead of the first store of this block:
+                // stores share the load counter, and a wait placed after
+                // (predicated) stores would also wait for them to reach memory.
                 A4 inr[SHIFT], ini[SHIFT];
 #pragma unroll
                 for (int k = 0; k < SHIFT; ++k) {
@@ -515,11 +658,9 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
                         ini[k][q] = c;
                     }
                 }
-                // the other buffer was last read in block t - 1, before the
-                // barrier that closed it
-                publish(buf ^ 1, rv, rt, vmask);
+                wait_vm_all();  // the direct LDS loads of block t + 1 (nothing else is pending)
 #pragma unroll
-                for (int k = 0; k < SHIFT; ++k) store_tile<F>(Z, ldz, rs, k, lane, h, colok, col, zr[k], zi[k]);
+                for (int k = 0; k < SHIFT; ++k) put_tile(rs, k, h, zr[k], zi[k]);
 #pragma unroll
                 for (int k = 0; k + SHIFT < HT; ++k) {
                     zr[k] = zr[k + SHIFT];
@@ -533,7 +674,7 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
                 __syncthreads();
             } else {
 #pragma unroll
-                for (int k = 0; k < HT; ++k) store_tile<F>(Z, ldz, rs, k, lane, h, colok, col, zr[k], zi[k]);
+                for (int k = 0; k < HT; ++k) put_tile(rs, k, h, zr[k], zi[k]);
                 break;
             }
         }
@@ -541,6 +682,8 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
 }
 
 }  // namespace
+
+bool bt2_rowmajor_ok(int b) { return b >= 16 && b <= BMAX && b % 16 == 0; }
 
 int64_t bt2_nblocks(int64_t n, int b) {
     const int64_t nsw = n - 2;
@@ -568,6 +711,25 @@ int phase_scale_t(int64_t n, int64_t m, const double *Y, int64_t i0, const doubl
 }
 
 template <typename F>
+int phase_scale_rm_t(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, F *Zrm,
+                     int64_t ldr, hipStream_t s) {
+    if (m <= 0 || n <= 0) return 0;
+    hipLaunchKernelGGL((scale_phase_rm<F>), dim3((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32)), dim3(256),
+                       0, s, n, m, Y, i0, ph, Zrm, ldr);
+    BDG_CHECK_LAUNCH();
+    return 0;
+}
+
+template <typename F>
+int rm_to_cm_t(int64_t n, int64_t m, const F *Zrm, int64_t ldr, F *Z, int64_t ldz, hipStream_t s) {
+    if (m <= 0 || n <= 0) return 0;
+    hipLaunchKernelGGL((rm_to_cm_kernel<F>), dim3((unsigned)((n + 31) / 32), (unsigned)((m + 31) / 32)), dim3(256),
+                       0, s, n, m, Zrm, ldr, Z, ldz);
+    BDG_CHECK_LAUNCH();
+    return 0;
+}
+
+template <typename F>
 int bt2_prepare_t(int64_t n, int b, const F *V2, const F *tau2, const int64_t *voff, void *work,
                   hipStream_t s) {
     if (n < 3) return 0;
@@ -583,7 +745,7 @@ int bt2_prepare_t(int64_t n, int b, const F *V2, const F *tau2, const int64_t *v
 
 template <typename F>
 int bt2_apply_t(int64_t n, int b, int64_t m, const F *V2, const int64_t *voff, F *Z, int64_t ldz,
-                void *work, hipStream_t s) {
+                void *work, hipStream_t s, bool rm = false) {
     if (n < 3 || m <= 0) return 0;
     if (b > BMAX) return BDG_ERR_NOT_IMPLEMENTED;
     const int64_t nsw = n - 2;
@@ -596,13 +758,24 @@ int bt2_apply_t(int64_t n, int b, int64_t m, const F *V2, const int64_t *voff, F
     // ahead of two-per-CU occupancy: 23.7 s for the generic kernel at 384
     // slabs of the 32x32x24 workload against an estimated 2 x 10.3 s);
     // other widths: the generic kernel, two workgroups per CU
+    // Z row-major (rm, row stride ldz): the pipelined kernel only
+    if (rm && !bt2_rowmajor_ok(b)) {
+        set_error("bt2: a row-major Z needs a band width that is a multiple of 16");
+        return BDG_ERR_NOT_IMPLEMENTED;
+    }
+#define BDG_BT2_PIPE(SH)                                                                                     \
+    if (rm) hipLaunchKernelGGL((bt2_apply_pipe<F, SH, true>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, \
+                               tmax, TFw, Z, ldz);                                                           \
+    else hipLaunchKernelGGL((bt2_apply_pipe<F, SH, false>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb,   \
+                            tmax, TFw, Z, ldz);
     switch (b % 16 == 0 ? b / 16 : 0) {
-        case 1: hipLaunchKernelGGL((bt2_apply_pipe<F, 1>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
-        case 2: hipLaunchKernelGGL((bt2_apply_pipe<F, 2>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
-        case 3: hipLaunchKernelGGL((bt2_apply_pipe<F, 3>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
-        case 4: hipLaunchKernelGGL((bt2_apply_pipe<F, 4>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
+        case 1: BDG_BT2_PIPE(1) break;
+        case 2: BDG_BT2_PIPE(2) break;
+        case 3: BDG_BT2_PIPE(3) break;
+        case 4: BDG_BT2_PIPE(4) break;
         default: hipLaunchKernelGGL((bt2_apply<F, 0, 2>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
     }
+#undef BDG_BT2_PIPE
     BDG_CHECK_LAUNCH();
     return 0;
 }
@@ -655,6 +828,33 @@ int bt2_apply_blocks(int64_t n, int b, int64_t m, const double *V2, const int64_
 int bt2_apply_blocks(int64_t n, int b, int64_t m, const float *V2, const int64_t *voff, float *Z,
                      int64_t ldz, void *work, hipStream_t s) {
     return bt2_apply_t<float>(n, b, m, V2, voff, Z, ldz, work, s);
+}
+
+}  // namespace bdg
+
+namespace bdg {
+
+int phase_scale_rm(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, double *Zrm,
+                   int64_t ldr, hipStream_t s) {
+    return phase_scale_rm_t<double>(n, m, Y, i0, ph, Zrm, ldr, s);
+}
+int phase_scale_rm(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, float *Zrm,
+                   int64_t ldr, hipStream_t s) {
+    return phase_scale_rm_t<float>(n, m, Y, i0, ph, Zrm, ldr, s);
+}
+int bt2_apply_blocks_rm(int64_t n, int b, int64_t m, const double *V2, const int64_t *voff, double *Zrm,
+                        int64_t ldr, void *work, hipStream_t s) {
+    return bt2_apply_t<double>(n, b, m, V2, voff, Zrm, ldr, work, s, true);
+}
+int bt2_apply_blocks_rm(int64_t n, int b, int64_t m, const float *V2, const int64_t *voff, float *Zrm,
+                        int64_t ldr, void *work, hipStream_t s) {
+    return bt2_apply_t<float>(n, b, m, V2, voff, Zrm, ldr, work, s, true);
+}
+int rm_to_cm(int64_t n, int64_t m, const double *Zrm, int64_t ldr, double *Z, int64_t ldz, hipStream_t s) {
+    return rm_to_cm_t<double>(n, m, Zrm, ldr, Z, ldz, s);
+}
+int rm_to_cm(int64_t n, int64_t m, const float *Zrm, int64_t ldr, float *Z, int64_t ldz, hipStream_t s) {
+    return rm_to_cm_t<float>(n, m, Zrm, ldr, Z, ldz, s);
 }
 
 }  // namespace bdg

@@ -173,7 +173,10 @@ int bdg_stage_workspace(int stage, int64_t n, int band, int64_t m, size_t *bytes
         case 1: *bytes = bdg::he2hb_workspace(n, band); return 0;
         case 2: *bytes = 0; return 0;
         case 3: *bytes = bdg::stedc_workspace(n); return 0;
-        case 4: *bytes = bdg::bt2_workspace(n, band) + 16 * (size_t)n + 8 * (size_t)n + 512; return 0;
+        case 4:  // phases, T factors, and the row-major copy of Z when the band allows that route
+            *bytes = bdg::bt2_workspace(n, band) + 16 * (size_t)n + 8 * (size_t)n + 1024 +
+                     (bdg::bt2_rowmajor_ok(band) ? 16 * (size_t)n * (size_t)(m > 0 ? m : 0) : 0);
+            return 0;
         case 5: *bytes = bdg::bt1_workspace(n, m, band); return 0;
         default: set_error("bdg_stage_workspace: unknown stage %d", stage); return -1;
     }
@@ -216,12 +219,21 @@ int bdg_stage_bt2(int64_t n, int band, int64_t m, const double *e, const double 
     if (work_bytes < need) return BDG_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)work;
+    auto al = [](size_t x) { return (x + 255) / 256 * 256; };
     double *ph = (double *)w;
-    double *ea = (double *)(w + 16 * (size_t)n + 256);
-    void *rest = w + 16 * (size_t)n + 8 * (size_t)n + 512;
+    double *ea = (double *)(w + al(16 * (size_t)n));
+    void *rest = w + al(16 * (size_t)n) + al(8 * (size_t)n);
     BDG_TRY(bdg::phases(n, e, ph, ea, s));
-    BDG_TRY(bdg::phase_scale(n, m, Y, i0, ph, Z, ldz, s));
-    return bdg::bt2(n, band, m, V2, tau2, voff, Z, ldz, rest, s);
+    if (!bdg::bt2_rowmajor_ok(band) || n < 3 || m <= 0) {
+        BDG_TRY(bdg::phase_scale(n, m, Y, i0, ph, Z, ldz, s));
+        return bdg::bt2(n, band, m, V2, tau2, voff, Z, ldz, rest, s);
+    }
+    // row-major route: Zrm after the T factors
+    double *Zrm = (double *)((char *)rest + (bdg::bt2_workspace(n, band) + 255) / 256 * 256);
+    BDG_TRY(bdg::phase_scale_rm(n, m, Y, i0, ph, Zrm, m, s));
+    BDG_TRY(bdg::bt2_prepare(n, band, V2, tau2, voff, rest, s));
+    BDG_TRY(bdg::bt2_apply_blocks_rm(n, band, m, V2, voff, Zrm, m, rest, s));
+    return bdg::rm_to_cm(n, m, Zrm, m, Z, ldz, s);
 }
 
 int bdg_stage_bt1(int64_t n, int64_t m, const double *A, int64_t lda, int band, const double *T1,

@@ -108,7 +108,7 @@ struct MLayout {
     int b;
     int64_t ldab, np, nrefl;
     size_t off_AB, off_T1, off_V2, off_tau2, off_voff, off_d, off_ec, off_ea, off_ph, off_W2,
-        off_lam, off_flag, off_s1, off_s2, off_s3, off_s4, total;
+        off_lam, off_flag, off_s1, off_s2, off_s3, off_s4, s3_bytes, total;
 };
 
 // Mixed-precision workspace: slot1 = A32 (later the low half of X64), slot2 = Y
@@ -143,7 +143,8 @@ MLayout mlayout(int64_t n, const bdg_opts *o) {
     sc = std::max(sc, bt2_workspace(n, L.b));
     sc = std::max(sc, bt1_workspace(n, n, L.b));
     const size_t rw = refine_workspace(n, n);
-    L.off_s3 = put(std::max(sc, rw / 2 + 65536));
+    L.s3_bytes = std::max(sc, rw / 2 + 65536);
+    L.off_s3 = put(L.s3_bytes);
     L.off_s4 = put(std::max(8 * nn, rw / 2 + 65536));
     L.total = o_ + 256;
     return L;
@@ -235,12 +236,19 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
     // FP32 basis: all columns, or the E >= 0 half and its particle-hole partners
     const int64_t c0 = ph_mirror ? n / 2 : 0;
     const int64_t nc = n - c0;
-    BDG_TRY(phase_scale(n, nc, Y, c0, ph, X32 + 2 * c0 * n, n, s));
+    // row-major route for the back-transformation 2 as in the FP64 driver
+    const size_t tf_bytes = al(bt2_workspace(n, b));
+    const bool rm = n >= 3 && nc > 0 && bt2_rowmajor_ok(b) && tf_bytes + 8 * (size_t)n * nc <= L.s3_bytes;
+    float *Zrm = (float *)((char *)scratch + tf_bytes);
+    if (rm) BDG_TRY(phase_scale_rm(n, nc, Y, c0, ph, Zrm, nc, s));
+    else BDG_TRY(phase_scale(n, nc, Y, c0, ph, X32 + 2 * c0 * n, n, s));
     tm.mark(5, "phase scaling");
     BDG_TRY(bt2_prepare(n, b, V2, tau2, voff, scratch, s));
     tm.mark(10);
-    BDG_TRY(bt2_apply_blocks(n, b, nc, V2, voff, X32 + 2 * c0 * n, n, scratch, s));
+    if (rm) BDG_TRY(bt2_apply_blocks_rm(n, b, nc, V2, voff, Zrm, nc, scratch, s));
+    else BDG_TRY(bt2_apply_blocks(n, b, nc, V2, voff, X32 + 2 * c0 * n, n, scratch, s));
     tm.mark(11);
+    if (rm) BDG_TRY(rm_to_cm(n, nc, Zrm, nc, X32 + 2 * c0 * n, n, s));
     tm.mark(6, "bt2");
     BDG_TRY(bt1(n, nc, A32, n, b, T1, X32 + 2 * c0 * n, n, scratch, s));
     if (ph_mirror) {
@@ -399,13 +407,21 @@ int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
     }
     const int64_t mb = bt_hi - bt_lo;
     double *Zb = Z + 2 * (bt_lo - i0) * ldz;
-    BDG_TRY(phase_scale(n, mb, Y, bt_lo, ph, Zb, ldz, s));
+    // back-transformation 2 on a row-major copy of Z when the scratch holds it
+    // after the block T factors (rows of a block are then contiguous)
+    const size_t tf_bytes = al(bt2_workspace(n, b));
+    const bool rm = n >= 3 && mb > 0 && bt2_rowmajor_ok(b) && tf_bytes + 16 * (size_t)n * mb <= L.scratch;
+    double *Zrm = (double *)((char *)scratch + tf_bytes);
+    if (rm) BDG_TRY(phase_scale_rm(n, mb, Y, bt_lo, ph, Zrm, mb, s));
+    else BDG_TRY(phase_scale(n, mb, Y, bt_lo, ph, Zb, ldz, s));
     tm.mark(5, "window + phase scaling");
     // ---- back-transformation 2 (band <- tridiagonal), then 1 (dense <- band)
     BDG_TRY(bt2_prepare(n, b, V2, tau2, voff, scratch, s));
     tm.mark(8);
-    BDG_TRY(bt2_apply_blocks(n, b, mb, V2, voff, Zb, ldz, scratch, s));
+    if (rm) BDG_TRY(bt2_apply_blocks_rm(n, b, mb, V2, voff, Zrm, mb, scratch, s));
+    else BDG_TRY(bt2_apply_blocks(n, b, mb, V2, voff, Zb, ldz, scratch, s));
     tm.mark(9);
+    if (rm) BDG_TRY(rm_to_cm(n, mb, Zrm, mb, Zb, ldz, s));
     tm.mark(6, "bt2");
     BDG_TRY(bt1(n, mb, A, lda, b, T1, Zb, ldz, scratch, s));
     if (mirror) BDG_TRY(mirror_columns(n, Z, ldz, 0, (n - 1 - i0) - i0, h - i0, s));

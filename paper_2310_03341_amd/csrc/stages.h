@@ -55,6 +55,20 @@ int bt2_apply_blocks(int64_t n, int b, int64_t m, const double *V2, const int64_
 int bt2_apply_blocks(int64_t n, int b, int64_t m, const float *V2, const int64_t *voff, float *Z,
                      int64_t ldz, void *work, hipStream_t s);
 size_t bt2_workspace(int64_t n, int b);
+// Row-major route for the back-transformation 2 (band widths that are a
+// multiple of 16): Zrm [n x m], row stride ldr >= m, built from Y with the
+// phase scaling, transformed in place, then copied to column-major Z.
+bool bt2_rowmajor_ok(int b);
+int phase_scale_rm(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, double *Zrm,
+                   int64_t ldr, hipStream_t s);
+int phase_scale_rm(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, float *Zrm,
+                   int64_t ldr, hipStream_t s);
+int bt2_apply_blocks_rm(int64_t n, int b, int64_t m, const double *V2, const int64_t *voff, double *Zrm,
+                        int64_t ldr, void *work, hipStream_t s);
+int bt2_apply_blocks_rm(int64_t n, int b, int64_t m, const float *V2, const int64_t *voff, float *Zrm,
+                        int64_t ldr, void *work, hipStream_t s);
+int rm_to_cm(int64_t n, int64_t m, const double *Zrm, int64_t ldr, double *Z, int64_t ldz, hipStream_t s);
+int rm_to_cm(int64_t n, int64_t m, const float *Zrm, int64_t ldr, float *Z, int64_t ldz, hipStream_t s);
 int bt2(int64_t n, int b, int64_t m, const double *V2, const double *tau2, const int64_t *voff,
         double *Z, int64_t ldz, void *work, hipStream_t s);
 int bt2(int64_t n, int b, int64_t m, const float *V2, const float *tau2, const int64_t *voff,
