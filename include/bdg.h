@@ -85,6 +85,11 @@ typedef struct {
 /* Progress: when the environment variable BDG_VERBOSE is set (and not "0"),
  * bdg_eigh waits for each stage and prints one line per finished stage and
  * per refinement step to stderr.  Off by default (no extra synchronisation). */
+/* Look-ahead: stage 1 factors the next panel on a second stream of the library
+ * while the trailing update runs on the caller's stream.  When the environment
+ * variable BDG_NO_LOOKAHEAD is set (and not "0"), every panel is factored on
+ * the caller's stream instead (same results; for tools that serialise
+ * dispatches, such as hardware-counter profilers). */
 
 /* Per-call accuracy and timing report (filled when non-NULL). */
 typedef struct {

@@ -28,6 +28,14 @@ bool verbose() {
     return v;
 }
 
+bool lookahead() {
+    static const bool v = [] {
+        const char *e = getenv("BDG_NO_LOOKAHEAD");
+        return !(e && e[0] && e[0] != '0');
+    }();
+    return v;
+}
+
 int hip_fail(hipError_t e, const char *what, const char *file, int line) {
     set_error("HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e), what, file, line);
     return BDG_ERR_HIP;

@@ -122,6 +122,8 @@ namespace bdg {
 void set_error(const char* fmt, ...);
 // true when the environment sets BDG_VERBOSE (progress lines on stderr)
 bool verbose();
+// false when the environment sets BDG_NO_LOOKAHEAD (stage 1 on one stream)
+bool lookahead();
 int hip_fail(hipError_t e, const char* what, const char* file, int line);
 }  // namespace bdg
 

@@ -490,7 +490,7 @@ int he2hb_t(int64_t n, F *A, int64_t lda, int b, F *AB, int64_t ldab, F *T1,
             BDG_CHECK_LAUNCH();
         }
         // A22 -= [V W] [W V]^H   (lower tiles)
-        const bool ahead = (k + b) + b + 1 < n && mr > nb;
+        const bool ahead = lookahead() && (k + b) + b + 1 < n && mr > nb;
         if (ahead) {
             // the next panel's columns first (all rows), then that panel's QR
             // on the side stream, then the rest of A22
