@@ -6,14 +6,15 @@
 namespace bdg {
 namespace {
 
-constexpr int BM = 64;
-constexpr int BN = 64;
 constexpr int NT = 256;
 
-template <typename T, bool CPLX>
+// WB: 16x16 MFMA blocks per wave along M and along N; the workgroup's four
+// waves form a 2 x 2 grid, so a tile of C is 32 WB x 32 WB.
+template <typename T, bool CPLX, int WB = 2>
 struct Cfg {
     static constexpr int EW = CPLX ? 2 : 1;       // scalars per element
-    static constexpr int BK = CPLX ? 16 : 32;     // k-depth of one LDS tile
+    static constexpr int BM = 32 * WB;            // tile rows (and columns)
+    static constexpr int BK = (CPLX || WB > 2) ? 16 : 32;  // k-depth of one LDS tile
     static constexpr int LDS_LD = BM + 1;         // elements per k-row in LDS
     static constexpr int TILE_ELEMS = BK * BM;    // elements of one operand tile
     static constexpr int PER_THREAD = TILE_ELEMS / NT;
@@ -24,12 +25,12 @@ struct Cfg {
 //   KFAST = true : element (i, k) at P[(k0 + k) + (r0 + i) * ld]  (contiguous in k)
 // Out-of-range elements are zero.  HEMM_DIAG: lower-Hermitian select for the
 // diagonal tile (i-fast layout only).
-template <typename T, bool CPLX, bool KFAST, bool CONJ>
+template <typename T, bool CPLX, int WB, bool KFAST, bool CONJ>
 __device__ inline void load_tile(const T *__restrict__ P, int64_t ld, int64_t r0, int64_t k0,
-                                 int64_t MN, int64_t K, typename v2t<T>::type (&v)[Cfg<T, CPLX>::PER_THREAD],
+                                 int64_t MN, int64_t K, typename v2t<T>::type (&v)[Cfg<T, CPLX, WB>::PER_THREAD],
                                  unsigned &okm, unsigned &cjm, bool hemm_diag,
                                  const int *__restrict__ kmap = nullptr) {
-    typedef Cfg<T, CPLX> C;
+    typedef Cfg<T, CPLX, WB> C;
     constexpr int PT = C::PER_THREAD;
     const int t = threadIdx.x;
     // all loads of the tile are issued before any is used: unconditional (from
@@ -44,8 +45,8 @@ __device__ inline void load_tile(const T *__restrict__ P, int64_t ld, int64_t r0
             k = t % C::BK;
             i = t / C::BK + (NT / C::BK) * j;
         } else {
-            i = t % BM;
-            k = t / BM + (NT / BM) * j;
+            i = t % C::BM;
+            k = t / C::BM + (NT / C::BM) * j;
         }
         gi[j] = r0 + i;
         gk[j] = k0 + k;
@@ -88,10 +89,10 @@ __device__ inline void load_tile(const T *__restrict__ P, int64_t ld, int64_t r0
     }
 }
 
-template <typename T, bool CPLX, bool KFAST>
-__device__ inline void store_tile(T *__restrict__ S, const typename v2t<T>::type (&v)[Cfg<T, CPLX>::PER_THREAD],
+template <typename T, bool CPLX, int WB, bool KFAST>
+__device__ inline void store_tile(T *__restrict__ S, const typename v2t<T>::type (&v)[Cfg<T, CPLX, WB>::PER_THREAD],
                                   unsigned okm, unsigned cjm) {
-    typedef Cfg<T, CPLX> C;
+    typedef Cfg<T, CPLX, WB> C;
     const int t = threadIdx.x;
     T reg[C::PER_THREAD][2];
 #pragma unroll
@@ -107,8 +108,8 @@ __device__ inline void store_tile(T *__restrict__ S, const typename v2t<T>::type
             k = t % C::BK;
             i = t / C::BK + (NT / C::BK) * j;
         } else {
-            i = t % BM;
-            k = t / BM + (NT / BM) * j;
+            i = t % C::BM;
+            k = t / C::BM + (NT / C::BM) * j;
         }
         const int idx = k * C::LDS_LD + i;
         if (CPLX) {
@@ -121,11 +122,13 @@ __device__ inline void store_tile(T *__restrict__ S, const typename v2t<T>::type
 }
 
 // opA: false = 'N', true = 'C'.  opB likewise.
-template <typename T, bool CPLX, bool CA, bool CB, int MODE>
+template <typename T, bool CPLX, bool CA, bool CB, int MODE, int WB>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk) {
-    typedef Cfg<T, CPLX> C;
+    typedef Cfg<T, CPLX, WB> C;
     typedef typename acc4<T>::type A4;
     constexpr int EW = C::EW;
+    constexpr int BM = C::BM, BN = C::BM, WT = 16 * WB;  // tile, and each wave's share of it
+    static_assert(WB == 2 || (WB == 4 && !CPLX && MODE == GEMM_FULL), "large tiles: real, full mode");
     __shared__ T As[2][C::BK * C::LDS_LD * EW];
     __shared__ T Bs[2][C::BK * C::LDS_LD * EW];
 
@@ -155,15 +158,20 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
     // complex: three real products per complex one (Gauss' form),
     // P1 = sum ar br, P2 = sum ai bi, P3 = sum (ar + ai)(br + bi);
     // Re = P1 - P2, Im = P3 - P1 - P2 (formed after the k loop).  Real: P1 only.
-    A4 accR[2][2], accI[2][2], acc3[2][2];
+    A4 accR[WB][WB], accI[CPLX ? WB : 1][CPLX ? WB : 1], acc3[CPLX ? WB : 1][CPLX ? WB : 1];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < WB; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            accR[a][b] = A4{0, 0, 0, 0};
-            accI[a][b] = A4{0, 0, 0, 0};
-            acc3[a][b] = A4{0, 0, 0, 0};
-        }
+        for (int b = 0; b < WB; ++b) accR[a][b] = A4{0, 0, 0, 0};
+    if (CPLX) {
+#pragma unroll
+        for (int a = 0; a < (CPLX ? WB : 1); ++a)
+#pragma unroll
+            for (int b = 0; b < (CPLX ? WB : 1); ++b) {
+                accI[a][b] = A4{0, 0, 0, 0};
+                acc3[a][b] = A4{0, 0, 0, 0};
+            }
+    }
 
     typename v2t<T>::type ra[C::PER_THREAD], rb[C::PER_THREAD];
     unsigned aok = 0, acj = 0, bok = 0, bcj = 0;
@@ -173,33 +181,33 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
         if (MODE == GEMM_HEMM_L) {
             // block column of A holding k0 (tiles aligned to BM)
             if (k0 + C::BK <= m0) {
-                load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false);
+                load_tile<T, CPLX, WB, false, false>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false);
             } else if (k0 >= m0 + BM) {
-                load_tile<T, CPLX, true, true>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false);
+                load_tile<T, CPLX, WB, true, true>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false);
             } else {
-                load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, true);
+                load_tile<T, CPLX, WB, false, false>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, true);
             }
         } else if (CA) {
-            load_tile<T, CPLX, true, true>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false);
+            load_tile<T, CPLX, WB, true, true>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false);
         } else {
-            load_tile<T, CPLX, false, false>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false, g.acol);
+            load_tile<T, CPLX, WB, false, false>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, false, g.acol);
         }
     };
     auto storeA = [&](int buf, int64_t k0) {
         bool kf;
         if (MODE == GEMM_HEMM_L) kf = (k0 >= m0 + BM);
         else kf = CA;
-        if (kf) store_tile<T, CPLX, true>(As[buf], ra, aok, acj);
-        else store_tile<T, CPLX, false>(As[buf], ra, aok, acj);
+        if (kf) store_tile<T, CPLX, WB, true>(As[buf], ra, aok, acj);
+        else store_tile<T, CPLX, WB, false>(As[buf], ra, aok, acj);
     };
     // B operand: 'N' -> k-fast (B stored K x N), 'C' -> i-fast (B stored N x K).
     auto loadB = [&](int64_t k0) {
-        if (CB) load_tile<T, CPLX, false, true>(B, g.ldb, n0, k0, g.N, kend, rb, bok, bcj, false);
-        else load_tile<T, CPLX, true, false>(B, g.ldb, n0, k0, g.N, kend, rb, bok, bcj, false, g.brow);
+        if (CB) load_tile<T, CPLX, WB, false, true>(B, g.ldb, n0, k0, g.N, kend, rb, bok, bcj, false);
+        else load_tile<T, CPLX, WB, true, false>(B, g.ldb, n0, k0, g.N, kend, rb, bok, bcj, false, g.brow);
     };
     auto storeB = [&](int buf) {
-        if (CB) store_tile<T, CPLX, false>(Bs[buf], rb, bok, bcj);
-        else store_tile<T, CPLX, true>(Bs[buf], rb, bok, bcj);
+        if (CB) store_tile<T, CPLX, WB, false>(Bs[buf], rb, bok, bcj);
+        else store_tile<T, CPLX, WB, true>(Bs[buf], rb, bok, bcj);
     };
 
     if (kbeg < kend) {
@@ -221,10 +229,10 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
 #pragma unroll
             for (int kk = 0; kk < C::BK; kk += 4) {
                 const int kr = kk + (lane >> 4);
-                T are[2], aim[2], bre[2], bim[2];
+                T are[WB], aim[WB], bre[WB], bim[WB];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    const int idx = kr * C::LDS_LD + wm * 32 + a * 16 + (lane & 15);
+                for (int a = 0; a < WB; ++a) {
+                    const int idx = kr * C::LDS_LD + wm * WT + a * 16 + (lane & 15);
                     if (CPLX) {
                         are[a] = as[2 * idx];
                         aim[a] = as[2 * idx + 1];
@@ -234,8 +242,8 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
                     }
                 }
 #pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    const int idx = kr * C::LDS_LD + wn * 32 + b * 16 + (lane & 15);
+                for (int b = 0; b < WB; ++b) {
+                    const int idx = kr * C::LDS_LD + wn * WT + b * 16 + (lane & 15);
                     if (CPLX) {
                         bre[b] = bs[2 * idx];
                         bim[b] = bs[2 * idx + 1];
@@ -245,23 +253,23 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
                     }
                 }
 #pragma unroll
-                for (int a = 0; a < 2; ++a)
+                for (int a = 0; a < WB; ++a)
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) accR[a][b] = mfma16(are[a], bre[b], accR[a][b]);
+                    for (int b = 0; b < WB; ++b) accR[a][b] = mfma16(are[a], bre[b], accR[a][b]);
                 if (CPLX) {
-                    T as2[2], bs2[2];
+                    T as2[WB], bs2[WB];
 #pragma unroll
-                    for (int a = 0; a < 2; ++a) as2[a] = are[a] + aim[a];
+                    for (int a = 0; a < WB; ++a) as2[a] = are[a] + aim[a];
 #pragma unroll
-                    for (int b = 0; b < 2; ++b) bs2[b] = bre[b] + bim[b];
+                    for (int b = 0; b < WB; ++b) bs2[b] = bre[b] + bim[b];
 #pragma unroll
-                    for (int a = 0; a < 2; ++a)
+                    for (int a = 0; a < (CPLX ? WB : 1); ++a)
 #pragma unroll
-                        for (int b = 0; b < 2; ++b) accI[a][b] = mfma16(aim[a], bim[b], accI[a][b]);
+                        for (int b = 0; b < (CPLX ? WB : 1); ++b) accI[a][b] = mfma16(aim[a], bim[b], accI[a][b]);
 #pragma unroll
-                    for (int a = 0; a < 2; ++a)
+                    for (int a = 0; a < (CPLX ? WB : 1); ++a)
 #pragma unroll
-                        for (int b = 0; b < 2; ++b) acc3[a][b] = mfma16(as2[a], bs2[b], acc3[a][b]);
+                        for (int b = 0; b < (CPLX ? WB : 1); ++b) acc3[a][b] = mfma16(as2[a], bs2[b], acc3[a][b]);
                 }
             }
             if (more) {
@@ -275,63 +283,59 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
 
     if (CPLX) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < (CPLX ? WB : 1); ++a)
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
+            for (int b = 0; b < (CPLX ? WB : 1); ++b) {
                 const A4 p1 = accR[a][b], p2 = accI[a][b];
                 accR[a][b] = p1 - p2;
                 accI[a][b] = acc3[a][b] - p1 - p2;
             }
     }
-    // epilogue: the 16 entries of C this thread owns are read (when beta != 0)
-    // in one batch before any of them is written
+    // epilogue, one row of blocks at a time: its 4 WB entries of C are read
+    // (when beta != 0) in one batch before any of them is written
     const bool to_part = g.splitk > 1;
     T *__restrict__ P = (T *)g.part;
     const T ar = (T)g.alpha_re, ai = (T)g.alpha_im, br = (T)g.beta_re, bi = (T)g.beta_im;
     const bool beta0 = (br == (T)0 && bi == (T)0);
-    int64_t coff[2][2][4];
-    bool cok[2][2][4];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < WB; ++a) {
+        int64_t coff[WB][4];
+        bool cok[WB][4];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int64_t col = n0 + wn * 32 + b * 16 + (lane & 15);
+        for (int b = 0; b < WB; ++b) {
+            const int64_t col = n0 + wn * WT + b * 16 + (lane & 15);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t row = m0 + wm * 32 + a * 16 + mfma_row((T)0, lane, q);
+                const int64_t row = m0 + wm * WT + a * 16 + mfma_row((T)0, lane, q);
                 const bool ok = (row < g.M) & (col < g.N);
-                cok[a][b][q] = ok;
-                if (to_part) coff[a][b][q] = (int64_t)blockIdx.z * g.M * g.N + row + col * g.M;
-                else coff[a][b][q] = ok ? row + (g.ccol ? (int64_t)g.ccol[col] : col) * g.ldc : 0;
+                cok[b][q] = ok;
+                if (to_part) coff[b][q] = (int64_t)blockIdx.z * g.M * g.N + row + col * g.M;
+                else coff[b][q] = ok ? row + (g.ccol ? (int64_t)g.ccol[col] : col) * g.ldc : 0;
             }
         }
-    T oldr[2][2][4], oldi[2][2][4];
-    if (!to_part && !beta0) {
+        T oldr[WB][4], oldi[WB][4];
+        if (!to_part && !beta0) {
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
+            for (int b = 0; b < WB; ++b)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (CPLX) {
-                        const typename v2t<T>::type v = *(const typename v2t<T>::type *)(Cm + 2 * coff[a][b][q]);
-                        oldr[a][b][q] = v.x;
-                        oldi[a][b][q] = v.y;
+                        const typename v2t<T>::type v = ld2<T>(Cm + 2 * coff[b][q]);
+                        oldr[b][q] = v.x;
+                        oldi[b][q] = v.y;
                     } else {
-                        oldr[a][b][q] = Cm[coff[a][b][q]];
-                        oldi[a][b][q] = 0;
+                        oldr[b][q] = Cm[coff[b][q]];
+                        oldi[b][q] = 0;
                     }
                 }
-    }
+        }
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < WB; ++b) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                if (!cok[a][b][q]) continue;
-                const T vr = accR[a][b][q], vi = CPLX ? accI[a][b][q] : (T)0;
-                const int64_t off = coff[a][b][q];
+                if (!cok[b][q]) continue;
+                const T vr = accR[a][b][q], vi = CPLX ? accI[CPLX ? a : 0][CPLX ? b : 0][q] : (T)0;
+                const int64_t off = coff[b][q];
                 if (to_part) {
                     if (CPLX) {
                         P[2 * off] = vr;
@@ -344,18 +348,19 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
                 if (CPLX) {
                     T cr = ar * vr - ai * vi, ci = ar * vi + ai * vr;
                     if (!beta0) {
-                        const T orr = oldr[a][b][q], oi = oldi[a][b][q];
+                        const T orr = oldr[b][q], oi = oldi[b][q];
                         cr += br * orr - bi * oi;
                         ci += br * oi + bi * orr;
                     }
-                    *(typename v2t<T>::type *)(Cm + 2 * off) = mk2<T>(cr, ci);
+                    st2<T>(Cm + 2 * off, mk2<T>(cr, ci));
                 } else {
                     T cr = ar * vr;
-                    if (!beta0) cr += br * oldr[a][b][q];
+                    if (!beta0) cr += br * oldr[b][q];
                     Cm[off] = cr;
                 }
             }
         }
+    }
 }
 
 template <typename T, bool CPLX>
@@ -396,10 +401,10 @@ __global__ void splitk_reduce(GemmArgs g) {
     }
 }
 
-template <typename T, bool CPLX, bool CA, bool CB, int MODE>
+template <typename T, bool CPLX, bool CA, bool CB, int MODE, int WB = 2>
 int launch(const GemmArgs &g, hipStream_t s) {
-    typedef Cfg<T, CPLX> C;
-    const int64_t tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+    typedef Cfg<T, CPLX, WB> C;
+    const int64_t tm = (g.M + C::BM - 1) / C::BM, tn = (g.N + C::BM - 1) / C::BM;
     int splitk = g.splitk > 1 ? g.splitk : 1;
     int64_t kchunk = g.K;
     if (splitk > 1) {
@@ -417,7 +422,7 @@ int launch(const GemmArgs &g, hipStream_t s) {
         grid = dim3((unsigned)tm, (unsigned)tn, splitk);
     }
     if (tm <= 0 || tn <= 0) return 0;
-    hipLaunchKernelGGL((gemm_kernel<T, CPLX, CA, CB, MODE>), grid, dim3(NT), 0, s, h, kchunk);
+    hipLaunchKernelGGL((gemm_kernel<T, CPLX, CA, CB, MODE, WB>), grid, dim3(NT), 0, s, h, kchunk);
     BDG_CHECK_LAUNCH();
     if (splitk > 1) {
         const int64_t total = g.M * g.N;
@@ -446,12 +451,19 @@ int gemm(char opA, char opB, const GemmArgs &g, hipStream_t s) {
         set_error("gemm: lower mode supports opA='N' only");
         return BDG_ERR_NOT_IMPLEMENTED;
     }
+    // real products with room for them: 128 x 128 tiles (twice the reuse of
+    // every operand element loaded)
+    const bool big = !CPLX && g.M >= 256 && g.N >= 256;
     if (ca) {
-        if (cb) return launch<T, CPLX, true, true, GEMM_FULL>(g, s);
-        return launch<T, CPLX, true, false, GEMM_FULL>(g, s);
+        if (cb) return big ? launch<T, CPLX, true, true, GEMM_FULL, CPLX ? 2 : 4>(g, s)
+                           : launch<T, CPLX, true, true, GEMM_FULL>(g, s);
+        return big ? launch<T, CPLX, true, false, GEMM_FULL, CPLX ? 2 : 4>(g, s)
+                   : launch<T, CPLX, true, false, GEMM_FULL>(g, s);
     }
-    if (cb) return launch<T, CPLX, false, true, GEMM_FULL>(g, s);
-    return launch<T, CPLX, false, false, GEMM_FULL>(g, s);
+    if (cb) return big ? launch<T, CPLX, false, true, GEMM_FULL, CPLX ? 2 : 4>(g, s)
+                       : launch<T, CPLX, false, true, GEMM_FULL>(g, s);
+    return big ? launch<T, CPLX, false, false, GEMM_FULL, CPLX ? 2 : 4>(g, s)
+               : launch<T, CPLX, false, false, GEMM_FULL>(g, s);
 }
 
 template int gemm<double, true>(char, char, const GemmArgs &, hipStream_t);

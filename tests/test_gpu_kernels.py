@@ -54,7 +54,8 @@ def test_assemble_metric_size_sampled(dev):
     torch.cuda.empty_cache()
 
 
-SHAPES = [(1, 1, 1), (37, 65, 19), (130, 70, 257), (64, 64, 64), (200, 17, 100)]
+SHAPES = [(1, 1, 1), (37, 65, 19), (130, 70, 257), (64, 64, 64), (200, 17, 100),
+          (300, 290, 70), (513, 256, 33)]  # the last two take the 128 x 128 tiles (real)
 
 
 def _op(M, op):
