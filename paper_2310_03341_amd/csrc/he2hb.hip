@@ -540,7 +540,7 @@ namespace bdg {
 // b rows per panel, zeros above), T from the recurrence
 // T = [[T_a, -T_a (V_a^H V_c) T_c], [0, T_c]], so the three products per
 // group have inner dimension g b instead of b.
-constexpr int BT1_GROUP = 4;
+constexpr int BT1_GROUP = 8;
 
 template <typename F>
 __global__ void bt1_gather_v(const F *__restrict__ A, int64_t lda, int64_t k0, int b, int64_t R,
