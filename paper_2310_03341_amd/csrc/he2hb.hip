@@ -55,15 +55,27 @@ template <typename F>
 __device__ inline void reduce_partials(const F *__restrict__ part, int G, int nb,
                                        F *__restrict__ s_sh /* 2*(nb+1) */) {
     // 4 threads per column (256 threads)
+    typedef typename v2t<F>::type CV;
     __shared__ F tmp[4][2 * (MAXB + 1)];
     const int t = threadIdx.x;
     for (int col = t & 63; col <= nb; col += 64) {
         const int g0 = t >> 6;
         F re = 0.0, im = 0.0;
-        for (int g = g0; g < G; g += 4) {
-            const F *p = part + (size_t)g * 2 * (nb + 1) + 2 * col;
-            re += p[0];
-            im += p[1];
+        // eight loads in flight per round (entry of workgroup 0 past the end,
+        // dropped by the select), so the sum does not wait on each in turn
+        for (int gb = g0; gb < G; gb += 32) {
+            CV v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int g = gb + 4 * u;
+                v[u] = ld2<F>(part + (size_t)(g < G ? g : 0) * 2 * (nb + 1) + 2 * col);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (gb + 4 * u < G) {
+                    re += v[u].x;
+                    im += v[u].y;
+                }
         }
         tmp[g0][2 * col] = re;
         tmp[g0][2 * col + 1] = im;
@@ -227,12 +239,10 @@ __global__ __launch_bounds__(256) void panel_step(F *__restrict__ P, int64_t ld,
             part_out[(size_t)blockIdx.x * 2 * (nb + 1) + 2 * c] = sr;
             part_out[(size_t)blockIdx.x * 2 * (nb + 1) + 2 * c + 1] = si;
         }
-        if (have && r == jn) {
-            for (int c = 0; c < nb; ++c) {
-                row_out[2 * c] = P[2 * (r + (int64_t)c * ld)];
-                row_out[2 * c + 1] = P[2 * (r + (int64_t)c * ld) + 1];
-            }
-        }
+        // the pivot row jn, copied by the workgroup that owns it (one thread per column)
+        const int64_t rb = (int64_t)blockIdx.x * PQ_ROWS;
+        if (jn >= rb && jn < rb + PQ_ROWS && t < nb)
+            st2<F>(row_out + 2 * t, ld2<F>(P + 2 * (jn + (int64_t)t * ld)));
     }
 }
 
