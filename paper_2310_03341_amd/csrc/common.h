@@ -100,6 +100,32 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
+// Wave sum through DPP lane moves (no LDS round trips); the total is valid
+// in lane 63 only.  Pairs, quads, half rows, rows (mirrors), then the row
+// broadcasts 15 and 31 fold rows 0 + 1 into 1, 2 + 3 into 3, and 1 into 3.
+template <int CTRL, int ROWMASK>
+__device__ inline double dpp_fold(double v) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, ROWMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, ROWMASK, 0xf, false);
+    return v + __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL, int ROWMASK>
+__device__ inline float dpp_fold(float v) {
+    const int t = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xf, false);
+    return v + __int_as_float(t);
+}
+template <typename T>
+__device__ inline T wave_sum_last(T v) {
+    v = dpp_fold<0xB1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_fold<0x4E, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_fold<0x141, 0xf>(v);  // row_half_mirror
+    v = dpp_fold<0x140, 0xf>(v);  // row_mirror
+    v = dpp_fold<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+    v = dpp_fold<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+    return v;
+}
+
 // Block-level sum over blockDim.x threads (multiple of 64), result to all.
 template <typename T>
 __device__ inline T block_sum(T v, T* red /* >= blockDim.x/64 */) {

@@ -169,6 +169,18 @@ __global__ void neg_reverse(int64_t half, const double *__restrict__ W, double *
     }
 }
 
+// Z[:, j] = X[:, perm[j]] (complex, n rows)
+__global__ void gather_columns(int64_t n, const double *__restrict__ X, int64_t ldx,
+                               const int64_t *__restrict__ perm, double *__restrict__ Z, int64_t ldz) {
+    const int64_t j = blockIdx.x;
+    const double *src = X + 2 * perm[j] * ldx;
+    double *dst = Z + 2 * j * ldz;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        dst[2 * i] = src[2 * i];
+        dst[2 * i + 1] = src[2 * i + 1];
+    }
+}
+
 // W[k] = -W[src0 - k] for k < count
 __global__ void neg_reverse_w(int64_t count, double *__restrict__ W, int64_t src0) {
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
@@ -290,8 +302,34 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
     } else if (mr > 0) {  // refinement switched off: the FP32 result, widened
         BDG_HIP(hipMemcpyAsync(W + (r0 - i0), lam + r0, 8 * (size_t)mr, hipMemcpyDeviceToDevice, s));
     }
-    if (mr > 0) BDG_HIP(hipMemcpy2DAsync(Z + 2 * (r0 - i0) * ldz, 16 * (size_t)ldz, X64 + 2 * r0 * n,
-                                         16 * (size_t)n, 16 * (size_t)n, (size_t)mr, hipMemcpyDeviceToDevice, s));
+    // Refined pairs come back in column order.  A pair closer than the
+    // FP32 basis could separate, refined column by column, can converge with
+    // its two columns swapped; the window is then put in ascending order.
+    bool sorted = true;
+    std::vector<int64_t> perm;
+    if (iters > 0 && mr > 1) {
+        std::vector<double> wr((size_t)mr);
+        BDG_HIP(hipMemcpyAsync(wr.data(), W + (r0 - i0), 8 * (size_t)mr, hipMemcpyDeviceToHost, s));
+        BDG_HIP(hipStreamSynchronize(s));
+        for (int64_t j = 1; j < mr; ++j) sorted = sorted && !(wr[j] < wr[j - 1]);
+        if (!sorted) {
+            perm.resize((size_t)mr);
+            for (int64_t j = 0; j < mr; ++j) perm[j] = j;
+            std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return wr[a] < wr[b]; });
+            std::vector<double> ws((size_t)mr);
+            for (int64_t j = 0; j < mr; ++j) ws[j] = wr[perm[j]];
+            int64_t *pd = (int64_t *)rscratch;
+            BDG_HIP(hipMemcpyAsync(pd, perm.data(), 8 * (size_t)mr, hipMemcpyHostToDevice, s));
+            BDG_HIP(hipMemcpyAsync(W + (r0 - i0), ws.data(), 8 * (size_t)mr, hipMemcpyHostToDevice, s));
+            hipLaunchKernelGGL(gather_columns, dim3((unsigned)mr), dim3(256), 0, s, n, X64 + 2 * r0 * n, n, pd,
+                               Z + 2 * (r0 - i0) * ldz, ldz);
+            BDG_CHECK_LAUNCH();
+            BDG_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+        }
+    }
+    if (mr > 0 && sorted)
+        BDG_HIP(hipMemcpy2DAsync(Z + 2 * (r0 - i0) * ldz, 16 * (size_t)ldz, X64 + 2 * r0 * n, 16 * (size_t)n,
+                                 16 * (size_t)n, (size_t)mr, hipMemcpyDeviceToDevice, s));
     if (mir) {
         BDG_TRY(mirror_columns(n, Z, ldz, 0, (n - 1 - i0) - i0, h - i0, s));
         hipLaunchKernelGGL(neg_reverse_w, dim3(64), dim3(256), 0, s, h - i0, W, (n - 1 - i0) - i0);

@@ -209,8 +209,8 @@ __global__ __launch_bounds__(256) void panel_step(F *__restrict__ P, int64_t ld,
         const int w = t >> 6, l = t & 63;
         // tail2 over r > jn
         F t2 = (in && r > jn) ? xr * xr + xi * xi : 0.0;
-        t2 = wave_sum(t2);
-        if (l == 0) { red[w][2 * nb] = t2; red[w][2 * nb + 1] = 0.0; }
+        t2 = wave_sum_last(t2);
+        if (l == 63) { red[w][2 * nb] = t2; red[w][2 * nb + 1] = 0.0; }
         for (int c0 = jn + 1; c0 < nb; c0 += 16) {
             CV pv[16];
 #pragma unroll
@@ -225,9 +225,9 @@ __global__ __launch_bounds__(256) void panel_step(F *__restrict__ P, int64_t ld,
                 if (c >= nb) break;
                 // conj(x) * p
                 F sr = xr * pv[q].x + xi * pv[q].y, si = xr * pv[q].y - xi * pv[q].x;
-                sr = wave_sum(sr);
-                si = wave_sum(si);
-                if (l == 0) { red[w][2 * c] = sr; red[w][2 * c + 1] = si; }
+                sr = wave_sum_last(sr);
+                si = wave_sum_last(si);
+                if (l == 63) { red[w][2 * c] = sr; red[w][2 * c + 1] = si; }
             }
         }
         __syncthreads();
