@@ -126,6 +126,14 @@ __device__ inline T wave_sum_last(T v) {
     return v;
 }
 
+// Sum over each group of 4 consecutive lanes, to all 4 (DPP quad permutes).
+template <typename T>
+__device__ inline T quad_sum(T v) {
+    v = dpp_fold<0xB1, 0xf>(v);  // quad_perm [1, 0, 3, 2]
+    v = dpp_fold<0x4E, 0xf>(v);  // quad_perm [2, 3, 0, 1]
+    return v;
+}
+
 // Block-level sum over blockDim.x threads (multiple of 64), result to all.
 template <typename T>
 __device__ inline T block_sum(T v, T* red /* >= blockDim.x/64 */) {

@@ -127,8 +127,8 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
                 si += a.x * v.y + a.y * v.x;
             }
         }
-        sr += __shfl_xor(sr, 1, 64); si += __shfl_xor(si, 1, 64);
-        sr += __shfl_xor(sr, 2, 64); si += __shfl_xor(si, 2, 64);
+        sr = quad_sum(sr);
+        si = quad_sum(si);
         F n2 = 0.0;
         if (qr < BT) {
             yr = mk2<F>(tp * sr, tp * si);
@@ -140,12 +140,12 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
             }
             if (q == 0 && qr > 0) n2 = xr.x * xr.x + xr.y * xr.y;
         }
-        n2 = wave_sum(n2);
+        n2 = wave_sum_last(n2);
         if (qr < BT && q == 0) {
             yv[qr] = yr;
             if (t > 0) xv[qr] = xr;  // for t = 0, xv already holds x (read above)
         }
-        if (l == 0) red[w][0] = n2;
+        if (l == 63) red[w][0] = n2;
     }
     __syncthreads();
 
@@ -221,10 +221,10 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
                 }
             }
         }
-        pr += __shfl_xor(pr, 1, 64); pi += __shfl_xor(pi, 1, 64);
-        pr += __shfl_xor(pr, 2, 64); pi += __shfl_xor(pi, 2, 64);
-        wr += __shfl_xor(wr, 1, 64); wi += __shfl_xor(wi, 1, 64);
-        wr += __shfl_xor(wr, 2, 64); wi += __shfl_xor(wi, 2, 64);
+        pr = quad_sum(pr);
+        pi = quad_sum(pi);
+        wr = quad_sum(wr);
+        wi = quad_sum(wi);
         F kr = 0.0, ki = 0.0, gr = 0.0, gi = 0.0;
         if (qr < BT && q == 0) {
             const CV p = mk2<F>(tj * pr, tj * pi);
@@ -236,8 +236,11 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
             gr = v.x * yr.x + v.y * yr.y;
             gi = v.x * yr.y - v.y * yr.x;
         }
-        kr = wave_sum(kr); ki = wave_sum(ki); gr = wave_sum(gr); gi = wave_sum(gi);
-        if (l == 0) { red[w][0] = kr; red[w][1] = ki; red[w][2] = gr; red[w][3] = gi; }
+        kr = wave_sum_last(kr);
+        ki = wave_sum_last(ki);
+        gr = wave_sum_last(gr);
+        gi = wave_sum_last(gi);
+        if (l == 63) { red[w][0] = kr; red[w][1] = ki; red[w][2] = gr; red[w][3] = gi; }
     }
     __syncthreads();
 
