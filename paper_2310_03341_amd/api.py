@@ -286,14 +286,19 @@ def stage_stedc(d: torch.Tensor, e: torch.Tensor, leaf: int = 0):
     return W, Q
 
 
-def stage_bt2(e_cplx, Y, i0, m, V2, tau2, voff, band: int = 64):
+def stage_bt2(e_cplx, Y, i0, m, V2, tau2, voff, band: int = 64, rowmajor: bool = True):
+    """rowmajor=False passes a workspace without room for the row-major copy
+    of Z, which makes the library take its column-major route."""
     L = lib()
     _stage_sigs(L)
     n = Y.shape[0]
     Z = colmajor(n, max(m, 1), torch.complex128, Y.device)
     work = stage_workspace(4, n, band, m, Y.device)
+    nbytes = work.numel()
+    if not rowmajor and band % 16 == 0:
+        nbytes -= 16 * n * max(m, 0)
     _call("bdg_stage_bt2", n, band, m, _dev(e_cplx), _dev(Y), i0, _dev(V2), _dev(tau2), _dev(voff),
-          _dev(Z), _ld(Z), _dev(work), work.numel(), _stream(Y.device))
+          _dev(Z), _ld(Z), _dev(work), nbytes, _stream(Y.device))
     return Z[:, :m]
 
 

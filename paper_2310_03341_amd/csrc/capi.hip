@@ -222,9 +222,13 @@ int bdg_stage_stedc(int64_t n, const double *d, const double *e, double *W, doub
 int bdg_stage_bt2(int64_t n, int band, int64_t m, const double *e, const double *Y, int64_t i0,
                   const double *V2, const double *tau2, const int64_t *voff, double *Z,
                   int64_t ldz, void *work, size_t work_bytes, bdg_stream_t stream) {
+    // workspace of stage 4: with the row-major copy of Z when the band allows
+    // it; a workspace without room for that copy takes the column-major route
     size_t need = 0;
     bdg_stage_workspace(4, n, band, m, &need);
-    if (work_bytes < need) return BDG_ERR_WORKSPACE;
+    const size_t zrm = bdg::bt2_rowmajor_ok(band) ? 16 * (size_t)n * (size_t)(m > 0 ? m : 0) : 0;
+    if (work_bytes < need - zrm) return BDG_ERR_WORKSPACE;
+    const bool rm = zrm > 0 && work_bytes >= need;
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)work;
     auto al = [](size_t x) { return (x + 255) / 256 * 256; };
@@ -232,7 +236,7 @@ int bdg_stage_bt2(int64_t n, int band, int64_t m, const double *e, const double 
     double *ea = (double *)(w + al(16 * (size_t)n));
     void *rest = w + al(16 * (size_t)n) + al(8 * (size_t)n);
     BDG_TRY(bdg::phases(n, e, ph, ea, s));
-    if (!bdg::bt2_rowmajor_ok(band) || n < 3 || m <= 0) {
+    if (!rm || n < 3 || m <= 0) {
         BDG_TRY(bdg::phase_scale(n, m, Y, i0, ph, Z, ldz, s));
         return bdg::bt2(n, band, m, V2, tau2, voff, Z, ldz, rest, s);
     }

@@ -138,9 +138,16 @@ def test_hb2st_and_bt2(dev, n, band):
     # eigenvectors of B via GPU D&C + BT2
     ea = torch.from_numpy(np.abs(eh).copy()).to(dev)
     W, Y = api.stage_stedc(d, ea)
-    Z = api.stage_bt2(e, Y, 0, n, V2, tau2, voff, band)
-    torch.cuda.synchronize()
-    Wh, Zh = W.cpu().numpy(), Z.cpu().numpy()
+    Wh = W.cpu().numpy()
     assert np.abs(Wh - ref).max() < 1e-12 * width
-    assert np.abs(B @ Zh - Zh * Wh).max() < 1e-12 * np.abs(ref).max()
-    assert np.abs(Zh.conj().T @ Zh - np.eye(n)).max() < 1e-12
+    # both routes of the back-transformation 2 (row-major copy of Z, and in
+    # place on the column-major Z when the workspace has no room for the copy)
+    Zs = []
+    for rowmajor in (True, False):
+        Z = api.stage_bt2(e, Y, 0, n, V2, tau2, voff, band, rowmajor=rowmajor)
+        torch.cuda.synchronize()
+        Zh = Z.cpu().numpy()
+        assert np.abs(B @ Zh - Zh * Wh).max() < 1e-12 * np.abs(ref).max(), rowmajor
+        assert np.abs(Zh.conj().T @ Zh - np.eye(n)).max() < 1e-12, rowmajor
+        Zs.append(Zh)
+    assert np.abs(Zs[0] - Zs[1]).max() < 1e-12
