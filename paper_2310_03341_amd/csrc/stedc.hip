@@ -20,6 +20,7 @@
 #include "stages.h"
 
 #include <math.h>
+#include <mutex>
 #include <vector>
 
 namespace bdg {
@@ -157,8 +158,21 @@ struct MergeScratch {
     int *rtop;
     int *cbot;      // ... touching the bottom half
     int *rbot;
-    int *info;      // [0]=k [1]=ndef [2]=nrot [3]=error [4]=k_top [5]=k_bot
+    int *info;      // [0]=k [1]=ndef [2]=nrot [4]=k_top [5]=k_bot (one block per merge)
+    int *err;       // secular iteration did not converge (shared by all merges)
 };
+
+// The merges of one tree level cover disjoint column ranges [a, a + K): each
+// takes the slice of every K-sized array that starts at a, its own info block
+// and rho slot.
+MergeScratch slice(const MergeScratch &m, int64_t a, int *info) {
+    MergeScratch r = m;
+    r.z += a; r.Ds += a; r.sidx += a; r.nd += a; r.Dnd += a; r.znd += a; r.dfi += a; r.Ddf += a;
+    r.rotp += a; r.rotq += a; r.rotc += a; r.rots += a; r.orig += a; r.tau += a; r.zhat += a;
+    r.posnd += a; r.posdf += a; r.lamnd += a; r.ctop += a; r.rtop += a; r.cbot += a; r.rbot += a;
+    r.info = info;
+    return r;
+}
 
 // z, sorted order and deflation (one workgroup).  The rank merge, the gathers
 // and the final split of the kept columns by half run on all threads; the
@@ -410,7 +424,7 @@ __global__ __launch_bounds__(256) void merge_secular(const double *__restrict__ 
         tau = tn;
     }
     if (lane != 0) return;
-    if (!conv) atomicOr(&m.info[3], 1);
+    if (!conv) atomicOr(m.err, 1);
     m.orig[j] = o;
     m.tau[j] = tau;
     m.lamnd[j] = Do + tau;
@@ -500,6 +514,40 @@ __global__ void copy_deflated(int64_t K, const double *__restrict__ Qblk, int64_
 
 struct Node { int64_t a, m, c; };
 
+constexpr int MERGE_STREAMS = 4;
+
+// MERGE_STREAMS non-blocking streams per device (default priority), created
+// on first use and kept for the life of the process.
+hipStream_t *merge_streams() {
+    static std::mutex mu;
+    static hipStream_t st[64][MERGE_STREAMS];
+    static bool made[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!made[dev]) {
+        for (int q = 0; q < MERGE_STREAMS; ++q)
+            if (hipStreamCreateWithFlags(&st[dev][q], hipStreamNonBlocking) != hipSuccess) return nullptr;
+        made[dev] = true;
+    }
+    return st[dev];
+}
+
+struct StreamEvents {
+    hipEvent_t main = nullptr, side[MERGE_STREAMS] = {};
+    bool ok = false;
+    StreamEvents() {
+        ok = hipEventCreateWithFlags(&main, hipEventDisableTiming) == hipSuccess;
+        for (int q = 0; q < MERGE_STREAMS; ++q)
+            ok = ok && hipEventCreateWithFlags(&side[q], hipEventDisableTiming) == hipSuccess;
+    }
+    ~StreamEvents() {
+        if (main) (void)hipEventDestroy(main);
+        for (int q = 0; q < MERGE_STREAMS; ++q)
+            if (side[q]) (void)hipEventDestroy(side[q]);
+    }
+};
+
 }  // namespace
 
 size_t stedc_workspace(int64_t n) {
@@ -509,6 +557,7 @@ size_t stedc_workspace(int64_t n) {
     w += 8 * (size_t)n * 4;       // dt, lam a/b, spare
     w += (size_t)n * (8 * 12 + 4 * 20);  // merge scratch
     w += 8 * (size_t)n + 4096;    // splits, starts, rho, info
+    w += 48 * (size_t)n;          // per-merge info blocks and rho slots
     return w;
 }
 
@@ -553,8 +602,12 @@ int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *
     ms.rtop = (int *)take(4 * (size_t)n);
     ms.cbot = (int *)take(4 * (size_t)n);
     ms.rbot = (int *)take(4 * (size_t)n);
-    ms.info = (int *)take(64);
-    double *rho_d = (double *)take(64);
+    // per merge of a level (at most n / 2 merges): an info block of 8 ints
+    // and a rho slot; plus the shared error flag
+    int *info_all = (int *)take(32 * (size_t)n + 64);
+    double *rho_all = (double *)take(8 * (size_t)n + 64);
+    ms.err = (int *)take(64);
+    ms.info = info_all;
 
     // tree: split every node at its midpoint down to a common depth
     int depth = 0;
@@ -598,7 +651,7 @@ int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *
     Lbuf[(depth + 1) % 2] = lamB;
     BDG_HIP(hipMemsetAsync(Q_out, 0, 8 * (size_t)n * n, s));
     if (depth > 0) BDG_HIP(hipMemsetAsync(Qalt, 0, 8 * (size_t)n * n, s));
-    BDG_HIP(hipMemsetAsync(ms.info, 0, 64, s));
+    BDG_HIP(hipMemsetAsync(ms.err, 0, sizeof(int), s));
     hipLaunchKernelGGL(leaf_jacobi, dim3((unsigned)(nst - 1)), dim3(64), 0, s, dt, e, dstart, n, Qbuf[0],
                        Lbuf[0]);
     BDG_CHECK_LAUNCH();
@@ -607,63 +660,106 @@ int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *
         BDG_HIP(hipMemcpyAsync(eh.data(), e, 8 * (size_t)(n - 1), hipMemcpyDeviceToHost, s));
         BDG_HIP(hipStreamSynchronize(s));
     }
+    // The merges of one level are independent (disjoint columns of Q, scratch
+    // slices, U blocks): they run on MERGE_STREAMS streams in two phases,
+    // deflation for all of them, one copy of their sizes to the host, then
+    // the rest, so a level costs one host round trip instead of one per merge.
+    hipStream_t *mst = merge_streams();
+    if (!mst) {
+        set_error("stedc: could not create the merge streams");
+        return BDG_ERR_HIP;
+    }
+    StreamEvents evs;
+    if (!evs.ok) {
+        set_error("stedc: could not create events");
+        return BDG_ERR_HIP;
+    }
+    auto fork = [&]() -> int {
+        BDG_HIP(hipEventRecord(evs.main, s));
+        for (int q = 0; q < MERGE_STREAMS; ++q) BDG_HIP(hipStreamWaitEvent(mst[q], evs.main, 0));
+        return 0;
+    };
+    auto join = [&]() -> int {
+        for (int q = 0; q < MERGE_STREAMS; ++q) {
+            BDG_HIP(hipEventRecord(evs.side[q], mst[q]));
+            BDG_HIP(hipStreamWaitEvent(s, evs.side[q], 0));
+        }
+        return 0;
+    };
+    std::vector<int> infoh;
     for (int h = 1; h <= depth; ++h) {
         double *Qc = Qbuf[(h - 1) % 2], *Qn = Qbuf[h % 2];
         double *Lc = Lbuf[(h - 1) % 2], *Ln = Lbuf[h % 2];
-        for (const Node &nd : levels[h]) {
+        const std::vector<Node> &lv = levels[h];
+        const int nm = (int)lv.size();
+        BDG_TRY(fork());
+        for (int i = 0; i < nm; ++i) {
+            const Node &nd = lv[i];
             const int64_t K = nd.c - nd.a, n1 = nd.m - nd.a;
             const double ev = eh[nd.m - 1];
             const double rho = fabs(ev), sg = ev >= 0.0 ? 1.0 : -1.0;
+            const MergeScratch mi = slice(ms, nd.a, info_all + 8 * i);
+            hipLaunchKernelGGL(merge_deflate, dim3(1), dim3(1024), 0, mst[i % MERGE_STREAMS], K, n1, rho, sg,
+                               Qc + nd.a + nd.a * n, n, Lc + nd.a, mi, rho_all + i);
+            BDG_CHECK_LAUNCH();
+        }
+        BDG_TRY(join());
+        infoh.resize((size_t)8 * nm);
+        BDG_HIP(hipMemcpyAsync(infoh.data(), info_all, 32 * (size_t)nm, hipMemcpyDeviceToHost, s));
+        BDG_HIP(hipStreamSynchronize(s));
+        BDG_TRY(fork());
+        for (int i = 0; i < nm; ++i) {
+            const Node &nd = lv[i];
+            hipStream_t q = mst[i % MERGE_STREAMS];
+            const int64_t K = nd.c - nd.a, n1 = nd.m - nd.a;
+            const int *inf = infoh.data() + 8 * i;
+            const int k = inf[0], ndef = inf[1], nrot = inf[2], ktop = inf[4], kbot = inf[5];
+            const MergeScratch mi = slice(ms, nd.a, info_all + 8 * i);
+            double *rho_d = rho_all + i;
+            double *Ui = U + nd.a * n;  // k x k with ld k inside columns [a, a + K) of U
             double *Qblk = Qc + nd.a + nd.a * n;
             double *Qnb = Qn + nd.a + nd.a * n;
-            hipLaunchKernelGGL(merge_deflate, dim3(1), dim3(1024), 0, s, K, n1, rho, sg, Qblk, n,
-                               Lc + nd.a, ms, rho_d);
-            BDG_CHECK_LAUNCH();
-            int info[6];
-            BDG_HIP(hipMemcpyAsync(info, ms.info, sizeof(info), hipMemcpyDeviceToHost, s));
-            BDG_HIP(hipStreamSynchronize(s));
-            const int k = info[0], ndef = info[1], nrot = info[2], ktop = info[4], kbot = info[5];
             if (nrot > 0) {
-                hipLaunchKernelGGL(merge_rotate, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, K,
-                                   Qblk, n, ms);
+                hipLaunchKernelGGL(merge_rotate, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, q, K, Qblk, n, mi);
                 BDG_CHECK_LAUNCH();
             }
             if (k > 0) {
-                hipLaunchKernelGGL(merge_secular, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, s, rho_d, ms);
+                hipLaunchKernelGGL(merge_secular, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, q, rho_d, mi);
                 BDG_CHECK_LAUNCH();
-                hipLaunchKernelGGL(merge_zhat, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, s, rho_d, ms);
+                hipLaunchKernelGGL(merge_zhat, dim3((unsigned)((k + 3) / 4)), dim3(256), 0, q, rho_d, mi);
                 BDG_CHECK_LAUNCH();
-                hipLaunchKernelGGL(merge_vectors, dim3((unsigned)k), dim3(256), 0, s, ms, U);
+                hipLaunchKernelGGL(merge_vectors, dim3((unsigned)k), dim3(256), 0, q, mi, Ui);
                 BDG_CHECK_LAUNCH();
             }
-            hipLaunchKernelGGL(merge_place, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, s, K, Qblk, n,
-                               Qnb, Ln + nd.a, ms);
+            hipLaunchKernelGGL(merge_place, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, q, K, Qblk, n, Qnb,
+                               Ln + nd.a, mi);
             BDG_CHECK_LAUNCH();
             if (ndef > 0) {
-                hipLaunchKernelGGL(copy_deflated, dim3((unsigned)ndef), dim3(256), 0, s, K, Qblk, n, Qnb, ms);
+                hipLaunchKernelGGL(copy_deflated, dim3((unsigned)ndef), dim3(256), 0, q, K, Qblk, n, Qnb, mi);
                 BDG_CHECK_LAUNCH();
             }
             if (k > 0) {
                 // top rows use the columns nonzero there, bottom rows likewise
-                GemmArgs gt{n1, k, ktop, 1.0, 0.0, 0.0, 0.0, Qblk, n, U, k, Qnb, n, GEMM_FULL, 1, nullptr};
-                gt.acol = ms.ctop;
-                gt.brow = ms.rtop;
-                gt.ccol = ms.posnd;
-                BDG_TRY((gemm<double, false>('N', 'N', gt, s)));
-                GemmArgs gb{K - n1, k, kbot, 1.0, 0.0, 0.0, 0.0, Qblk + n1, n, U, k, Qnb + n1, n, GEMM_FULL, 1,
+                GemmArgs gt{n1, k, ktop, 1.0, 0.0, 0.0, 0.0, Qblk, n, Ui, k, Qnb, n, GEMM_FULL, 1, nullptr};
+                gt.acol = mi.ctop;
+                gt.brow = mi.rtop;
+                gt.ccol = mi.posnd;
+                BDG_TRY((gemm<double, false>('N', 'N', gt, q)));
+                GemmArgs gb{K - n1, k, kbot, 1.0, 0.0, 0.0, 0.0, Qblk + n1, n, Ui, k, Qnb + n1, n, GEMM_FULL, 1,
                             nullptr};
-                gb.acol = ms.cbot;
-                gb.brow = ms.rbot;
-                gb.ccol = ms.posnd;
-                BDG_TRY((gemm<double, false>('N', 'N', gb, s)));
+                gb.acol = mi.cbot;
+                gb.brow = mi.rbot;
+                gb.ccol = mi.posnd;
+                BDG_TRY((gemm<double, false>('N', 'N', gb, q)));
             }
         }
+        BDG_TRY(join());
     }
     BDG_HIP(hipMemcpyAsync(lam_out, Lbuf[depth % 2], 8 * (size_t)n, hipMemcpyDeviceToDevice, s));
-    int info[6];
-    BDG_HIP(hipMemcpyAsync(info, ms.info, sizeof(info), hipMemcpyDeviceToHost, s));
+    int errh = 0;
+    BDG_HIP(hipMemcpyAsync(&errh, ms.err, sizeof(int), hipMemcpyDeviceToHost, s));
     BDG_HIP(hipStreamSynchronize(s));
-    if (info[3]) {
+    if (errh) {
         set_error("stedc: secular equation did not converge");
         return BDG_ERR_NOCONV;
     }
