@@ -137,92 +137,86 @@ __global__ __launch_bounds__(256) void panel_step(F *__restrict__ P, int64_t ld,
             }
         }
         __syncthreads();
-        const F tj = sc[2];
-        const F ur = sc[0], ui = sc[1];
-        const bool active = sc[5] != 0.0;
-        if (blockIdx.x == 0 && t == 0) tau[j] = tj;
-        if (active) {
-            // w_c = (s_c - conj(beta) P[j,c]) / conj(u0), scaled by tau: tw_c = tau * w_c
-            const F br = sc[3], bi = sc[4];
-            for (int c = j + 1 + t; c < nb; c += blockDim.x) {
-                const F sr = s_sh[2 * c], si = s_sh[2 * c + 1];
-                const F pr = row_in[2 * c], pi = row_in[2 * c + 1];
-                // s - conj(beta) * p
-                const F nr = sr - (br * pr + bi * pi);
-                const F ni = si - (br * pi - bi * pr);
-                // / conj(u0) == * conj(1/u0)   (1/conj(u0) = conj(1/u0))
-                const F cr = ur, ci = -ui;
-                wc[2 * c] = tj * (nr * cr - ni * ci);
-                wc[2 * c + 1] = tj * (nr * ci + ni * cr);
-            }
-            __syncthreads();
-            if (have && r >= j) {
-                // v_r: 1 at r == j, x_r / u0 below
-                F vr, vi;
-                F *pj = P + 2 * (r + (int64_t)j * ld);
-                if (r == j) {
-                    vr = 1.0; vi = 0.0;
-                    pj[0] = sc[3];
-                    pj[1] = sc[4];
-                } else {
-                    const F xr = pj[0], xi = pj[1];
-                    vr = xr * ur - xi * ui;
-                    vi = xr * ui + xi * ur;
-                    pj[0] = vr;
-                    pj[1] = vi;
-                }
-                // columns in chunks of 16: all loads of a chunk are issued first
-                for (int c0 = j + 1; c0 < nb; c0 += 16) {
-                    CV pv[16];
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        const int c = c0 + q;
-                        pv[q] = (c < nb) ? ld2<F>(P + 2 * (r + (int64_t)c * ld))
-                                         : mk2<F>(0.0, 0.0);
-                    }
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        const int c = c0 + q;
-                        if (c >= nb) break;
-                        const F wr = wc[2 * c], wi = wc[2 * c + 1];
-                        st2<F>(P + 2 * (r + (int64_t)c * ld),
-                               mk2<F>(pv[q].x - (vr * wr - vi * wi), pv[q].y - (vr * wi + vi * wr)));
-                    }
-                }
-            }
-        } else if (have && r == j) {
-            // no reflector: R diagonal keeps alpha (already in place)
+    }
+    const F tj = j >= 0 ? sc[2] : 0.0;
+    const F ur = j >= 0 ? sc[0] : 0.0, ui = j >= 0 ? sc[1] : 0.0;
+    const bool upd = j >= 0 && sc[5] != 0.0;  // uniform: a reflector to apply
+    if (j >= 0 && blockIdx.x == 0 && t == 0) tau[j] = tj;
+    if (upd) {
+        // w_c = (s_c - conj(beta) P[j,c]) / conj(u0), scaled by tau: tw_c = tau * w_c
+        const F br = sc[3], bi = sc[4];
+        for (int c = j + 1 + t; c < nb; c += blockDim.x) {
+            const F sr = s_sh[2 * c], si = s_sh[2 * c + 1];
+            const F pr = row_in[2 * c], pi = row_in[2 * c + 1];
+            // s - conj(beta) * p
+            const F nr = sr - (br * pr + bi * pi);
+            const F ni = si - (br * pi - bi * pr);
+            // / conj(u0) == * conj(1/u0)   (1/conj(u0) = conj(1/u0))
+            const F cr = ur, ci = -ui;
+            wc[2 * c] = tj * (nr * cr - ni * ci);
+            wc[2 * c + 1] = tj * (nr * ci + ni * cr);
         }
         __syncthreads();
     }
-
     const int jn = j + 1;
-    if (jn < ncol) {
-        // partials for column jn over rows r >= jn
-        F xr = 0.0, xi = 0.0;
-        const bool in = have && r >= jn;
-        if (in) {
-            const F *px = P + 2 * (r + (int64_t)jn * ld);
-            xr = px[0];
-            xi = px[1];
+    const bool part = jn < ncol;  // uniform: partials for column jn wanted
+    if (!upd && !part) return;
+    // One pass over this thread's panel row: apply reflector j to columns
+    // > j, then form the partials of column jn from the updated values while
+    // they are still in registers.
+    const bool rowupd = upd && have && r >= j;
+    const bool in = part && have && r >= jn;
+    F vr = 0.0, vi = 0.0;
+    if (rowupd) {
+        // v_r: 1 at r == j, x_r / u0 below
+        F *pj = P + 2 * (r + (int64_t)j * ld);
+        if (r == j) {
+            vr = 1.0;
+            pj[0] = sc[3];
+            pj[1] = sc[4];
+        } else {
+            const F xr = pj[0], xi = pj[1];
+            vr = xr * ur - xi * ui;
+            vi = xr * ui + xi * ur;
+            pj[0] = vr;
+            pj[1] = vi;
         }
-        const int w = t >> 6, l = t & 63;
-        // tail2 over r > jn
-        F t2 = (in && r > jn) ? xr * xr + xi * xi : 0.0;
-        t2 = wave_sum_last(t2);
-        if (l == 63) { red[w][2 * nb] = t2; red[w][2 * nb + 1] = 0.0; }
-        for (int c0 = jn + 1; c0 < nb; c0 += 16) {
-            CV pv[16];
+    }
+    const bool need = rowupd || in;
+    const int w = t >> 6, l = t & 63;
+    F xr = 0.0, xi = 0.0;
+    // columns in chunks of 16: all loads of a chunk are issued first
+    for (int c0 = jn; c0 < nb; c0 += 16) {
+        CV pv[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int c = c0 + q;
+            pv[q] = (need && c < nb) ? ld2<F>(P + 2 * (r + (int64_t)c * ld)) : mk2<F>(0.0, 0.0);
+        }
+        if (rowupd) {
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int c = c0 + q;
-                pv[q] = (in && c < nb) ? ld2<F>(P + 2 * (r + (int64_t)c * ld))
-                                       : mk2<F>(0.0, 0.0);
+                if (c >= nb) break;
+                const F wr = wc[2 * c], wi = wc[2 * c + 1];
+                pv[q] = mk2<F>(pv[q].x - (vr * wr - vi * wi), pv[q].y - (vr * wi + vi * wr));
+                st2<F>(P + 2 * (r + (int64_t)c * ld), pv[q]);
+            }
+        }
+        if (part) {
+            if (c0 == jn) {
+                // column jn itself: x, and tail2 over r > jn
+                xr = in ? pv[0].x : 0.0;
+                xi = in ? pv[0].y : 0.0;
+                F t2 = (in && r > jn) ? xr * xr + xi * xi : 0.0;
+                t2 = wave_sum_last(t2);
+                if (l == 63) { red[w][2 * nb] = t2; red[w][2 * nb + 1] = 0.0; }
             }
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
                 const int c = c0 + q;
                 if (c >= nb) break;
+                if (c == jn) continue;
                 // conj(x) * p
                 F sr = xr * pv[q].x + xi * pv[q].y, si = xr * pv[q].y - xi * pv[q].x;
                 sr = wave_sum_last(sr);
@@ -230,6 +224,8 @@ __global__ __launch_bounds__(256) void panel_step(F *__restrict__ P, int64_t ld,
                 if (l == 63) { red[w][2 * c] = sr; red[w][2 * c + 1] = si; }
             }
         }
+    }
+    if (part) {
         __syncthreads();
         for (int c = t; c <= nb; c += blockDim.x) {
             F sr = 0.0, si = 0.0;
