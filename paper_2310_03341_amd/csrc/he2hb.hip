@@ -49,6 +49,7 @@ struct Events {
     }
 };
 constexpr int MAXB = 64;      // largest supported band
+constexpr int PCH = 32;       // panel columns per load batch in a column step
 
 // Partials layout per workgroup: [0..nb) complex s_c, [nb] (tail2, 0).
 template <typename F>
@@ -185,17 +186,17 @@ __global__ __launch_bounds__(256) void panel_step(F *__restrict__ P, int64_t ld,
     const bool need = rowupd || in;
     const int w = t >> 6, l = t & 63;
     F xr = 0.0, xi = 0.0;
-    // columns in chunks of 16: all loads of a chunk are issued first
-    for (int c0 = jn; c0 < nb; c0 += 16) {
-        CV pv[16];
+    // columns in chunks of PCH: all loads of a chunk are issued first
+    for (int c0 = jn; c0 < nb; c0 += PCH) {
+        CV pv[PCH];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < PCH; ++q) {
             const int c = c0 + q;
             pv[q] = (need && c < nb) ? ld2<F>(P + 2 * (r + (int64_t)c * ld)) : mk2<F>(0.0, 0.0);
         }
         if (rowupd) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
+            for (int q = 0; q < PCH; ++q) {
                 const int c = c0 + q;
                 if (c >= nb) break;
                 const F wr = wc[2 * c], wi = wc[2 * c + 1];
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(256) void panel_step(F *__restrict__ P, int64_t ld,
                 if (l == 63) { red[w][2 * nb] = t2; red[w][2 * nb + 1] = 0.0; }
             }
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
+            for (int q = 0; q < PCH; ++q) {
                 const int c = c0 + q;
                 if (c >= nb) break;
                 if (c == jn) continue;
