@@ -596,6 +596,7 @@ int bt1_t(int64_t n, int64_t m, const F *A, int64_t lda, int b, const F *T1, F *
     F *Tg = G + 2 * (size_t)gmax * gmax;            // gb x gb
     F *X = Tg + 2 * (size_t)gmax * gmax;            // gb x b
     F *Vg = X + 2 * (size_t)gmax * b;               // R x gb
+    F *Pk = Vg + 2 * (size_t)n * gmax;              // split-K partials of G (<= 64 gb x gb)
     const int ngroups = (np + BT1_GROUP - 1) / BT1_GROUP;
     for (int q = ngroups - 1; q >= 0; --q) {
         const int p0 = q * BT1_GROUP;
@@ -610,7 +611,11 @@ int bt1_t(int64_t n, int64_t m, const F *A, int64_t lda, int b, const F *T1, F *
                            T1 + 2 * (size_t)p0 * b * b, Tg);
         BDG_CHECK_LAUNCH();
         if (g > 1) {
-            GemmArgs gg{gb, gb, R, 1.0, 0.0, 0.0, 0.0, Vg, R, Vg, R, G, gb, GEMM_FULL, 1, nullptr};
+            // only (gb / 64)^2 output tiles over a long K: split K to fill the chip
+            const int64_t tg = (gb + 63) / 64;
+            const int skg = splitk_for(tg * tg, R);
+            GemmArgs gg{gb, gb, R, 1.0, 0.0, 0.0, 0.0, Vg, R, Vg, R, G, gb, GEMM_FULL, skg,
+                        skg > 1 ? Pk : nullptr};
             BDG_TRY((gemm<F, true>('C', 'N', gg, s)));
             for (int c = 1; c < g; ++c) {
                 const int cb = c * b;
@@ -635,7 +640,7 @@ int bt1_t(int64_t n, int64_t m, const F *A, int64_t lda, int b, const F *T1, F *
 
 size_t bt1_workspace(int64_t n, int64_t m, int b) {
     const size_t gb = (size_t)BT1_GROUP * b;
-    return 16 * (2 * gb * (size_t)m + 2 * gb * gb + gb * (size_t)b + gb * (size_t)n) + 1024;
+    return 16 * (2 * gb * (size_t)m + 2 * gb * gb + gb * (size_t)b + gb * (size_t)n + 64 * gb * gb) + 1024;
 }
 
 }  // namespace bdg
