@@ -122,6 +122,13 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const F *_
     const int64_t s0 = S * NBK;
     const int tid = threadIdx.x;
     const int64_t nsw = n - 2;
+    // the first sweep of the block has the most tasks: when it has none at
+    // step t, no sweep of the block has, and T is zero
+    if (s0 >= nsw || t >= (n - 2 - s0) / b + 1) {
+        for (int e = tid; e < NBK * NBK; e += blockDim.x)
+            st2<F>(TF + 2 * (blk * NBK * NBK + e), mk2<F>(0.0, 0.0));
+        return;
+    }
     // parallelogram: column j holds reflector (s0 + j, t) at rows j .. j + b - 1
     for (int e = tid; e < HT * 16 * NBK; e += blockDim.x) {
         const int r = e % (HT * 16), j = e / (HT * 16);
