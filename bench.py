@@ -32,8 +32,8 @@ PEAK_HBM = 8.0e12
 # 1 GiB device copy in the same run.  Valid only for the kernel source it was
 # measured on (sha256 of csrc/bt2.hip) and the same workload; otherwise the
 # bench reports null.
-BT2_TRAFFIC = {"sha256": "9821f0cf520c5d721dde1f28274a9443cb2d1673f32bf79ef67e32eefc590de2",
-               "n": 27648, "m_bt": 13824, "fetch_bytes": 2752994630272.3, "write_bytes": 2644664025600.0}
+BT2_TRAFFIC = {"sha256": "dda6933e22db1ebe8de7d7e0571a36404f7aba599481187a0620e8dd9b2fded8",
+               "n": 27648, "m_bt": 13824, "fetch_bytes": 2815356218815.6, "write_bytes": 2644663801472.0}
 
 
 def _bt2_source_sha() -> str:
