@@ -548,6 +548,18 @@ struct StreamEvents {
     }
 };
 
+// Between a fork and its join the merge streams may still run kernels on the
+// caller's workspace: an early error return drains them first.
+struct MergeDrain {
+    hipStream_t *st;
+    bool armed = false;
+    explicit MergeDrain(hipStream_t *s) : st(s) {}
+    ~MergeDrain() {
+        if (armed)
+            for (int q = 0; q < MERGE_STREAMS; ++q) (void)hipStreamSynchronize(st[q]);
+    }
+};
+
 }  // namespace
 
 size_t stedc_workspace(int64_t n) {
@@ -674,8 +686,10 @@ int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *
         set_error("stedc: could not create events");
         return BDG_ERR_HIP;
     }
+    MergeDrain drain(mst);
     auto fork = [&]() -> int {
         BDG_HIP(hipEventRecord(evs.main, s));
+        drain.armed = true;
         for (int q = 0; q < MERGE_STREAMS; ++q) BDG_HIP(hipStreamWaitEvent(mst[q], evs.main, 0));
         return 0;
     };
@@ -684,6 +698,7 @@ int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *
             BDG_HIP(hipEventRecord(evs.side[q], mst[q]));
             BDG_HIP(hipStreamWaitEvent(s, evs.side[q], 0));
         }
+        drain.armed = false;
         return 0;
     };
     std::vector<int> infoh;
