@@ -318,22 +318,40 @@ __global__ void tfactor(int nb, const F *__restrict__ G, const F *__restrict__ t
     }
     for (int e = t; e < nb; e += blockDim.x) taus[e] = tau[e];
     __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        const F tj = taus[j];
-        if (t < j) {
-            F sr = 0.0, si = 0.0;
-            for (int l = t; l < j; ++l) {
-                const F ar = Ts[2 * (t + l * nb)], ai = Ts[2 * (t + l * nb) + 1];
-                const F gr = Gs[2 * (l + j * nb)], gi = Gs[2 * (l + j * nb) + 1];
-                sr += ar * gr - ai * gi;
-                si += ar * gi + ai * gr;
+    // T is the inverse of U = diag(1 / tau) + (strictly upper part of G), G =
+    // V^H V: the same matrix the forward column recurrence builds.  Each quad
+    // of lanes solves one column by back substitution,
+    //   T[c, c] = tau_c,  T[i, c] = -tau_i sum_{k = i+1 .. c} G[i, k] T[k, c],
+    // the four lanes taking every fourth k; the columns proceed independently
+    // with no block barrier per step (a quad's lanes are in one wave, whose
+    // LDS accesses complete in order).  A zero tau gives a zero row and
+    // column, as in the recurrence.
+    {
+        const int c = t >> 2, q = t & 3;
+        if (c < nb) {
+            if (q == 0) {
+                Ts[2 * (c + c * nb)] = taus[c];
+                Ts[2 * (c + c * nb) + 1] = 0.0;
             }
-            Ts[2 * (t + j * nb)] = -tj * sr;
-            Ts[2 * (t + j * nb) + 1] = -tj * si;
+            for (int i = c - 1; i >= 0; --i) {
+                F sr = 0.0, si = 0.0;
+                for (int k = i + 1 + q; k <= c; k += 4) {
+                    const F gr = Gs[2 * (i + k * nb)], gi = Gs[2 * (i + k * nb) + 1];
+                    const F xr = Ts[2 * (k + c * nb)], xi = Ts[2 * (k + c * nb) + 1];
+                    sr += gr * xr - gi * xi;
+                    si += gr * xi + gi * xr;
+                }
+                sr = quad_sum(sr);
+                si = quad_sum(si);
+                if (q == 0) {
+                    const F ti = taus[i];
+                    Ts[2 * (i + c * nb)] = -ti * sr;
+                    Ts[2 * (i + c * nb) + 1] = -ti * si;
+                }
+            }
         }
-        if (t == j) { Ts[2 * (j + j * nb)] = tj; Ts[2 * (j + j * nb) + 1] = 0.0; }
-        __syncthreads();
     }
+    __syncthreads();
     for (int e = t; e < nb * nb; e += blockDim.x) { T[2 * e] = Ts[2 * e]; T[2 * e + 1] = Ts[2 * e + 1]; }
 }
 
