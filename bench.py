@@ -32,8 +32,8 @@ PEAK_HBM = 8.0e12
 # 1 GiB device copy in the same run.  Valid only for the kernel source it was
 # measured on (sha256 of csrc/bt2.hip) and the same workload; otherwise the
 # bench reports null.
-BT2_TRAFFIC = {"sha256": "dda6933e22db1ebe8de7d7e0571a36404f7aba599481187a0620e8dd9b2fded8",
-               "n": 27648, "m_bt": 13824, "fetch_bytes": 2815356218815.6, "write_bytes": 2644663801472.0}
+BT2_TRAFFIC = {"sha256": "122662b2e2e208d74920f58867aaaab03df1824c15fa9fcf0d98d4e523273fa4",
+               "n": 27648, "m_bt": 13824, "fetch_bytes": 2835046342875.2, "write_bytes": 2644667391104.0}
 
 
 def _bt2_source_sha() -> str:

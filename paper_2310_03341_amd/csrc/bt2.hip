@@ -105,8 +105,8 @@ __global__ __launch_bounds__(256) void rm_to_cm_kernel(int64_t n, int64_t m, con
     }
 }
 
-// T factor of every block G(S, t): forward column-wise recurrence from
-// V^H V over the parallelogram and the scales tau.  One workgroup per block.
+// T factor of every block G(S, t), the compact-WY factor of its reflectors,
+// from V^H V over the parallelogram and the scales tau.  One workgroup per block.
 template <typename F>
 __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const F *__restrict__ V2,
                                                     const F *__restrict__ tau2,
@@ -160,20 +160,30 @@ __global__ __launch_bounds__(256) void bt2_tfactors(int64_t n, int b, const F *_
         Ts[e] = mk2<F>(0.0, 0.0);
     }
     __syncthreads();
-    for (int j = 0; j < NBK; ++j) {
-        const F tj = ts[j];
-        if (tid < j) {
-            F sr = 0.0, si = 0.0;
-            for (int l = tid; l < j; ++l) {
-                const CV a = Ts[tid + l * NBK], g = Gs[l + j * NBK];
-                sr += a.x * g.x - a.y * g.y;
-                si += a.x * g.y + a.y * g.x;
+    // T is the inverse of U = diag(1 / tau) + (strictly upper part of G): each
+    // quad of lanes solves one column by back substitution,
+    //   T[c, c] = tau_c,  T[i, c] = -tau_i sum_{k = i+1 .. c} G[i, k] T[k, c],
+    // the four lanes taking every fourth k (a quad's lanes are in one wave,
+    // whose LDS accesses complete in order, so no block barrier per step).
+    // A zero tau gives a zero row and column.
+    {
+        const int c = tid >> 2, q = tid & 3;
+        if (c < NBK) {
+            if (q == 0) Ts[c + c * NBK] = mk2<F>(ts[c], 0.0);
+            for (int i = c - 1; i >= 0; --i) {
+                F sr = 0.0, si = 0.0;
+                for (int k = i + 1 + q; k <= c; k += 4) {
+                    const CV g = Gs[i + k * NBK], x = Ts[k + c * NBK];
+                    sr += g.x * x.x - g.y * x.y;
+                    si += g.x * x.y + g.y * x.x;
+                }
+                sr = quad_sum(sr);
+                si = quad_sum(si);
+                if (q == 0) Ts[i + c * NBK] = mk2<F>(-ts[i] * sr, -ts[i] * si);
             }
-            Ts[tid + j * NBK] = mk2<F>(-tj * sr, -tj * si);
         }
-        if (tid == j) Ts[j + j * NBK] = mk2<F>(tj, 0.0);
-        __syncthreads();
     }
+    __syncthreads();
     for (int e = tid; e < NBK * NBK; e += blockDim.x)
         st2<F>(TF + 2 * (blk * NBK * NBK + e), Ts[e]);
 }
