@@ -90,6 +90,12 @@ typedef struct {
  * variable BDG_NO_LOOKAHEAD is set (and not "0"), every panel is factored on
  * the caller's stream instead (same results; for tools that serialise
  * dispatches, such as hardware-counter profilers). */
+/* Divide and conquer (bdg_eigh, bdg_stage_stedc): the merges of one level of
+ * the merge tree run on four non-blocking streams the library creates once
+ * per device (default priority, kept until the process ends), ordered against
+ * the caller's stream by events.  The stage synchronises the caller's stream
+ * once per tree level to read the merge sizes back to the host, and returns
+ * only after all its work has been ordered before later work on `stream`. */
 
 /* Per-call accuracy and timing report (filled when non-NULL). */
 typedef struct {
