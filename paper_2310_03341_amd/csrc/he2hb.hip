@@ -367,9 +367,9 @@ __global__ void copy_cols(const F *__restrict__ src, int64_t lds, F *__restrict_
 }
 
 int splitk_for(int64_t tiles, int64_t K) {
-    // aim for >= 2048 workgroups (several per CU, so the last round is
+    // aim for >= 4096 workgroups (sixteen per CU, so the last round is
     // short), chunks of at least 512 along K
-    int64_t s = (2048 + tiles - 1) / tiles;
+    int64_t s = (4096 + tiles - 1) / tiles;
     const int64_t kmax = (K + 511) / 512;
     if (s > kmax) s = kmax;
     if (s < 1) s = 1;
