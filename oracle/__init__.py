@@ -16,6 +16,10 @@ Contents
   * ``eigh``: dispatcher (Jacobi for small n, Householder+QL otherwise), with
     an optional closed energy window [emin, emax] as in the density sums of
     eq. (densities2).
+  * ``assemble_entries``: selected entries of H from the same definition.
+  * ``apply_h``: H applied to vectors without forming H (one 1-D kinetic
+    matrix per lattice axis, then the local U - mu and Delta terms), for
+    residuals of eigenvectors at sizes where the dense H does not fit the CPU.
 Further oracle modules: ``oracle.scf`` (densities and SCF update),
 ``oracle.refine`` (Ogita-Aishima refinement step), ``oracle.net`` (conv net).
 """
@@ -211,3 +215,42 @@ def assemble_entries(dims, U, Delta, mu, rows, cols) -> np.ndarray:
         elif si == sj:
             out[k] = np.conj(D[si]) if bi else D[si]
     return out
+
+
+def apply_h(dims, U, Delta, mu, Z) -> np.ndarray:
+    """H @ Z for the BdG matrix of eq. (stHpsi) without forming H.
+
+    Z is (n, k) with rows [u; v], site index r = x + Nx (y + Ny z).  The
+    kinetic operator of "Numerical setup and implementation" is separable:
+    h acts on u as sum_d T_d along axis d (T_d from ``kinetic_1d``, the direct
+    Fourier sum) plus the local U(r) - mu.  Then
+        (H z)_u = h u + Delta v,     (H z)_v = conj(Delta) u - conj(h) v.
+    """
+    dims = [int(v) for v in dims]
+    ns = int(np.prod(dims))
+    Z = np.asarray(Z, dtype=np.complex128)
+    if Z.ndim == 1:
+        return apply_h(dims, U, Delta, mu, Z[:, None])[:, 0]
+    k = Z.shape[1]
+    assert Z.shape[0] == 2 * ns
+    U = np.asarray(U, dtype=np.float64)
+    D = np.asarray(Delta, dtype=np.complex128)
+    # array axes (z, y, x, column) in C order put x fastest
+    shape = tuple(reversed(dims)) + (k,)
+
+    def kin(f, conj):
+        f = f.reshape(shape)
+        out = np.zeros(shape, dtype=np.complex128)
+        for d, N in enumerate(dims):
+            T = kinetic_1d(N)
+            if conj:
+                T = T.conj()
+            ax = len(dims) - 1 - d
+            out += np.moveaxis(np.tensordot(T, f, axes=([1], [ax])), 0, ax)
+        return out.reshape(ns, k)
+
+    u, v = Z[:ns], Z[ns:]
+    loc = (U - mu)[:, None]
+    hu = kin(u, False) + loc * u
+    hv = kin(v, True) + loc * v
+    return np.vstack([hu + D[:, None] * v, D.conj()[:, None] * u - hv])

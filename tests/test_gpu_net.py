@@ -135,3 +135,39 @@ def test_net_training_reduces_loss(dev):
         sn.adam(3e-3)
     l1 = sn.backward(Vd, Td, mu, tg).item()
     assert l1 < 0.2 * l0, (l0, l1)
+
+
+def test_adam_matches_oracle_elementwise(dev):
+    """bdg_net_adam_step against Kingma & Ba's update in the oracle (FP64) over
+    ten steps.  Gradients span 1e-9 .. 1, so that epsilon (1e-8) decides the
+    smallest updates and its placement is checked too.  Tolerance: the kernel
+    computes in FP32, and 1 - 0.999f^t carries a relative error of about 1.3e-5
+    that the bias-corrected second moment only partly cancels."""
+    import torch
+    from oracle import net
+    from paper_2310_03341_amd import api
+    rng = np.random.default_rng(41)
+    nparam = 5000
+    p0 = rng.standard_normal(nparam).astype(np.float32)
+    scale = 10.0 ** rng.uniform(-9, 0, nparam)
+    sn = api.StartNet(4, 4, 4, 1, dev)  # only its Adam state is used
+    params = torch.from_numpy(p0).to(dev)
+    grads = torch.zeros_like(params)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    ref_p, ref_m, ref_v = [p0.astype(np.float64)], [np.zeros(nparam)], [np.zeros(nparam)]
+    lr = 1e-2
+    for t in range(1, 11):
+        g = (rng.standard_normal(nparam) * scale).astype(np.float32)
+        grads.copy_(torch.from_numpy(g))
+        api._call("bdg_net_adam_step", nparam, params.data_ptr(), grads.data_ptr(), m.data_ptr(),
+                  v.data_ptr(), t, float(lr), api._stream(dev))
+        ref_p = net.adam_step(ref_p, [g.astype(np.float64)], ref_m, ref_v, t, lr=lr)
+        torch.cuda.synchronize()
+        gp, gm, gv = params.cpu().numpy(), m.cpu().numpy(), v.cpu().numpy()
+        assert np.abs(gm - ref_m[0]).max() <= 1e-6 * np.abs(ref_m[0]).max()
+        assert np.all(np.abs(gv - ref_v[0]) <= 3e-5 * ref_v[0] + 1e-38)
+        assert np.all(np.abs(gm - ref_m[0]) <= 1e-5 * np.abs(ref_m[0]) + 1e-45)
+        # each step moves a parameter by at most ~lr; FP32 rounding of p itself
+        assert np.all(np.abs(gp - ref_p[0]) <= 2e-5 * lr * t + 2e-7 * np.abs(ref_p[0])), t
+    del sn
