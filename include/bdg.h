@@ -80,6 +80,12 @@ typedef struct {
                                 the E < 0 ones as (-v^*, u^*) (particle-hole
                                 symmetry of a BdG matrix with real h and local
                                 Delta); 0: back-transform every vector          */
+    int64_t max_pairs;       /* BDG_FP32_REFINED: most eigenpairs the window can
+                                hold (0 = n).  The refinement buffers are sized
+                                for it (plus max_pairs/64 + 64 columns for the
+                                guard band around the window), so a window of a
+                                few tenths of the spectrum needs far less
+                                workspace than n.  Ignored by BDG_FP64.          */
 } bdg_opts;
 
 /* Progress: when the environment variable BDG_VERBOSE is set (and not "0"),
@@ -145,12 +151,74 @@ int bdg_eigh_workspace(int64_t n, const bdg_opts *opts, size_t *bytes);
  *   opts      options (NULL = defaults, FP64).
  *   work      device workspace of work_bytes >= bdg_eigh_workspace(n, opts).
  *   report    optional host pointer for accuracy/timing information.
- * Synchronises `stream` once to read the window count m back to the host.
+ * Host synchronisation: the call returns only after its work on `stream` has
+ * finished.  On the way it waits for `stream` to read back the NaN/Inf flag,
+ * after uploading the stage-2 reflector offsets, once per level of the
+ * divide-and-conquer merge tree (merge sizes) and to read the eigenvalues
+ * that decide the window; the mixed arm also once per refinement step.
  * Returns BDG_ERR_NONFINITE (and does not modify W, Z) if A holds NaN/Inf.
+ *
+ * BDG_FP32_REFINED: A is only read (kept intact; the FP64 refinement needs
+ * it).  The window is cut on the REFINED eigenvalues: every eigenvalue of the
+ * FP32 stages within 1e-4 ||H||_2 of [emin, emax] is refined, then the window
+ * is taken; *m counts the refined eigenvalues inside it.  If more pairs need
+ * refining than opts.max_pairs allows, BDG_ERR_WORKSPACE is returned and *m
+ * holds that count.
  */
 int bdg_eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
              double *Z, int64_t ldz, int64_t zcols, int64_t *m, const bdg_opts *opts,
              void *work, size_t work_bytes, bdg_err_report *report, bdg_stream_t stream);
+
+/*
+ * bdg_refine_workspace -- device workspace (bytes) of bdg_refine for order n
+ * and m refined columns.
+ */
+int bdg_refine_workspace(int64_t n, int64_t m, size_t *bytes);
+
+/*
+ * bdg_refine -- FP64 refinement of the eigenpairs in columns [i0, i0 + m) of
+ * an approximate eigenbasis X of the Hermitian H (the precision extension of
+ * the method: Ogita & Aishima, "Iterative refinement for symmetric eigenvalue
+ * decomposition", Japan J. Indust. Appl. Math. 35 (2018), complex Hermitian
+ * form, with a Rayleigh-Ritz step inside groups of close eigenvalues as in
+ * their part II on clustered eigenvalues, 2019).  One step, for the window
+ * columns W against the whole basis:
+ *     R = I[:, W] - X^H X_W,  S = X^H H X_W   (window rows Hermitian-symmetrised)
+ *     lam_j = s_jj / (1 - r_jj),
+ *     E_ij = (s_ij + lam_j r_ij) / (lam_j - lam_i), or r_ij / 2 for close pairs,
+ *     X_W <- X_W + X E.
+ * A pair is close when |s_ij + lam_j r_ij| >= 1e-3 |lam_j - lam_i|; connected
+ * groups of close window pairs (cut into pieces of at most 48) get the
+ * Rayleigh-Ritz step.  Steps repeat until the defect (max |r_ij| and
+ * |s_ij + lam_j r_ij| / ||H||_2 off the diagonal, in-cluster coupling /
+ * ||H||_2) drops below opts.refine_tol or opts.refine_max_iter steps are done.
+ *   n      order of H (>= 1).
+ *   H      [ldh x n] complex128 Hermitian, lower triangle read, not modified.
+ *   lam    [n] f64 approximate eigenvalues of ALL columns of X (device); they
+ *          stand in for the Rayleigh quotients of the columns outside the
+ *          window.  max |lam| is taken as ||H||_2.
+ *   X      [ldx x n] complex128 approximate eigenvectors, all n of them
+ *          (refining a subset needs the whole basis: the error of a window
+ *          column along the other eigenvectors is corrected from them);
+ *          columns i0 .. i0+m-1 are refined in place, the others are read.
+ *   i0, m  the refined columns, 0 <= i0, i0 + m <= n.
+ *   W      [m] f64 output: W[k] is the refined eigenvalue of column i0 + k.
+ *          The column order is kept (two columns of a pair closer than the
+ *          basis error may converge swapped: sort W if order matters).
+ *   opts   refine_max_iter (0 = 4, < 0 invalid), refine_tol (0 = 1e-14); the
+ *          other fields are ignored.  NULL = defaults.
+ *   work   device workspace of work_bytes >= bdg_refine_workspace(n, m).
+ *   report optional host pointer: refine_iters, max_resid (last defect),
+ *          eig_shift_max (largest change of an eigenvalue in the first step),
+ *          refine_close_pairs / refine_cluster_cols (first step),
+ *          stage_ms[5] = stage_ms[7] = elapsed time.
+ * Synchronises `stream` once per step (close pairs and the defect are read
+ * back).  Returns BDG_ERR_REFINE_TOL when the last defect still exceeds
+ * sqrt(refine_tol) (X and W hold the refined result all the same).
+ */
+int bdg_refine(int64_t n, const double *H, int64_t ldh, const double *lam, double *X, int64_t ldx,
+               int64_t i0, int64_t m, double *W, const bdg_opts *opts, void *work, size_t work_bytes,
+               bdg_err_report *report, bdg_stream_t stream);
 
 /*
  * Constants of one self-consistency step (the SLDA loop of "Methods").
@@ -243,7 +311,7 @@ const char *bdg_version(void);
 
 /*
  * bdg_zgemm -- C = alpha op(A) op(B) + beta C, complex128, column-major,
- * op = 'N' (none) or 'C' (conjugate transpose).  alpha/beta are host
+ * op = 'N' (none) or 'C' (conjugate transpose); 'T' is refused (-1 / -2).  alpha/beta are host
  * complex scalars given as (re, im) pairs.  The MFMA tile kernel shared by
  * stage 1 and the back-transformations.
  */
@@ -256,7 +324,8 @@ int bdg_cgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, const float *
               const float *A, int64_t lda, const float *B, int64_t ldb, const float *beta,
               float *C, int64_t ldc, bdg_stream_t stream);
 
-/* bdg_dgemm -- same for real f64 (used by the divide-and-conquer merges). */
+/* bdg_dgemm -- same for real f64 (used by the divide-and-conquer merges);
+ * 'T' and 'C' both transpose. */
 int bdg_dgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, double alpha,
               const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
               double *C, int64_t ldc, bdg_stream_t stream);
@@ -278,6 +347,24 @@ int bdg_dgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, double alpha,
  * bdg_stage_bt1: Z <- Q1 Z with the stage-1 reflectors left in A.
  */
 int bdg_stage_workspace(int stage, int64_t n, int band, int64_t m, size_t *bytes);
+
+/*
+ * bdg_stage_zgemm -- the complex128 tile GEMM in one of the modes the solver
+ * stages use, with an explicit split of K (the stage-1 products and the BT1
+ * Gram product split K over several workgroups and sum the partial products
+ * in a second kernel).  C = alpha op(A) op(B) + beta C, column-major.
+ *   mode 0: every tile of C.
+ *   mode 1: only the 64 x 64 tiles of C on and below the diagonal (Hermitian
+ *           rank-k updates); needs opA = 'N', M == N, splitk == 1.
+ *   mode 2: A is Hermitian M x M with only its lower triangle valid (the
+ *           upper triangle is never read); needs opA = 'N', K == M.
+ *   splitk 1..64: number of K chunks (rounded to whole 16-deep steps; may
+ *           come out smaller).  work: >= 16 splitk M N bytes when splitk > 1.
+ */
+int bdg_stage_zgemm(int mode, int splitk, char opA, char opB, int64_t M, int64_t N, int64_t K,
+                    const double *alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                    const double *beta, double *C, int64_t ldc, void *work, size_t work_bytes,
+                    bdg_stream_t stream);
 int64_t bdg_stage_nrefl(int64_t n, int band);
 int bdg_stage_he2hb(int64_t n, double *A, int64_t lda, int band, double *AB, int64_t ldab,
                     double *T1, void *work, size_t work_bytes, bdg_stream_t stream);

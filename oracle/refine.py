@@ -138,8 +138,9 @@ def oa_step(H: np.ndarray, X: np.ndarray, normH: float | None = None, cluster_rr
 
 
 def oa_step_window(H: np.ndarray, X: np.ndarray, lam0: np.ndarray, cols: np.ndarray, normH: float,
-                   cluster_rr: bool = True, rule: str = "pair"):
-    """Refine columns `cols` of the full basis X; returns (X_W_new, lam_W).
+                   cluster_rr: bool = True, rule: str = "pair", return_clusters: bool = False):
+    """Refine columns `cols` of the full basis X; returns (X_W_new, lam_W),
+    and the clusters (index arrays into the window) if return_clusters.
 
     lam0 are the approximate eigenvalues that came with X; outside the window
     they stand in for the Rayleigh quotients in the denominators (their error
@@ -164,6 +165,8 @@ def oa_step_window(H: np.ndarray, X: np.ndarray, lam0: np.ndarray, cols: np.ndar
     E, cl = _correction(S, R, lam_all, lam_W, cols, rule, delta)
     if cluster_rr:
         _cluster_rr(E, I_W, Rw, Sw, lam_W, cl)
+    if return_clusters:
+        return XW + X @ E, lam_W, cl
     return XW + X @ E, lam_W
 
 

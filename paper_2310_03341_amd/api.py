@@ -40,7 +40,8 @@ class Lattice(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("band", ctypes.c_int32),
                 ("refine_max_iter", ctypes.c_int32), ("refine_tol", ctypes.c_double),
-                ("dc_leaf", ctypes.c_int32), ("ph_mirror", ctypes.c_int32)]
+                ("dc_leaf", ctypes.c_int32), ("ph_mirror", ctypes.c_int32),
+                ("max_pairs", ctypes.c_int64)]
 
 
 class Report(ctypes.Structure):
@@ -73,6 +74,9 @@ def lib():
         L.bdg_cgemm.argtypes = L.bdg_zgemm.argtypes
         L.bdg_dgemm.argtypes = [ctypes.c_char, ctypes.c_char, I64, I64, I64, D, P, I64, P, I64,
                                 D, P, I64, S]
+        L.bdg_refine_workspace.argtypes = [I64, I64, ctypes.POINTER(ctypes.c_size_t)]
+        L.bdg_refine.argtypes = [I64, P, I64, P, P, I64, I64, I64, P, ctypes.POINTER(Opts), P,
+                                 ctypes.c_size_t, ctypes.POINTER(Report), S]
         _lib = L
     return _lib
 
@@ -136,10 +140,12 @@ def assemble(dims: Sequence[int], U: torch.Tensor, Delta: torch.Tensor, mu: floa
 
 
 def make_opts(precision: int = BDG_FP64, band: int = 0, refine_max_iter: int = 0,
-              refine_tol: float = 0.0, dc_leaf: int = 0, ph_mirror: int = 0) -> Opts:
+              refine_tol: float = 0.0, dc_leaf: int = 0, ph_mirror: int = 0,
+              max_pairs: int = 0) -> Opts:
     o = Opts()
     o.precision, o.band, o.refine_max_iter = precision, band, refine_max_iter
     o.refine_tol, o.dc_leaf, o.ph_mirror = refine_tol, dc_leaf, ph_mirror
+    o.max_pairs = max_pairs
     return o
 
 
@@ -179,6 +185,31 @@ def eigh(A: torch.Tensor, emin: float = -math.inf, emax: float = math.inf,
          opts: Optional[Opts] = None):
     """Eigenpairs of the Hermitian A (destroyed) with eigenvalues in [emin, emax]."""
     return Solver(A.shape[0], opts, A.device)(A, emin, emax)
+
+
+def refine_workspace(n: int, m: int) -> int:
+    nb = ctypes.c_size_t(0)
+    _call("bdg_refine_workspace", int(n), int(m), ctypes.byref(nb))
+    return int(nb.value)
+
+
+def refine(H: torch.Tensor, lam: torch.Tensor, X: torch.Tensor, i0: int, m: int,
+           opts: Optional[Opts] = None, W: Optional[torch.Tensor] = None):
+    """FP64 refinement of columns [i0, i0 + m) of the approximate eigenbasis X
+    (n x n complex128, column-major; refined in place) of the Hermitian H,
+    lam the approximate eigenvalues of all n columns.  Returns (W, report):
+    W[k] is the refined eigenvalue of column i0 + k."""
+    n = H.shape[0]
+    if X.shape != (n, n) or lam.numel() != n:
+        raise ValueError("X must be n x n and lam hold n values")
+    W = W if W is not None else torch.empty(max(m, 1), dtype=torch.float64, device=H.device)
+    nb = refine_workspace(n, m)
+    work = torch.empty(max(nb, 1), dtype=torch.uint8, device=H.device)
+    rep = Report()
+    _call("bdg_refine", n, _dev(H), _ld(H), _dev(lam), _dev(X), _ld(X), int(i0), int(m), _dev(W),
+          ctypes.byref(opts) if opts is not None else None, _dev(work), nb, ctypes.byref(rep),
+          _stream(H.device), warn_codes=(BDG_ERR_REFINE_TOL,))
+    return W[:m], rep
 
 
 def check(H: torch.Tensor, W: torch.Tensor, Z: torch.Tensor):
@@ -300,6 +331,25 @@ def stage_bt2(e_cplx, Y, i0, m, V2, tau2, voff, band: int = 64, rowmajor: bool =
     _call("bdg_stage_bt2", n, band, m, _dev(e_cplx), _dev(Y), i0, _dev(V2), _dev(tau2), _dev(voff),
           _dev(Z), _ld(Z), _dev(work), nbytes, _stream(Y.device))
     return Z[:, :m]
+
+
+def stage_zgemm(mode: int, splitk: int, opA: str, opB: str, A, B, C, alpha=1.0, beta=0.0):
+    """The complex128 tile GEMM in mode 0 (full), 1 (lower tiles) or 2 (Hermitian
+    A from its lower triangle) with K split into `splitk` chunks."""
+    L = lib()
+    P, I64, S = ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p
+    L.bdg_stage_zgemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_char, ctypes.c_char, I64, I64,
+                                  I64, P, P, I64, P, I64, P, P, I64, P, ctypes.c_size_t, S]
+    M, N = C.shape
+    K = A.shape[1] if opA == "N" else A.shape[0]
+    nb = 16 * splitk * M * N if splitk > 1 else 0
+    work = torch.empty(max(nb, 1), dtype=torch.uint8, device=C.device)
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    _call("bdg_stage_zgemm", mode, splitk, opA.encode(), opB.encode(), M, N, K,
+          ctypes.cast(al, ctypes.c_void_p), _dev(A), _ld(A), _dev(B), _ld(B),
+          ctypes.cast(be, ctypes.c_void_p), _dev(C), _ld(C), _dev(work), nb, _stream(C.device))
+    return C
 
 
 def stage_bt1(A, T1, Z, band: int = 64):

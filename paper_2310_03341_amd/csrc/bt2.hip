@@ -51,10 +51,13 @@ __global__ void phases_kernel(int64_t n, const double *__restrict__ e_cplx, doub
     }
 }
 
-// Z[:, j] = ph .* Y[:, i0 + j]  (Y real, ld n)
+// Z[:, j] = ph .* Y[:, i0 + j]  (Y real, ld n).  Each element is read once and
+// written once at its own position, so a complex64 Z may overwrite Y in place
+// (Z = Y + i0 n elements, ldz = n: both are 8-byte elements); Y and Z are not
+// declared restrict for that reason.
 template <typename F>
-__global__ void scale_phase(int64_t n, int64_t m, const double *__restrict__ Y, int64_t i0,
-                            const double *__restrict__ ph, F *__restrict__ Z, int64_t ldz) {
+__global__ void scale_phase(int64_t n, int64_t m, const double *Y, int64_t i0,
+                            const double *__restrict__ ph, F *Z, int64_t ldz) {
     const int64_t j = blockIdx.x;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         const double y = Y[i + (i0 + j) * n];

@@ -7,6 +7,7 @@
 #include "common.h"
 #include "gemm.h"
 #include "net.h"
+#include "refine.h"
 #include "solver.h"
 
 namespace bdg {
@@ -73,9 +74,12 @@ int bdg_assemble(const bdg_lattice *lat, const double *U, const double *Delta, d
     return bdg::assemble(lat, U, Delta, mu, H, ldh, (hipStream_t)stream);
 }
 
+// op 'T' (transpose without conjugation) only for real products, where it is 'C'
 static int check_gemm_args(char opA, char opB, int64_t M, int64_t N, int64_t K, const void *A,
-                           int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc) {
-    auto okop = [](char o) { return o == 'N' || o == 'n' || o == 'C' || o == 'c' || o == 'T' || o == 't'; };
+                           int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc, bool real) {
+    auto okop = [real](char o) {
+        return o == 'N' || o == 'n' || o == 'C' || o == 'c' || (real && (o == 'T' || o == 't'));
+    };
     if (!okop(opA)) { set_error("gemm: bad opA"); return -1; }
     if (!okop(opB)) { set_error("gemm: bad opB"); return -2; }
     if (M < 0) return -3;
@@ -94,7 +98,7 @@ static int check_gemm_args(char opA, char opB, int64_t M, int64_t N, int64_t K, 
 int bdg_zgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, const double *alpha,
               const double *A, int64_t lda, const double *B, int64_t ldb, const double *beta,
               double *C, int64_t ldc, bdg_stream_t stream) {
-    BDG_TRY(check_gemm_args(opA, opB, M, N, K, A, lda, B, ldb, C, ldc));
+    BDG_TRY(check_gemm_args(opA, opB, M, N, K, A, lda, B, ldb, C, ldc, false));
     GemmArgs g{M, N, K, alpha[0], alpha[1], beta[0], beta[1], A, lda, B, ldb, C, ldc, GEMM_FULL, 1, nullptr};
     return gemm<double, true>(opA, opB, g, (hipStream_t)stream);
 }
@@ -102,7 +106,7 @@ int bdg_zgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, const double 
 int bdg_cgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, const float *alpha,
               const float *A, int64_t lda, const float *B, int64_t ldb, const float *beta,
               float *C, int64_t ldc, bdg_stream_t stream) {
-    BDG_TRY(check_gemm_args(opA, opB, M, N, K, A, lda, B, ldb, C, ldc));
+    BDG_TRY(check_gemm_args(opA, opB, M, N, K, A, lda, B, ldb, C, ldc, false));
     GemmArgs g{M, N, K, alpha[0], alpha[1], beta[0], beta[1], A, lda, B, ldb, C, ldc, GEMM_FULL, 1, nullptr};
     return gemm<float, true>(opA, opB, g, (hipStream_t)stream);
 }
@@ -110,7 +114,7 @@ int bdg_cgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, const float *
 int bdg_dgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, double alpha,
               const double *A, int64_t lda, const double *B, int64_t ldb, double beta,
               double *C, int64_t ldc, bdg_stream_t stream) {
-    BDG_TRY(check_gemm_args(opA, opB, M, N, K, A, lda, B, ldb, C, ldc));
+    BDG_TRY(check_gemm_args(opA, opB, M, N, K, A, lda, B, ldb, C, ldc, true));
     GemmArgs g{M, N, K, alpha, 0.0, beta, 0.0, A, lda, B, ldb, C, ldc, GEMM_FULL, 1, nullptr};
     return gemm<double, false>(opA, opB, g, (hipStream_t)stream);
 }
@@ -165,6 +169,35 @@ int bdg_eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double
     }
     return bdg::eigh(n, A, lda, emin, emax, W, Z, ldz, zcols, m, opts, work, work_bytes, report,
                      (hipStream_t)stream);
+}
+
+int bdg_refine_workspace(int64_t n, int64_t m, size_t *bytes) {
+    if (n < 1) { set_error("bdg_refine_workspace: n must be >= 1"); return -1; }
+    if (m < 0 || m > n) { set_error("bdg_refine_workspace: m must be in [0, n]"); return -2; }
+    if (!bytes) return -3;
+    *bytes = bdg::refine_workspace(n, m);
+    return 0;
+}
+
+int bdg_refine(int64_t n, const double *H, int64_t ldh, const double *lam, double *X, int64_t ldx,
+               int64_t i0, int64_t m, double *W, const bdg_opts *opts, void *work, size_t work_bytes,
+               bdg_err_report *report, bdg_stream_t stream) {
+    if (n < 1) { set_error("bdg_refine: n must be >= 1"); return -1; }
+    if (!H) return -2;
+    if (ldh < n) { set_error("bdg_refine: ldh < n"); return -3; }
+    if (!lam) return -4;
+    if (!X) return -5;
+    if (ldx < n) { set_error("bdg_refine: ldx < n"); return -6; }
+    if (i0 < 0 || i0 > n) { set_error("bdg_refine: i0 must be in [0, n]"); return -7; }
+    if (m < 0 || i0 + m > n) { set_error("bdg_refine: need 0 <= m and i0 + m <= n"); return -8; }
+    if (m > 0 && !W) return -9;
+    if (opts && opts->refine_max_iter < 0) { set_error("bdg_refine: refine_max_iter < 0"); return -10; }
+    const size_t need = bdg::refine_workspace(n, m);
+    if (m > 0 && (!work || work_bytes < need)) {
+        set_error("bdg_refine: workspace %zu < %zu bytes", work_bytes, need);
+        return BDG_ERR_WORKSPACE;
+    }
+    return bdg::refine_pairs(n, H, ldh, lam, X, ldx, i0, m, W, opts, work, report, (hipStream_t)stream);
 }
 
 }  // extern "C"
@@ -246,6 +279,32 @@ int bdg_stage_bt2(int64_t n, int band, int64_t m, const double *e, const double 
     BDG_TRY(bdg::bt2_prepare(n, band, V2, tau2, voff, rest, s));
     BDG_TRY(bdg::bt2_apply_blocks_rm(n, band, m, V2, voff, Zrm, m, rest, s));
     return bdg::rm_to_cm(n, m, Zrm, m, Z, ldz, s);
+}
+
+int bdg_stage_zgemm(int mode, int splitk, char opA, char opB, int64_t M, int64_t N, int64_t K,
+                    const double *alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                    const double *beta, double *C, int64_t ldc, void *work, size_t work_bytes,
+                    bdg_stream_t stream) {
+    if (mode < GEMM_FULL || mode > GEMM_HEMM_L) { set_error("bdg_stage_zgemm: unknown mode %d", mode); return -1; }
+    if (splitk < 1 || splitk > 64) { set_error("bdg_stage_zgemm: splitk must be in [1, 64]"); return -2; }
+    BDG_TRY(check_gemm_args(opA, opB, M, N, K, A, lda, B, ldb, C, ldc, false));
+    const bool na = (opA == 'N' || opA == 'n');
+    if (mode == GEMM_LOWER && (!na || M != N || splitk > 1)) {
+        set_error("bdg_stage_zgemm: lower-tile mode needs opA = 'N', M == N and splitk == 1");
+        return -1;
+    }
+    if (mode == GEMM_HEMM_L && (!na || M != K)) {
+        set_error("bdg_stage_zgemm: HEMM mode needs opA = 'N' and M == K");
+        return -1;
+    }
+    const size_t need = splitk > 1 ? 16 * gemm_split_elems(M, N, splitk) : 0;
+    if (need && (!work || work_bytes < need)) {
+        set_error("bdg_stage_zgemm: workspace %zu < %zu bytes", work_bytes, need);
+        return BDG_ERR_WORKSPACE;
+    }
+    GemmArgs g{M, N, K, alpha[0], alpha[1], beta[0], beta[1], A, lda, B, ldb, C, ldc, mode, splitk,
+               splitk > 1 ? work : nullptr};
+    return gemm<double, true>(opA, opB, g, (hipStream_t)stream);
 }
 
 int bdg_stage_bt1(int64_t n, int64_t m, const double *A, int64_t lda, int band, const double *T1,

@@ -413,6 +413,12 @@ int launch(const GemmArgs &g, hipStream_t s) {
         splitk = (int)((g.K + kchunk - 1) / kchunk);
     }
     if (kchunk <= 0) kchunk = C::BK;
+    if (MODE == GEMM_LOWER && splitk > 1) {
+        // the reduction writes every entry of C, the lower-tile product only
+        // the tiles on and below the diagonal
+        set_error("gemm: the lower-tile mode does not split K");
+        return BDG_ERR_NOT_IMPLEMENTED;
+    }
     GemmArgs h = g;
     h.splitk = splitk;
     dim3 grid;

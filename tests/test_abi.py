@@ -50,3 +50,49 @@ def test_argument_errors_without_gpu():
     assert b"even" in L.bdg_last_error()
     nb = ctypes.c_size_t(0)
     assert L.bdg_eigh_workspace(0, None, ctypes.byref(nb)) == -1
+
+
+def test_refine_argument_errors_without_gpu():
+    from paper_2310_03341_amd import api
+    if not os.path.exists(api.LIB_PATH):
+        pytest.skip("libbdg.so not built")
+    L = api.lib()
+    P = ctypes.c_void_p(256)  # never dereferenced: every call below fails its argument check
+    nb = ctypes.c_size_t(0)
+    assert L.bdg_refine_workspace(10, 11, ctypes.byref(nb)) == -2
+    assert L.bdg_refine_workspace(10, 4, ctypes.byref(nb)) == 0 and nb.value >= 2 * 16 * 10 * 4
+    args = lambda **k: dict(dict(n=10, H=P, ldh=10, lam=P, X=P, ldx=10, i0=0, m=4, W=P), **k)  # noqa: E731
+
+    def call(a):
+        return L.bdg_refine(a["n"], a["H"], a["ldh"], a["lam"], a["X"], a["ldx"], a["i0"], a["m"],
+                            a["W"], None, None, 0, None, None)
+    assert call(args(n=0)) == -1
+    assert call(args(H=None)) == -2
+    assert call(args(ldh=9)) == -3
+    assert call(args(lam=None)) == -4
+    assert call(args(X=None)) == -5
+    assert call(args(ldx=9)) == -6
+    assert call(args(i0=-1)) == -7
+    assert call(args(i0=8, m=3)) == -8
+    assert call(args(W=None)) == -9
+    assert call(args()) == 4  # no workspace: BDG_ERR_WORKSPACE
+    o = api.make_opts(refine_max_iter=-1)
+    assert L.bdg_refine(10, P, 10, P, P, 10, 0, 4, P, ctypes.byref(o), None, 0, None, None) == -10
+
+
+def test_mixed_workspace_fits_largest_window():
+    """The 32^3 ring (n = 65536) with the window [0, 6] (about 25,000 pairs):
+    workspace of the mixed arm sized by max_pairs, plus H and a Z of 26,214
+    columns, stays inside one MI355X's 288 GB (with 8 GB to spare)."""
+    from paper_2310_03341_amd import api
+    if not os.path.exists(api.LIB_PATH):
+        pytest.skip("libbdg.so not built")
+    n, zc = 65536, 26214
+    nb = ctypes.c_size_t(0)
+    o = api.make_opts(precision=api.BDG_FP32_REFINED, ph_mirror=1, max_pairs=zc)
+    assert api.lib().bdg_eigh_workspace(n, ctypes.byref(o), ctypes.byref(nb)) == 0
+    total = nb.value + 16 * n * n + 16 * n * zc
+    assert total <= 280e9, total / 1e9
+    full = api.make_opts(precision=api.BDG_FP32_REFINED, ph_mirror=1)
+    assert api.lib().bdg_eigh_workspace(n, ctypes.byref(full), ctypes.byref(nb)) == 0
+    assert nb.value > total - 16 * n * n - 16 * n * zc

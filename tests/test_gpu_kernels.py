@@ -96,3 +96,76 @@ def test_gemm_matches_reference(dev, kind, opA, opB, shape):
     scale = np.sqrt(K) * 4.0
     tol = (2e-15 if kind != "c" else 2e-6) * scale * 4
     assert np.abs(got - ref).max() < tol * max(1.0, np.abs(ref).max() / np.sqrt(K))
+
+
+def _crand(rng, r, c):
+    return rng.standard_normal((r, c)) + 1j * rng.standard_normal((r, c))
+
+
+@pytest.mark.parametrize("splitk", [1, 2, 3, 7, 64])
+@pytest.mark.parametrize("opA,opB,M,N,K", [("N", "N", 130, 64, 1500), ("C", "N", 64, 64, 2500),
+                                           ("N", "C", 200, 70, 1039)])
+def test_gemm_splitk_full(dev, splitk, opA, opB, M, N, K):
+    """The split-K path of the tile GEMM (partial products per K chunk, then
+    the reduction kernel) that the stage-1 products use at large n."""
+    import torch
+    from paper_2310_03341_amd import api
+    rng = np.random.default_rng(splitk * 7 + M)
+    A = _crand(rng, M, K) if opA == "N" else _crand(rng, K, M)
+    B = _crand(rng, K, N) if opB == "N" else _crand(rng, N, K)
+    C = _crand(rng, M, N)
+    alpha, beta = 0.5 + 0.25j, -0.75 + 0.1j
+    ref = alpha * (_op(A, opA) @ _op(B, opB)) + beta * C
+    dC = to_dev_colmajor(C, dev, ld=M + 5)
+    api.stage_zgemm(0, splitk, opA, opB, to_dev_colmajor(A, dev), to_dev_colmajor(B, dev), dC, alpha, beta)
+    torch.cuda.synchronize()
+    assert np.abs(dC.cpu().numpy() - ref).max() < 1e-13 * np.sqrt(K) * 4
+
+
+@pytest.mark.parametrize("splitk", [1, 4, 13])
+@pytest.mark.parametrize("M,N", [(700, 64), (1100, 130)])
+def test_gemm_splitk_hemm_lower(dev, splitk, M, N):
+    """HEMM from the lower triangle (stage 1's A22 V): the strict upper triangle
+    of A holds 1e30 garbage, which must not enter the product."""
+    import torch
+    from paper_2310_03341_amd import api
+    rng = np.random.default_rng(M + splitk)
+    Hf = _crand(rng, M, M)
+    Hf = Hf + Hf.conj().T
+    A = np.tril(Hf) + np.triu(np.full((M, M), 1e30 - 1e30j), 1)
+    B = _crand(rng, M, N)
+    ref = Hf @ B
+    dC = to_dev_colmajor(np.zeros((M, N), dtype=np.complex128), dev)
+    api.stage_zgemm(2, splitk, "N", "N", to_dev_colmajor(A, dev), to_dev_colmajor(B, dev), dC, 1.0, 0.0)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-13 * np.sqrt(M) * 8
+
+
+def test_gemm_lower_tiles(dev):
+    """Lower-tile mode writes the 64 x 64 tiles on and below the diagonal only;
+    it refuses a split of K."""
+    import torch
+    from paper_2310_03341_amd import api
+    rng = np.random.default_rng(5)
+    M, K = 200, 90
+    A, B = _crand(rng, M, K), _crand(rng, M, K)
+    C = _crand(rng, M, M)
+    ref = -1.0 * (A @ B.conj().T) + C
+    dC = to_dev_colmajor(C, dev)
+    api.stage_zgemm(1, 1, "N", "C", to_dev_colmajor(A, dev), to_dev_colmajor(B, dev), dC, -1.0, 1.0)
+    torch.cuda.synchronize()
+    got = dC.cpu().numpy()
+    I, J = np.meshgrid(np.arange(M) // 64, np.arange(M) // 64, indexing="ij")
+    low = I >= J
+    assert np.abs(got[low] - ref[low]).max() < 1e-13 * 40
+    assert np.abs(got[~low] - C[~low]).max() == 0.0
+    with pytest.raises(api.BdgError):
+        api.stage_zgemm(1, 2, "N", "C", to_dev_colmajor(A, dev), to_dev_colmajor(B, dev), dC, -1.0, 1.0)
+
+
+def test_complex_gemm_refuses_plain_transpose(dev):
+    from paper_2310_03341_amd import api
+    A = to_dev_colmajor(np.eye(4, dtype=np.complex128), dev)
+    with pytest.raises(api.BdgError):
+        api.zgemm("T", "N", A, A, A)

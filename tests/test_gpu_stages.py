@@ -80,8 +80,11 @@ def test_stedc_matches_oracle(dev, name, d, e):
 
 
 # ---------------------------------------------------------------- stage 1
+# n = 1200 and 2048: the panels' products split K over several workgroups
+# (K chunks of >= 512) and sum the partial products in a second kernel
 @pytest.mark.parametrize("kind,n,band", [("rand", 130, 64), ("rand", 300, 32), ("tiny2d", 512, 64),
-                                         ("rand", 97, 16), ("uniform", 128, 64)])
+                                         ("rand", 97, 16), ("uniform", 128, 64), ("rand", 1200, 64),
+                                         ("mid2d", 2048, 64)])
 def test_he2hb_preserves_spectrum(dev, kind, n, band):
     import torch
     from paper_2310_03341_amd import api
@@ -89,6 +92,9 @@ def test_he2hb_preserves_spectrum(dev, kind, n, band):
         H = inputs.random_hermitian(n, seed=n)
     elif kind == "tiny2d":
         H = oracle.assemble_workload(inputs.tiny_2d())
+    elif kind == "mid2d":
+        from tests.test_gpu_large import mid_2d
+        H = oracle.assemble_workload(mid_2d())
     else:
         H = oracle.assemble_workload(inputs.uniform((8, 8), 0.1, 0.3, 1.0))
     A = to_dev_colmajor(H, dev)
@@ -121,7 +127,8 @@ def random_band(n, band, seed):
     return AB
 
 
-@pytest.mark.parametrize("n,band", [(5, 4), (64, 8), (200, 16), (301, 64), (130, 64), (513, 32), (250, 48)])
+@pytest.mark.parametrize("n,band", [(5, 4), (64, 8), (200, 16), (301, 64), (130, 64), (513, 32), (250, 48),
+                                    (2000, 64)])
 def test_hb2st_and_bt2(dev, n, band):
     import torch
     from paper_2310_03341_amd import api
