@@ -140,9 +140,14 @@ def test_net_training_reduces_loss(dev):
 def test_adam_matches_oracle_elementwise(dev):
     """bdg_net_adam_step against Kingma & Ba's update in the oracle (FP64) over
     ten steps.  Gradients span 1e-9 .. 1, so that epsilon (1e-8) decides the
-    smallest updates and its placement is checked too.  Tolerance: the kernel
-    computes in FP32, and 1 - 0.999f^t carries a relative error of about 1.3e-5
-    that the bias-corrected second moment only partly cancels."""
+    smallest updates and its placement is checked too.  Tolerances: the kernel
+    computes in FP32.  The first moment m_t = b1 m + (1 - b1) g sums terms of
+    either sign, so its error is bounded by the terms' size, not by |m_t|:
+    each step rounds three times, so |err_t| <= b1 |err_{t-1}| + 3u a_t with
+    a_t = b1 a_{t-1} + (1 - b1)|g| and u = 2^-24, i.e. |err_t| <= 3 t u a_t.
+    The second moment sums positive terms (relative bound).  1 - 0.999f^t
+    carries a relative error of about 1.3e-5 that the bias-corrected second
+    moment only partly cancels."""
     import torch
     from oracle import net
     from paper_2310_03341_amd import api
@@ -156,6 +161,8 @@ def test_adam_matches_oracle_elementwise(dev):
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)
     ref_p, ref_m, ref_v = [p0.astype(np.float64)], [np.zeros(nparam)], [np.zeros(nparam)]
+    a = np.zeros(nparam)  # running size of the first moment's terms
+    u32 = 2.0 ** -24
     lr = 1e-2
     for t in range(1, 11):
         g = (rng.standard_normal(nparam) * scale).astype(np.float32)
@@ -163,11 +170,12 @@ def test_adam_matches_oracle_elementwise(dev):
         api._call("bdg_net_adam_step", nparam, params.data_ptr(), grads.data_ptr(), m.data_ptr(),
                   v.data_ptr(), t, float(lr), api._stream(dev))
         ref_p = net.adam_step(ref_p, [g.astype(np.float64)], ref_m, ref_v, t, lr=lr)
+        a = 0.9 * a + 0.1 * np.abs(g.astype(np.float64))
         torch.cuda.synchronize()
         gp, gm, gv = params.cpu().numpy(), m.cpu().numpy(), v.cpu().numpy()
         assert np.abs(gm - ref_m[0]).max() <= 1e-6 * np.abs(ref_m[0]).max()
         assert np.all(np.abs(gv - ref_v[0]) <= 3e-5 * ref_v[0] + 1e-38)
-        assert np.all(np.abs(gm - ref_m[0]) <= 1e-5 * np.abs(ref_m[0]) + 1e-45)
+        assert np.all(np.abs(gm - ref_m[0]) <= 3 * t * u32 * a + 1e-45)
         # each step moves a parameter by at most ~lr; FP32 rounding of p itself
         assert np.all(np.abs(gp - ref_p[0]) <= 2e-5 * lr * t + 2e-7 * np.abs(ref_p[0])), t
     del sn
