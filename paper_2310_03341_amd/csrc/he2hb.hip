@@ -379,13 +379,17 @@ int splitk_for(int64_t tiles, int64_t K) {
 
 }  // namespace
 
+// Most K chunks splitk_for gives a product whose K is at most n: the
+// split-K partial buffers are sized for it.
+static int64_t max_splits(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>(64, (n + 511) / 512)); }
+
 size_t he2hb_workspace(int64_t n, int b) {
     const size_t z = 16;
     size_t w = 0;
     w += z * (size_t)n * 2 * b * 2;              // VW, WV
     w += z * (size_t)n * b;                       // Y
     w += z * (size_t)b * b * 3;                   // G, S, M
-    w += z * 64 * (size_t)n * b;                  // split-K partials (upper bound)
+    w += z * max_splits(n) * (size_t)n * b;      // split-K partials (upper bound)
     w += z * 2 * ((size_t)(n / PQ_ROWS + 2) * (b + 1) + b) * 2;  // panel partials + rows
     w += 8 * (size_t)b;                           // tau
     w += 4096;
@@ -416,7 +420,7 @@ int he2hb_t(int64_t n, F *A, int64_t lda, int b, F *AB, int64_t ldab, F *T1,
     F *Gm = take(16 * (size_t)b * b);
     F *Sm = take(16 * (size_t)b * b);
     F *Mm = take(16 * (size_t)b * b);
-    F *part = take(16 * 64 * (size_t)n * b);
+    F *part = take(16 * max_splits(n) * (size_t)n * b);
     const int64_t Gmax = n / PQ_ROWS + 2;
     F *ppart[2], *prow[2];
     ppart[0] = take(16 * (size_t)Gmax * (b + 1));
@@ -614,7 +618,7 @@ int bt1_t(int64_t n, int64_t m, const F *A, int64_t lda, int b, const F *T1, F *
     F *Tg = G + 2 * (size_t)gmax * gmax;            // gb x gb
     F *X = Tg + 2 * (size_t)gmax * gmax;            // gb x b
     F *Vg = X + 2 * (size_t)gmax * b;               // R x gb
-    F *Pk = Vg + 2 * (size_t)n * gmax;              // split-K partials of G (<= 64 gb x gb)
+    F *Pk = Vg + 2 * (size_t)n * gmax;              // split-K partials of G (<= max_splits(n) gb x gb)
     const int ngroups = (np + BT1_GROUP - 1) / BT1_GROUP;
     for (int q = ngroups - 1; q >= 0; --q) {
         const int p0 = q * BT1_GROUP;
@@ -658,7 +662,8 @@ int bt1_t(int64_t n, int64_t m, const F *A, int64_t lda, int b, const F *T1, F *
 
 size_t bt1_workspace(int64_t n, int64_t m, int b) {
     const size_t gb = (size_t)BT1_GROUP * b;
-    return 16 * (2 * gb * (size_t)m + 2 * gb * gb + gb * (size_t)b + gb * (size_t)n + 64 * gb * gb) + 1024;
+    return 16 * (2 * gb * (size_t)m + 2 * gb * gb + gb * (size_t)b + gb * (size_t)n + max_splits(n) * gb * gb) +
+           1024;
 }
 
 }  // namespace bdg
