@@ -143,9 +143,12 @@ def test_adam_matches_oracle_elementwise(dev):
     smallest updates and its placement is checked too.  Tolerances: the kernel
     computes in FP32.  The first moment m_t = b1 m + (1 - b1) g sums terms of
     either sign, so its error is bounded by the terms' size, not by |m_t|:
-    each step rounds three times, so |err_t| <= b1 |err_{t-1}| + 3u a_t with
-    a_t = b1 a_{t-1} + (1 - b1)|g| and u = 2^-24, i.e. |err_t| <= 3 t u a_t.
-    The second moment sums positive terms (relative bound).  1 - 0.999f^t
+    each step rounds three times and uses the FP32 constants b1 = fl(0.9) and
+    fl(1 - fl(0.9)), which differ from 0.9 and 0.1 by the relative amounts
+    d_b and d_c (d_c is about 4u: 1 - fl(0.9) is exact, fl(0.9) is not), so
+    |err_t| <= b1 |err_{t-1}| + (3u + d_b + d_c) a_t with
+    a_t = b1 a_{t-1} + (1 - b1)|g| and u = 2^-24, i.e.
+    |err_t| <= t (3u + d_b + d_c) a_t.  The second moment sums positive terms (relative bound).  1 - 0.999f^t
     carries a relative error of about 1.3e-5 that the bias-corrected second
     moment only partly cancels."""
     import torch
@@ -163,6 +166,10 @@ def test_adam_matches_oracle_elementwise(dev):
     ref_p, ref_m, ref_v = [p0.astype(np.float64)], [np.zeros(nparam)], [np.zeros(nparam)]
     a = np.zeros(nparam)  # running size of the first moment's terms
     u32 = 2.0 ** -24
+    b1f = float(np.float32(0.9))
+    d_b = abs(b1f - 0.9) / 0.9
+    d_c = abs(float(np.float32(1.0) - np.float32(b1f)) - 0.1) / 0.1
+    step_err = 3 * u32 + d_b + d_c
     lr = 1e-2
     for t in range(1, 11):
         g = (rng.standard_normal(nparam) * scale).astype(np.float32)
@@ -175,7 +182,7 @@ def test_adam_matches_oracle_elementwise(dev):
         gp, gm, gv = params.cpu().numpy(), m.cpu().numpy(), v.cpu().numpy()
         assert np.abs(gm - ref_m[0]).max() <= 1e-6 * np.abs(ref_m[0]).max()
         assert np.all(np.abs(gv - ref_v[0]) <= 3e-5 * ref_v[0] + 1e-38)
-        assert np.all(np.abs(gm - ref_m[0]) <= 3 * t * u32 * a + 1e-45)
+        assert np.all(np.abs(gm - ref_m[0]) <= t * step_err * a + 1e-45)
         # each step moves a parameter by at most ~lr; FP32 rounding of p itself
         assert np.all(np.abs(gp - ref_p[0]) <= 2e-5 * lr * t + 2e-7 * np.abs(ref_p[0])), t
     del sn

@@ -6,13 +6,17 @@ inside clusters) on a spectrum with an exactly degenerate triple and pairs
 1e-6 and 1e-9 apart:
 
 * eigenvalues of the step within 1e-13 ||H||_2;
-* columns outside the oracle's clusters element by element within 1e-10.  Two
-  FP64 evaluations of the step that only sum in another order differ by up to
-  4e-12 there (the first-order coefficients divide by gaps down to ~1e-4),
-  while the step itself moves entries by ~1e-7;
-* columns inside a cluster are unique only as a subspace (an exact triple has
-  no preferred basis, the 1e-9 pair is rotated by FP64 rounding), so their
-  orthogonal projectors are compared instead.
+* columns outside the oracle's clusters and outside near-degenerate groups
+  element by element within 1e-10.  Two FP64 evaluations of the step that only
+  sum in another order differ by up to 2e-12 there, while the step itself
+  moves entries by ~1e-7;
+* columns inside a cluster, or in a group of step eigenvalues less than
+  1e-6 ||H||_2 apart, are unique only as a subspace: an exact triple has no
+  preferred basis, and the first-order coefficient of a pair with gap g
+  carries a rounding error of about u ||H||_2 / g (7e-8 for the 1e-9 pair,
+  which the close-pair rule need not flag: its coefficient is small, just not
+  well determined), so their orthogonal projectors are compared instead
+  (agreement ~1e-14 between two such evaluations).
 
 Then the full refinement (default step count) from FP32 must reach the FP64
 targets, checked on the host in numpy, and the mixed-precision eigensolver
@@ -71,14 +75,34 @@ def test_refine_step_matches_oracle(dev, seed, i0, m):
     in_cluster = np.zeros(m, dtype=bool)
     for J in clusters:
         in_cluster[J] = True
-        P = XW[:, J] @ XW[:, J].conj().T
-        Pr = XW_ref[:, J] @ XW_ref[:, J].conj().T
-        assert np.abs(P - Pr).max() <= 1e-10, J
     # the exact triple is a cluster whenever the window holds it
     triple = np.flatnonzero(wtrue == 2.5)
     if np.all((triple >= i0) & (triple < i0 + m)):
         assert in_cluster[triple - i0].all()
-    free = ~in_cluster
+    groups = [J for J in clusters]
+    order = np.argsort(lW_ref, kind="stable")
+    cur = [order[0]]
+    for a, b in zip(order[:-1], order[1:]):
+        if lW_ref[b] - lW_ref[a] <= 1e-6 * normH:
+            cur.append(b)
+            continue
+        if len(cur) > 1:
+            groups.append(np.array(cur))
+        cur = [b]
+    if len(cur) > 1:
+        groups.append(np.array(cur))
+    # merge groups that share a column (a cluster inside a near-degenerate run)
+    label = np.arange(m)
+    for J in groups:
+        label[np.isin(label, label[J])] = label[J[0]]
+    groups = [np.flatnonzero(label == k) for k in np.unique(label) if np.sum(label == k) > 1]
+    grouped = np.zeros(m, dtype=bool)
+    for J in groups:
+        grouped[J] = True
+        P = XW[:, J] @ XW[:, J].conj().T
+        Pr = XW_ref[:, J] @ XW_ref[:, J].conj().T
+        assert np.abs(P - Pr).max() <= 1e-10, J
+    free = ~grouped
     assert np.abs(XW[:, free] - XW_ref[:, free]).max() <= 1e-10
     # the step moved the basis by about the FP32 error
     assert np.abs(XW_ref[:, free] - X[:, cols][:, free]).max() > 1e-9
