@@ -277,6 +277,28 @@ int bdg_net_workspace(const bdg_net_shape *shape, size_t *bytes);
 int bdg_net_forward(const bdg_net_shape *shape, const float *params, const double *Vext,
                     const double *theta, double mu, float *y, void *work, size_t work_bytes,
                     bdg_stream_t stream);
+/*
+ * bdg_net_forward_noalloc -- bdg_net_forward without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP stream capture,
+ * tight inference loops, harnesses that forbid hipMalloc).  Same kernels and
+ * bit-identical output.  Its scratch (the BF16 weights and each layer's
+ * input) lives in a 32 MiB array in the library's device image, one per GPU,
+ * kept until the process ends.  A shape needs
+ *   2 * 9 * (3C + 2C^2 + 2C) + 2 * batch * ny * nx * (3 + 3C)
+ * bytes of it (each of the eight pieces rounded up to 256 bytes; C =
+ * channels), e.g. 3.1 MiB for C = 32 on 64 x 64 at batch 4.  A shape that
+ * needs more than 32 MiB returns BDG_ERR_WORKSPACE before anything is
+ * launched (use bdg_net_forward with a workspace then).
+ * The call uses the scratch of the CURRENT device, which must be the device
+ * of `stream`.  Every call on one GPU shares that array and leaves its
+ * contents behind: calls that overlap on one GPU (two streams, two threads)
+ * race and must be serialised by the caller.  A forward pass writes every
+ * scratch byte before reading it, so nothing needs clearing between calls.
+ * The first call on a device resolves the array's device address once
+ * (hipGetSymbolAddress); no call allocates or frees memory.
+ */
+int bdg_net_forward_noalloc(const bdg_net_shape *shape, const float *params, const double *Vext,
+                            const double *theta, double mu, float *y, bdg_stream_t stream);
 /* grads = d loss / d params, loss (device scalar) = mean((y - target)^2) */
 int bdg_net_backward(const bdg_net_shape *shape, const float *params, const double *Vext,
                      const double *theta, double mu, const float *target, float *grads,

@@ -418,6 +418,7 @@ def _net_sigs(L):
     L.bdg_net_nparams.restype = I64
     L.bdg_net_workspace.argtypes = [SH, ctypes.POINTER(ctypes.c_size_t)]
     L.bdg_net_forward.argtypes = [SH, P, P, P, D, P, P, ctypes.c_size_t, S]
+    L.bdg_net_forward_noalloc.argtypes = [SH, P, P, P, D, P, S]
     L.bdg_net_backward.argtypes = [SH, P, P, P, D, P, P, P, P, ctypes.c_size_t, S]
     L.bdg_net_adam_step.argtypes = [I64, P, P, P, P, ctypes.c_int32, ctypes.c_float, S]
 
@@ -449,6 +450,13 @@ class StartNet:
         y = y if y is not None else torch.empty((B, 2, P), dtype=torch.float32, device=self.device)
         _call("bdg_net_forward", ctypes.byref(self.shape), _dev(self.params), _dev(Vext), _dev(theta),
               float(mu), _dev(y), _dev(self.work), self.work.numel(), _stream(self.device))
+        return y
+
+    def forward_noalloc(self, Vext: torch.Tensor, theta: torch.Tensor, mu: float, y: torch.Tensor):
+        """bdg_net_forward_noalloc: the forward pass on the library's own device
+        scratch (no workspace); y [batch, 2, ny*nx] FP32 is caller-allocated."""
+        _call("bdg_net_forward_noalloc", ctypes.byref(self.shape), _dev(self.params), _dev(Vext), _dev(theta),
+              float(mu), _dev(y), _stream(self.device))
         return y
 
     def backward(self, Vext, theta, mu, target):

@@ -398,6 +398,16 @@ int bdg_net_forward(const bdg_net_shape *shape, const float *params, const doubl
     return bdg::net_forward(shape, params, Vext, theta, mu, y, work, (hipStream_t)stream);
 }
 
+int bdg_net_forward_noalloc(const bdg_net_shape *shape, const float *params, const double *Vext,
+                            const double *theta, double mu, float *y, bdg_stream_t stream) {
+    BDG_TRY(net_shape_ok(shape));
+    if (!params) return -2;
+    if (!Vext) return -3;
+    if (!theta) return -4;
+    if (!y) return -6;
+    return bdg::net_forward_noalloc(shape, params, Vext, theta, mu, y, (hipStream_t)stream);
+}
+
 int bdg_net_backward(const bdg_net_shape *shape, const float *params, const double *Vext,
                      const double *theta, double mu, const float *target, float *grads,
                      float *loss, void *work, size_t work_bytes, bdg_stream_t stream) {

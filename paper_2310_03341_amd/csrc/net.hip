@@ -10,6 +10,8 @@
 // spatially flipped weights; weight and bias gradients are FP32 reductions.
 #include <math.h>
 
+#include <mutex>
+
 #include "net.h"
 
 namespace bdg {
@@ -226,7 +228,7 @@ unsigned blocks_for(int64_t total) {
 
 }  // namespace
 
-NetLayout net_layout(const bdg_net_shape *sh) {
+NetLayout net_layout(const bdg_net_shape *sh, bool forward_only) {
     NetLayout L;
     const int C = sh->channels;
     const int64_t P = (int64_t)sh->ny * sh->nx;
@@ -244,11 +246,17 @@ NetLayout net_layout(const bdg_net_shape *sh) {
     L.nparams = off;
     size_t o = 0;
     auto put = [&](size_t bytes) { size_t r = o; o += (bytes + 255) / 256 * 256; return r; };
-    for (int l = 0; l < 4; ++l) {
-        L.wk[l] = put(2 * (size_t)cout[l] * cin[l] * 9);
-        L.wt[l] = put(2 * (size_t)cout[l] * cin[l] * 9);
-    }
+    for (int l = 0; l < 4; ++l) L.wk[l] = put(2 * (size_t)cout[l] * cin[l] * 9);
     for (int l = 0; l < 4; ++l) L.act[l] = put(2 * (size_t)B * cin[l] * P);  // inputs of layer l (bf16)
+    if (forward_only) {
+        // what a forward pass into a caller-given output touches: the BF16
+        // weights and the layer inputs; the backward buffers are left out
+        for (int l = 0; l < 4; ++l) L.wt[l] = 0;
+        L.y = L.g32 = L.gbf = L.gx32 = L.part = 0;
+        L.total = o;
+        return L;
+    }
+    for (int l = 0; l < 4; ++l) L.wt[l] = put(2 * (size_t)cout[l] * cin[l] * 9);
     L.y = put(4 * (size_t)B * 2 * P);
     L.g32 = put(4 * (size_t)B * C * P);
     L.gbf = put(2 * (size_t)B * C * P);
@@ -260,7 +268,9 @@ NetLayout net_layout(const bdg_net_shape *sh) {
 
 int net_forward(const bdg_net_shape *sh, const float *params, const double *Vext, const double *theta,
                 double mu, float *y_out, void *work, hipStream_t s) {
-    const NetLayout L = net_layout(sh);
+    // with a caller-given output only the forward part of the layout is used;
+    // its offsets are the same in both layouts
+    const NetLayout L = net_layout(sh, y_out != nullptr);
     char *w = (char *)work;
     const int64_t P = (int64_t)sh->ny * sh->nx;
     const int B = sh->batch;
@@ -330,6 +340,65 @@ int net_adam(int64_t np, float *params, const float *grads, float *m, float *v, 
                        eps, c1, c2);
     BDG_CHECK_LAUNCH();
     return 0;
+}
+
+}  // namespace bdg
+
+namespace bdg {
+
+// ---------------------------------------------------------------------------
+// Forward pass without a caller workspace, for callers that cannot allocate
+// device memory (code under stream capture, tight inference loops).  The
+// scratch is one file-scope device array per GPU, held until the process
+// ends; every call on a GPU reuses it, so calls that overlap on one GPU race.
+// A forward pass writes every scratch byte it later reads (BF16 weights, then
+// each layer's input), so nothing has to be cleared between calls.
+namespace {
+
+constexpr size_t NET_SCRATCH_BYTES = size_t(32) << 20;  // 32 MiB
+__device__ __align__(256) unsigned char net_scratch[NET_SCRATCH_BYTES];
+
+constexpr int NET_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NET_MAX_DEVICES] = {};
+
+// Device address of this GPU's scratch array (the host-side name of a
+// __device__ variable is not a device address; the runtime resolves the
+// address once per device, with that device current).
+int scratch_for_current_device(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice", __FILE__, __LINE__);
+    if (dev < 0 || dev >= NET_MAX_DEVICES) {
+        set_error("net_forward_noalloc: device %d beyond the %d supported", dev, NET_MAX_DEVICES);
+        return BDG_ERR_NOT_IMPLEMENTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(net_scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(net_scratch)", __FILE__, __LINE__);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
+}
+
+}  // namespace
+
+size_t net_scratch_capacity() { return NET_SCRATCH_BYTES; }
+
+int net_forward_noalloc(const bdg_net_shape *sh, const float *params, const double *Vext, const double *theta,
+                        double mu, float *y_out, hipStream_t s) {
+    const size_t need = net_layout(sh, true).total;
+    if (need > NET_SCRATCH_BYTES) {
+        set_error("bdg_net_forward_noalloc: the shape needs %zu scratch bytes, more than the %zu available "
+                  "(use bdg_net_forward with a workspace)", need, NET_SCRATCH_BYTES);
+        return BDG_ERR_WORKSPACE;
+    }
+    void *scratch = nullptr;
+    BDG_TRY(scratch_for_current_device(&scratch));
+    return net_forward(sh, params, Vext, theta, mu, y_out, scratch, s);
 }
 
 }  // namespace bdg
