@@ -223,14 +223,28 @@ int bdg_refine(int64_t n, const double *H, int64_t ldh, const double *lam, doubl
 /*
  * Constants of one self-consistency step (the SLDA loop of "Methods").
  *   U' = Vext + B eps_F(n)   (eps_F = pi n in 2D, (3 pi^2 n)^(2/3)/2 in 3D),
- *   |Delta|' = g |nu|        (pairing field Delta = g nu, phase held fixed),
- *   U, |Delta| <- (1 - alpha) old + alpha new,  states with 0 < E < Ec.
+ *   |Delta|' = g_eff |nu|    (pairing field Delta = g_eff nu, phase held fixed),
+ *   U, |Delta| <- (1 - alpha) old + alpha new,  states with 0 < E < Ec,
+ * with the densities of eq. (densities2) at temperature T (Fermi function
+ * f_T(E) = 1/(1 + exp(E/T)); T = 0 is the ground state):
+ *   n = 2 sum (|v|^2 f_T(-E) + |u|^2 f_T(E)),  nu = sum u v^* (f_T(-E) - f_T(E)).
+ * g_eff = g, or with regularize = 1 (3-D lattices only) the cut-off
+ * regularisation of "Density functional theory for superfluid fermions":
+ * g is then the finite coupling and g_eff(r) = 1 / (1/g + Lambda_c(r)),
+ *   Lambda_c = (k_c - (k_0/2) ln((k_c + k_0)/(k_c - k_0))) / (2 pi^2),
+ *   k_c^2 / 2 = Ec + mu - U(r),  k_0^2 / 2 = mu - U(r)
+ * (the principal-value integral of 1/(k^2 - k_0^2) over |k| < k_c; for
+ * mu < U(r) its pole-free form (k_c - kappa atan(k_c/kappa)) / (2 pi^2),
+ * kappa^2 = -k_0^2; zero where k_c^2 <= 0).
  */
 typedef struct {
     double B;     /* coefficient of the density term of U               */
-    double g;     /* pairing coupling                                   */
+    double g;     /* pairing coupling (the finite one with regularize)   */
     double alpha; /* linear mixing weight                               */
     double Ec;    /* energy cutoff (pi^2/2 = k_max^2/2 on the unit grid) */
+    double T;     /* temperature (>= 0)                                  */
+    int32_t regularize; /* 1: cut-off regularisation of g (3-D only)    */
+    int32_t pad;
 } bdg_scf_params;
 
 /* bdg_scf_workspace -- device workspace (bytes) of bdg_scf_step for `lat`. */
@@ -253,6 +267,24 @@ int bdg_scf_step(const bdg_lattice *lat, const double *Vext, const double *theta
                  const bdg_scf_params *params, double *U, double *absDelta, double *density,
                  double *nu_abs, double *change, int64_t *m, void *work, size_t work_bytes,
                  bdg_stream_t stream);
+
+/*
+ * bdg_regrid -- move a real periodic field between the lattices of the
+ * multigrid start ("Performance of the Matrix Diagonalization Algorithm":
+ * the solution on a coarser lattice starts the next finer one).
+ *   src, f   source lattice and field [src sites] (device, f64, x fastest).
+ *   dst, g   target lattice (same ndim) and field [dst sites] (device, f64).
+ *   scale    every output value is multiplied by it (the energy and density
+ *            rescaling between lattices whose unit is the lattice spacing).
+ * dst finer or equal along every axis: trigonometric interpolation of the
+ * samples (fine site x at x N_c / N_f coarse spacings; the Nyquist
+ * coefficient is split evenly between +-N_c/2 so a real field stays real;
+ * cost N_f^d N_c^d operations).  dst coarser along every axis by integer
+ * factors s_d: injection, g(x) = f(s x).  Anything else returns -3.
+ * Dimensions must be even (as for bdg_assemble).  Asynchronous.
+ */
+int bdg_regrid(const bdg_lattice *src, const double *f, const bdg_lattice *dst, double *g, double scale,
+               bdg_stream_t stream);
 
 /*
  * Start-field network of the learned SCF start (an extension of the method:

@@ -16,7 +16,11 @@
  *   - oracle_zhetrd + oracle_tridiag_ql + oracle_zheev_hqr: unblocked
  *     Householder reduction to a real tridiagonal (phase-scaled) followed by
  *     implicit QL with a Wilkinson-type shift (G&VL sec. 8.3), optional
- *     eigenvector accumulation and back-transformation.
+ *     eigenvector accumulation and back-transformation.  The QL iteration is
+ *     the classical formulation of Bowdler, Martin, Reinsch and Wilkinson's
+ *     tql2 (Numer. Math. 11, 1968; Handbook for Automatic Computation II,
+ *     1971): implicit shifted QL sweeps with plane rotations chasing from the
+ *     bottom of each unreduced block, and the same underflow split.
  *   - oracle_sturm_count / oracle_bisect: Sturm-sequence counts and bisection
  *     on a real symmetric tridiagonal (G&VL sec. 8.4).
  *

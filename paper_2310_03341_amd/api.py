@@ -365,7 +365,8 @@ def stage_bt1(A, T1, Z, band: int = 64):
 # ---------------------------------------------------------------- SCF step
 class ScfParamsC(ctypes.Structure):
     _fields_ = [("B", ctypes.c_double), ("g", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("Ec", ctypes.c_double)]
+                ("Ec", ctypes.c_double), ("T", ctypes.c_double), ("regularize", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 def _scf_sigs(L):
@@ -373,6 +374,22 @@ def _scf_sigs(L):
     L.bdg_scf_workspace.argtypes = [ctypes.POINTER(Lattice), ctypes.POINTER(ctypes.c_size_t)]
     L.bdg_scf_step.argtypes = [ctypes.POINTER(Lattice), P, P, D, ctypes.POINTER(ScfParamsC), P, P, P,
                                P, ctypes.POINTER(D), ctypes.POINTER(I64), P, ctypes.c_size_t, S]
+    L.bdg_regrid.argtypes = [ctypes.POINTER(Lattice), P, ctypes.POINTER(Lattice), P, D, S]
+
+
+def regrid(src_dims, f: torch.Tensor, dst_dims, scale: float = 1.0) -> torch.Tensor:
+    """bdg_regrid: the field f on lattice src_dims moved to dst_dims (trigonometric
+    interpolation to a finer lattice, injection to a coarser one), times scale."""
+    L = lib()
+    _scf_sigs(L)
+    src, dst = Lattice(), Lattice()
+    for lat, dims in ((src, src_dims), (dst, dst_dims)):
+        lat.ndim = len(dims)
+        for d, v in enumerate(dims):
+            lat.dims[d] = int(v)
+    g = torch.empty(math.prod(int(v) for v in dst_dims), dtype=torch.float64, device=f.device)
+    _call("bdg_regrid", ctypes.byref(src), _dev(f), ctypes.byref(dst), _dev(g), float(scale), _stream(f.device))
+    return g
 
 
 class ScfStepper:
@@ -386,7 +403,8 @@ class ScfStepper:
         for d, v in enumerate(dims):
             self.lat.dims[d] = int(v)
         self.Vext, self.theta, self.mu = Vext, theta, float(mu)
-        self.p = ScfParamsC(params.B, params.g, params.alpha, params.Ec)
+        self.p = ScfParamsC(params.B, params.g, params.alpha, params.Ec, float(getattr(params, "T", 0.0)),
+                            int(getattr(params, "regularize", 0)), 0)
         nb = ctypes.c_size_t(0)
         _call("bdg_scf_workspace", ctypes.byref(self.lat), ctypes.byref(nb))
         self.work = torch.empty(int(nb.value), dtype=torch.uint8, device=Vext.device)

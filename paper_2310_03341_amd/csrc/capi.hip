@@ -346,8 +346,13 @@ int bdg_scf_step(const bdg_lattice *lat, const double *Vext, const double *theta
     BDG_TRY(lattice_ok(lat, "bdg_scf_step"));
     if (!Vext) return -2;
     if (!theta) return -3;
-    if (!params || !(params->Ec > 0.0) || !(params->alpha > 0.0 && params->alpha <= 1.0)) {
-        set_error("bdg_scf_step: params must have Ec > 0 and 0 < alpha <= 1");
+    if (!params || !(params->Ec > 0.0) || !(params->alpha > 0.0 && params->alpha <= 1.0) ||
+        !(params->T >= 0.0) || (params->regularize != 0 && params->regularize != 1)) {
+        set_error("bdg_scf_step: params must have Ec > 0, 0 < alpha <= 1, T >= 0 and regularize 0 or 1");
+        return -5;
+    }
+    if (params->regularize && (lat->ndim != 3 || !(params->g > 0.0))) {
+        set_error("bdg_scf_step: the cut-off regularisation needs a 3-D lattice and g > 0");
         return -5;
     }
     if (!U) return -6;
@@ -360,6 +365,18 @@ int bdg_scf_step(const bdg_lattice *lat, const double *Vext, const double *theta
     }
     return bdg::scf_step(lat, Vext, theta, mu, params, U, absDelta, density, nu_abs, change, m, work,
                          (hipStream_t)stream);
+}
+
+int bdg_regrid(const bdg_lattice *src, const double *f, const bdg_lattice *dst, double *g, double scale,
+               bdg_stream_t stream) {
+    BDG_TRY(lattice_ok(src, "bdg_regrid"));
+    if (!f) return -2;
+    if (lattice_ok(dst, "bdg_regrid") || dst->ndim != src->ndim) {
+        set_error("bdg_regrid: the target lattice must be valid and have the source's ndim");
+        return -3;
+    }
+    if (!g) return -4;
+    return bdg::regrid(src, f, dst, g, scale, (hipStream_t)stream);
 }
 
 }  // extern "C"

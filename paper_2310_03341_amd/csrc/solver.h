@@ -31,5 +31,7 @@ size_t scf_workspace(const bdg_lattice *lat);
 int scf_step(const bdg_lattice *lat, const double *Vext, const double *theta, double mu,
              const bdg_scf_params *p, double *U, double *absDelta, double *density, double *nu_abs,
              double *change, int64_t *m_out, void *work, hipStream_t s);
+int regrid(const bdg_lattice *src, const double *f, const bdg_lattice *dst, double *g, double scale,
+           hipStream_t s);
 
 }  // namespace bdg

@@ -170,7 +170,7 @@ def line_3d_small(dims=(6, 6, 4), instance: int = 0) -> Workload:
 
 @dataclasses.dataclass(frozen=True)
 class ScfInstance:
-    dims: Tuple[int, int]
+    dims: Tuple[int, ...]
     Vext: np.ndarray      # float64
     theta: np.ndarray     # float64, fixed pairing phase
     mu: float
@@ -203,6 +203,31 @@ def scf_instance(instance: int, dims=(64, 64), mu: float = 1.0) -> ScfInstance:
     for v in range(nv):
         theta += vsign[v] * np.arctan2(y - vpos[v, 1], x - vpos[v, 0])
     return ScfInstance((Nx, Ny), V, theta, mu, seed)
+
+
+def scf_instance_3d(instance: int, dims=(16, 16, 8), mu: float = 1.0) -> ScfInstance:
+    """3-D trap for the regularised / finite-temperature / multigrid SCF: V =
+    0.5 w^2 |r - c|^2 (w ~ U(0.08, 0.16) scaled to a 16-site box) + one
+    Gaussian, and a straight vortex line along z through the centre with
+    random sign (or none)."""
+    seed = 1000 * 6 + instance
+    rng = _rng(seed)
+    Nx, Ny, Nz = dims
+    scale = Nx / 16.0
+    omega = rng.uniform(0.08, 0.16) / scale
+    centre = rng.uniform(0.0, 1.0, size=3) * np.array([Nx, Ny, Nz], dtype=np.float64)
+    width = rng.uniform(1.5, 3.0) * scale
+    amp = rng.uniform(-0.5, 0.5)
+    sign = int(rng.integers(-1, 2))
+    x, y, z = coords(dims)
+    cx, cy, cz = Nx / 2.0, Ny / 2.0, Nz / 2.0
+    V = 0.5 * omega ** 2 * ((x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2)
+    dx = _min_image(x - centre[0], float(Nx))
+    dy = _min_image(y - centre[1], float(Ny))
+    dz = _min_image(z - centre[2], float(Nz))
+    V += amp * np.exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * width ** 2))
+    theta = sign * np.arctan2(y - cy, x - cx)
+    return ScfInstance((Nx, Ny, Nz), V, theta, mu, seed)
 
 
 def random_hermitian(n: int, seed: int) -> np.ndarray:
@@ -244,6 +269,8 @@ class ScfParams:
     test constants, not the paper's (its A, B, C are not printed); g makes the
     uniform 2D gas at mu = 1, U = 0 carry Delta = 0.3 on a 64x64 lattice
     (value written by tests/golden/make_scf_constant.py from the oracle).
+    T is the temperature of the Fermi function in the densities (0 = ground
+    state); regularize = 1 switches on the cut-off regularisation of g (3-D).
     """
     B: float = -0.3
     g: float = 2.356643412040275
@@ -251,3 +278,5 @@ class ScfParams:
     Ec: float = 4.934802200544679   # pi^2 / 2
     tol: float = 1e-6
     max_iter: int = 200
+    T: float = 0.0
+    regularize: int = 0
