@@ -287,6 +287,53 @@ int bdg_regrid(const bdg_lattice *src, const double *f, const bdg_lattice *dst, 
                bdg_stream_t stream);
 
 /*
+ * Time evolution of the quasiparticle wavefunctions, eq. (TDSLDA):
+ *   i d/dt phi_j = H(t) phi_j,  H = [[h, Delta], [Delta^*, -h^*]],  h = -nabla^2/2 + U - mu,
+ * the kinetic term being the same spectral operator as in bdg_assemble.  With
+ * self_consistent = 1 the mean fields follow the evolved states at every
+ * evaluation (zero-temperature occupations, eq. densities2):
+ *   n = 2 sum_j |v_j|^2,  nu = sum_j u_j v_j^*,  U = Vext + B eps_F(n),  Delta = g nu
+ * (the pairing phase evolves freely); with 0 they stay the given U0, Delta0.
+ * Integrator ("Performance of the Time Evolution Algorithm"): fifth-order
+ * Adams-Bashforth-Moulton predictor-corrector, two evaluations of H per step,
+ *   phi* = phi_k + dt (1901 f_k - 2774 f_{k-1} + 2616 f_{k-2} - 1274 f_{k-3} + 251 f_{k-4}) / 720,
+ *   phi_{k+1} = phi_k + dt (251 f(phi*) + 646 f_k - 264 f_{k-1} + 106 f_{k-2} - 19 f_{k-3}) / 720,
+ * f = -i H[phi] phi; the first four steps of a fresh start take classical RK4.
+ */
+typedef struct {
+    double B;                /* density coefficient of U (as in bdg_scf_params)  */
+    double g;                /* pairing coupling, Delta = g nu                    */
+    int32_t self_consistent; /* 1: fields from the evolved states; 0: U0, Delta0  */
+    int32_t resume;          /* 1: continue the history the workspace holds from
+                                the previous call (same lattice, states, dt);
+                                0: fresh start (RK4 for the first four steps)    */
+} bdg_td_params;
+
+/* bdg_td_workspace -- device workspace (bytes) of bdg_td_evolve for m states:
+ * eight n x m complex128 state arrays (five derivatives of the history, the
+ * predictor, one evaluation, one RK4 sum) plus O(n) fields. */
+int bdg_td_workspace(const bdg_lattice *lat, int64_t m, size_t *bytes);
+
+/*
+ * bdg_td_evolve -- advance m states by nsteps steps of size dt.
+ *   lat      lattice with at most 4096 sites (u and v of a state are staged in
+ *            LDS); more returns BDG_ERR_NOT_IMPLEMENTED.
+ *   Vext     [nsites] f64 device (self-consistent fields; may be NULL otherwise).
+ *   mu       chemical potential in h.
+ *   Phi      [ldphi x m] complex128 device, the states [u; v] (n = 2 nsites
+ *            rows), advanced in place.
+ *   U0, Delta0  [nsites] f64 / complex128 device: the fixed fields when
+ *            self_consistent = 0 (may be NULL otherwise).
+ *   work     device workspace of work_bytes >= bdg_td_workspace(lat, m).
+ * Asynchronous (stream-ordered, no host wait) except that resume = 1 reads two
+ * integers of the workspace's history record back first.  A step moves 18
+ * state arrays (16 n m bytes each) through HBM.
+ */
+int bdg_td_evolve(const bdg_lattice *lat, const double *Vext, double mu, const bdg_td_params *params,
+                  int64_t m, double *Phi, int64_t ldphi, double dt, int64_t nsteps, const double *U0,
+                  const double *Delta0, void *work, size_t work_bytes, bdg_stream_t stream);
+
+/*
  * Start-field network of the learned SCF start (an extension of the method:
  * the paper starts its iterations from coarser lattices).  Four periodic 3x3
  * convolution layers, ReLU between them, FP32 master weights, BF16

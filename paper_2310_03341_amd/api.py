@@ -392,6 +392,45 @@ def regrid(src_dims, f: torch.Tensor, dst_dims, scale: float = 1.0) -> torch.Ten
     return g
 
 
+class TdParamsC(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_double), ("g", ctypes.c_double), ("self_consistent", ctypes.c_int32),
+                ("resume", ctypes.c_int32)]
+
+
+class TdEvolver:
+    """Workspace (and so the integrator's history) of bdg_td_evolve for m states
+    on one lattice.  evolve() advances Phi [n x m] (column-major, complex128) in
+    place; the first call starts fresh, later calls continue the history."""
+
+    def __init__(self, dims, m: int, mu: float, B: float = 0.0, g: float = 0.0, Vext=None, U0=None, D0=None,
+                 self_consistent: bool = True, device="cuda"):
+        L = lib()
+        P, I64, D, S = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+        L.bdg_td_workspace.argtypes = [ctypes.POINTER(Lattice), I64, ctypes.POINTER(ctypes.c_size_t)]
+        L.bdg_td_evolve.argtypes = [ctypes.POINTER(Lattice), P, D, ctypes.POINTER(TdParamsC), I64, P, I64, D, I64,
+                                    P, P, P, ctypes.c_size_t, S]
+        self.lat = Lattice()
+        self.lat.ndim = len(dims)
+        for d, v in enumerate(dims):
+            self.lat.dims[d] = int(v)
+        self.m, self.mu = int(m), float(mu)
+        self.p = TdParamsC(float(B), float(g), int(bool(self_consistent)), 0)
+        self.Vext, self.U0, self.D0 = Vext, U0, D0
+        nb = ctypes.c_size_t(0)
+        _call("bdg_td_workspace", ctypes.byref(self.lat), self.m, ctypes.byref(nb))
+        self.work = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
+        self.started = False
+
+    def evolve(self, Phi: torch.Tensor, dt: float, nsteps: int):
+        self.p.resume = 1 if self.started else 0
+        opt = lambda t: _dev(t) if t is not None else None  # noqa: E731
+        _call("bdg_td_evolve", ctypes.byref(self.lat), opt(self.Vext), self.mu, ctypes.byref(self.p), self.m,
+              _dev(Phi), _ld(Phi), float(dt), int(nsteps), opt(self.U0), opt(self.D0), _dev(self.work),
+              self.work.numel(), _stream(Phi.device))
+        self.started = True
+        return Phi
+
+
 class ScfStepper:
     """Workspace + fixed inputs of the SCF step on one lattice (device tensors)."""
 

@@ -1,4 +1,5 @@
 // C-ABI entry points of libbdg.so (declared in include/bdg.h).
+#include <math.h>
 #include <stdlib.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -365,6 +366,46 @@ int bdg_scf_step(const bdg_lattice *lat, const double *Vext, const double *theta
     }
     return bdg::scf_step(lat, Vext, theta, mu, params, U, absDelta, density, nu_abs, change, m, work,
                          (hipStream_t)stream);
+}
+
+int bdg_td_workspace(const bdg_lattice *lat, int64_t m, size_t *bytes) {
+    BDG_TRY(lattice_ok(lat, "bdg_td_workspace"));
+    if (m < 1) return -2;
+    if (!bytes) return -3;
+    *bytes = bdg::td_workspace(lat, m);
+    return 0;
+}
+
+int bdg_td_evolve(const bdg_lattice *lat, const double *Vext, double mu, const bdg_td_params *params,
+                  int64_t m, double *Phi, int64_t ldphi, double dt, int64_t nsteps, const double *U0,
+                  const double *Delta0, void *work, size_t work_bytes, bdg_stream_t stream) {
+    BDG_TRY(lattice_ok(lat, "bdg_td_evolve"));
+    int64_t ns = 1;
+    for (int d = 0; d < lat->ndim; ++d) ns *= lat->dims[d];
+    if (ns > bdg::td_max_sites()) {
+        set_error("bdg_td_evolve: %lld sites, at most %lld (a state's u and v are staged in LDS)",
+                  (long long)ns, (long long)bdg::td_max_sites());
+        return BDG_ERR_NOT_IMPLEMENTED;
+    }
+    if (!params || (params->self_consistent != 0 && params->self_consistent != 1) ||
+        (params->resume != 0 && params->resume != 1)) {
+        set_error("bdg_td_evolve: params must be given, self_consistent and resume 0 or 1");
+        return -4;
+    }
+    if (params->self_consistent && !Vext) return -2;
+    if (m < 1) return -5;
+    if (!Phi) return -6;
+    if (ldphi < 2 * ns) return -7;
+    if (!(dt > 0.0) || !isfinite(dt)) return -8;
+    if (nsteps < 0) return -9;
+    if (!params->self_consistent && !U0) return -10;
+    if (!params->self_consistent && !Delta0) return -11;
+    if (!work || work_bytes < bdg::td_workspace(lat, m)) {
+        set_error("bdg_td_evolve: workspace too small");
+        return BDG_ERR_WORKSPACE;
+    }
+    return bdg::td_evolve(lat, Vext, mu, params, m, Phi, ldphi, dt, nsteps, U0, Delta0, work,
+                          (hipStream_t)stream);
 }
 
 int bdg_regrid(const bdg_lattice *src, const double *f, const bdg_lattice *dst, double *g, double scale,

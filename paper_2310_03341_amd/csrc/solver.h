@@ -33,5 +33,10 @@ int scf_step(const bdg_lattice *lat, const double *Vext, const double *theta, do
              double *change, int64_t *m_out, void *work, hipStream_t s);
 int regrid(const bdg_lattice *src, const double *f, const bdg_lattice *dst, double *g, double scale,
            hipStream_t s);
+size_t td_workspace(const bdg_lattice *lat, int64_t m);
+int64_t td_max_sites();
+int td_evolve(const bdg_lattice *lat, const double *Vext, double mu, const bdg_td_params *p, int64_t m,
+              double *Phi, int64_t ldphi, double dt, int64_t nsteps, const double *U0, const double *D0,
+              void *work, hipStream_t s);
 
 }  // namespace bdg

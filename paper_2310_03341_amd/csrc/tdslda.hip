@@ -1,0 +1,415 @@
+// Time evolution of the quasiparticle wavefunctions, eq. (TDSLDA):
+//   i d/dt phi_j = H(t) phi_j,  H = [[h, Delta], [Delta^*, -h^*]],  h = -nabla^2/2 + U - mu,
+// with the mean fields recomputed from the evolved states at every evaluation
+// (zero-temperature occupations of the time-dependent runs, eq. densities2):
+//   n = 2 sum_j |v_j|^2,  nu = sum_j u_j v_j^*,  U = Vext + B eps_F(n),  Delta = g nu,
+// or held at given (U0, Delta0) when the evolution is not self-consistent.
+//
+// Integrator (sec. "Performance of the Time Evolution Algorithm"): fifth-order
+// Adams-Bashforth-Moulton predictor-corrector with two evaluations of H per
+// step, f = -i H[phi] phi, f_k = f(phi_k):
+//   phi*      = phi_k + dt (1901 f_k - 2774 f_{k-1} + 2616 f_{k-2} - 1274 f_{k-3} + 251 f_{k-4}) / 720
+//   phi_{k+1} = phi_k + dt (251 f(phi*) + 646 f_k - 264 f_{k-1} + 106 f_{k-2} - 19 f_{k-3}) / 720
+// The first four steps (history not yet filled) take classical RK4.
+//
+// Kernels, all bound by HBM traffic of the n x m state arrays:
+//  * td_combine: out = sum_i c_i X_i over up to eight state arrays, with the
+//    density partials of `out` summed in the same pass (one read of every
+//    input, one write);
+//  * td_fields: the partials -> n, nu -> U, Delta on the lattice;
+//  * td_apply: F = -i H X, one workgroup per state: the state's u and v sit in
+//    LDS (up to 4096 sites, 128 KB), the kinetic term is the periodic spectral
+//    second derivative, a circulant matrix along each axis, applied on 2 x 2
+//    site blocks so that every LDS value read feeds two outputs.  The paper
+//    applies the same operator with FFTs; on lattices of at most 64 points
+//    per axis the circulant product is as cheap and needs no transposes.
+// A step moves 18 state arrays through HBM (predictor 6 in / 1 out, two
+// evaluations 1 in / 1 out each, corrector 6 in / 1 out).
+#include <math.h>
+
+#include "solver.h"
+
+namespace bdg {
+namespace {
+
+constexpr int TD_JSPLIT = 32;
+constexpr int TD_MAXK = 8;
+
+struct Comb {
+    const double *X[TD_MAXK];
+    int64_t ld[TD_MAXK];
+    double c[TD_MAXK];
+    int K;
+};
+
+// out[:, j] = sum_i c_i X_i[:, j] for the m states (rows u then v, complex);
+// part[s][r] = (sum |v|^2, re sum u v^*, im sum u v^*) of `out` over slice s of
+// the states.  out may be one of the inputs (each entry is read before it is
+// written by the same thread); out == nullptr computes the partials only of X_0.
+__global__ __launch_bounds__(256) void td_combine(int64_t ns, int64_t m, Comb cb, double *out, int64_t ldo,
+                                                  double *__restrict__ part) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int sl = blockIdx.y;
+    if (r >= ns) return;
+    const int64_t per = (m + TD_JSPLIT - 1) / TD_JSPLIT;
+    const int64_t j0 = sl * per, j1 = min(m, j0 + per);
+    double nn = 0.0, vr = 0.0, vi = 0.0;
+    for (int64_t j = j0; j < j1; ++j) {
+        double ur = 0.0, ui = 0.0, wr = 0.0, wi = 0.0;
+        for (int i = 0; i < cb.K; ++i) {
+            const double2 a = *(const double2 *)(cb.X[i] + 2 * (r + j * cb.ld[i]));
+            const double2 b = *(const double2 *)(cb.X[i] + 2 * (ns + r + j * cb.ld[i]));
+            ur += cb.c[i] * a.x;
+            ui += cb.c[i] * a.y;
+            wr += cb.c[i] * b.x;
+            wi += cb.c[i] * b.y;
+        }
+        if (out) {
+            *(double2 *)(out + 2 * (r + j * ldo)) = make_double2(ur, ui);
+            *(double2 *)(out + 2 * (ns + r + j * ldo)) = make_double2(wr, wi);
+        }
+        nn += wr * wr + wi * wi;
+        vr += ur * wr + ui * wi;  // u conj(v)
+        vi += ui * wr - ur * wi;
+    }
+    if (part) {
+        double *q = part + 3 * (sl * ns + r);
+        q[0] = nn;
+        q[1] = vr;
+        q[2] = vi;
+    }
+}
+
+__device__ inline double td_fermi_energy(double n, int ndim) {
+    n = fmax(n, 0.0);
+    if (ndim == 2) return M_PI * n;
+    if (ndim == 3) return 0.5 * cbrt(3.0 * M_PI * M_PI * n) * cbrt(3.0 * M_PI * M_PI * n);
+    const double kf = 0.5 * M_PI * n;
+    return 0.5 * kf * kf;
+}
+
+// U = Vext + B eps_F(n), Delta = g nu from the partial sums
+__global__ void td_fields(int64_t ns, int ndim, const double *__restrict__ part, const double *__restrict__ Vext,
+                          double B, double g, double *__restrict__ U, double *__restrict__ D) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < ns;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        double nn = 0.0, vr = 0.0, vi = 0.0;
+        for (int s = 0; s < TD_JSPLIT; ++s) {
+            const double *q = part + 3 * (s * ns + r);
+            nn += q[0];
+            vr += q[1];
+            vi += q[2];
+        }
+        U[r] = Vext[r] + B * td_fermi_energy(2.0 * nn, ndim);
+        D[2 * r] = g * vr;
+        D[2 * r + 1] = g * vi;
+    }
+}
+
+// F[:, j] = -i H X[:, j]; one workgroup per state, u and v of the state in LDS.
+// Sites are taken in 2 x 2 blocks (x, y) (2 x 1 on a 1-D lattice).
+template <int MAXS>
+__global__ __launch_bounds__(256) void td_apply(int ndim, int Nx, int Ny, int Nz, const double *__restrict__ X,
+                                                int64_t ldx, const double *__restrict__ U,
+                                                const double *__restrict__ D, double mu, double *__restrict__ F,
+                                                int64_t ldf) {
+    __shared__ double2 sh[2 * MAXS];  // u: [0, ns), v: [ns, 2 ns); the launcher checks ns <= MAXS
+    __shared__ double tab[3][64];
+    const int64_t ns = (int64_t)Nx * Ny * Nz;
+    const int64_t j = blockIdx.x;
+    for (int d = 0; d < 3; ++d) {
+        const int Nd = d == 0 ? Nx : (d == 1 ? Ny : Nz);
+        for (int k = threadIdx.x; k < Nd; k += blockDim.x) {
+            double v;
+            const double pn = M_PI / (double)Nd;
+            if (k == 0) {
+                v = M_PI * M_PI * ((double)Nd * Nd + 2.0) / (6.0 * (double)Nd * Nd);
+            } else {
+                const double sn = sin(pn * (double)k);
+                v = ((k & 1) ? -1.0 : 1.0) * pn * pn / (sn * sn);
+            }
+            tab[d][k] = (d < ndim) ? v : 0.0;
+        }
+    }
+    const double2 *col = (const double2 *)(X + 2 * j * ldx);
+    for (int64_t i = threadIdx.x; i < 2 * ns; i += blockDim.x) sh[i] = col[i];
+    __syncthreads();
+    const int BY = ndim > 1 ? 2 : 1;
+    const int bx = Nx / 2, by = Ny / BY;
+    const int64_t nb = (int64_t)bx * by * Nz;
+    double2 *fcol = (double2 *)(F + 2 * j * ldf);
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        const int x0 = 2 * (int)(b % bx);
+        const int y0 = BY * (int)((b / bx) % by);
+        const int z = (int)(b / ((int64_t)bx * by));
+        double2 acc[2][2][2];  // [component u/v][yy][xx]
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int yy = 0; yy < 2; ++yy)
+#pragma unroll
+                for (int xx = 0; xx < 2; ++xx) acc[c][yy][xx] = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const double2 *s = sh + c * ns;
+            // along x: out(x0 + xx, y0 + yy) += t(x0 + xx - k) s(k, y0 + yy)
+            for (int k = 0; k < Nx; ++k) {
+                const int d0 = x0 - k < 0 ? x0 - k + Nx : x0 - k;
+                const int d1 = d0 + 1 == Nx ? 0 : d0 + 1;
+                const double t0 = tab[0][d0], t1 = tab[0][d1];
+                for (int yy = 0; yy < BY; ++yy) {
+                    const double2 a = s[k + (int64_t)Nx * (y0 + yy + (int64_t)Ny * z)];
+                    acc[c][yy][0].x += t0 * a.x;
+                    acc[c][yy][0].y += t0 * a.y;
+                    acc[c][yy][1].x += t1 * a.x;
+                    acc[c][yy][1].y += t1 * a.y;
+                }
+            }
+            if (ndim > 1) {
+                // along y: out(x0 + xx, y0 + yy) += t(y0 + yy - k) s(x0 + xx, k)
+                for (int k = 0; k < Ny; ++k) {
+                    const int d0 = y0 - k < 0 ? y0 - k + Ny : y0 - k;
+                    const int d1 = d0 + 1 == Ny ? 0 : d0 + 1;
+                    const double t0 = tab[1][d0], t1 = tab[1][d1];
+                    const double2 *row = s + (int64_t)Nx * (k + (int64_t)Ny * z) + x0;
+                    const double2 a0 = row[0], a1 = row[1];
+                    acc[c][0][0].x += t0 * a0.x;
+                    acc[c][0][0].y += t0 * a0.y;
+                    acc[c][0][1].x += t0 * a1.x;
+                    acc[c][0][1].y += t0 * a1.y;
+                    acc[c][1][0].x += t1 * a0.x;
+                    acc[c][1][0].y += t1 * a0.y;
+                    acc[c][1][1].x += t1 * a1.x;
+                    acc[c][1][1].y += t1 * a1.y;
+                }
+            }
+            if (ndim > 2) {
+                // along z: out(x, y, z) += t(z - k) s(x, y, k)
+                for (int k = 0; k < Nz; ++k) {
+                    const int d0 = z - k < 0 ? z - k + Nz : z - k;
+                    const double t0 = tab[2][d0];
+                    for (int yy = 0; yy < BY; ++yy) {
+                        const double2 *row = s + (int64_t)Nx * (y0 + yy + (int64_t)Ny * k) + x0;
+                        const double2 a0 = row[0], a1 = row[1];
+                        acc[c][yy][0].x += t0 * a0.x;
+                        acc[c][yy][0].y += t0 * a0.y;
+                        acc[c][yy][1].x += t0 * a1.x;
+                        acc[c][yy][1].y += t0 * a1.y;
+                    }
+                }
+            }
+        }
+        for (int yy = 0; yy < BY; ++yy) {
+#pragma unroll
+            for (int xx = 0; xx < 2; ++xx) {
+                const int64_t r = x0 + xx + (int64_t)Nx * (y0 + yy + (int64_t)Ny * z);
+                const double2 u = sh[r], v = sh[ns + r];
+                const double w = U[r] - mu;
+                const double2 dl = *(const double2 *)(D + 2 * r);
+                const double2 tu = acc[0][yy][xx], tv = acc[1][yy][xx];
+                // top = T u + (U - mu) u + Delta v;  bottom = Delta^* u - T v - (U - mu) v
+                const double ar = tu.x + w * u.x + (dl.x * v.x - dl.y * v.y);
+                const double ai = tu.y + w * u.y + (dl.x * v.y + dl.y * v.x);
+                const double br = (dl.x * u.x + dl.y * u.y) - tv.x - w * v.x;
+                const double bi = (dl.x * u.y - dl.y * u.x) - tv.y - w * v.y;
+                // f = -i (a + i b) = b - i a
+                fcol[r] = make_double2(ai, -ar);
+                fcol[ns + r] = make_double2(bi, -br);
+            }
+        }
+    }
+}
+
+// Resume state kept at the head of the workspace: [count of valid history
+// entries, ring position of f_k].
+__global__ void td_set_header(int64_t *hdr, int64_t count, int64_t head) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        hdr[0] = count;
+        hdr[1] = head;
+    }
+}
+
+struct TdLayout {
+    size_t hdr, arr[8], part, U, D, total;
+};
+
+TdLayout td_layout(int64_t ns, int64_t m) {
+    TdLayout L;
+    const size_t sa = 16 * (size_t)(2 * ns) * (size_t)m;
+    size_t o = 0;
+    auto put = [&](size_t bytes) { size_t r = o; o += (bytes + 255) / 256 * 256; return r; };
+    L.hdr = put(64);
+    for (int i = 0; i < 8; ++i) L.arr[i] = put(sa);
+    L.part = put(24 * (size_t)ns * TD_JSPLIT);
+    L.U = put(8 * (size_t)ns);
+    L.D = put(16 * (size_t)ns);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+size_t td_workspace(const bdg_lattice *lat, int64_t m) {
+    int64_t ns = 1;
+    for (int d = 0; d < lat->ndim; ++d) ns *= lat->dims[d];
+    return td_layout(ns, m).total;
+}
+
+int64_t td_max_sites() { return 4096; }
+
+int td_evolve(const bdg_lattice *lat, const double *Vext, double mu, const bdg_td_params *p, int64_t m,
+              double *Phi, int64_t ldphi, double dt, int64_t nsteps, const double *U0, const double *D0,
+              void *work, hipStream_t s) {
+    int dims[3] = {1, 1, 1};
+    int64_t ns = 1;
+    for (int d = 0; d < lat->ndim; ++d) {
+        dims[d] = lat->dims[d];
+        ns *= dims[d];
+    }
+    const int64_t n = 2 * ns;
+    const TdLayout L = td_layout(ns, m);
+    char *base = (char *)work;
+    int64_t *hdr = (int64_t *)(base + L.hdr);
+    double *A[8];
+    for (int i = 0; i < 8; ++i) A[i] = (double *)(base + L.arr[i]);
+    double *hist[5] = {A[0], A[1], A[2], A[3], A[4]};
+    double *tmp = A[5], *kb = A[6], *acc = A[7];
+    double *part = (double *)(base + L.part);
+    double *Uw = (double *)(base + L.U);
+    double *Dw = (double *)(base + L.D);
+    const bool sc = p->self_consistent != 0;
+    const double *Uf = sc ? Uw : U0;
+    const double *Df = sc ? Dw : D0;
+    const dim3 cgrid((unsigned)((ns + 255) / 256), TD_JSPLIT);
+    const unsigned fgrid = (unsigned)((ns + 255) / 256 > 1024 ? 1024 : (ns + 255) / 256);
+
+    // out = sum c_i X_i (+ partials, + fields when self-consistent)
+    auto combine = [&](int K, const double *const *X, const int64_t *ld, const double *c, double *out, int64_t ldo,
+                       bool fields) -> int {
+        Comb cb;
+        cb.K = K;
+        for (int i = 0; i < TD_MAXK; ++i) {
+            cb.X[i] = i < K ? X[i] : nullptr;
+            cb.ld[i] = i < K ? ld[i] : 0;
+            cb.c[i] = i < K ? c[i] : 0.0;
+        }
+        const bool dens = fields && sc;
+        hipLaunchKernelGGL(td_combine, cgrid, dim3(256), 0, s, ns, m, cb, out, ldo, dens ? part : (double *)nullptr);
+        if (dens)
+            hipLaunchKernelGGL(td_fields, dim3(fgrid), dim3(256), 0, s, ns, lat->ndim, part, Vext, p->B, p->g, Uw,
+                               Dw);
+        BDG_CHECK_LAUNCH();
+        return 0;
+    };
+    auto apply = [&](const double *X, int64_t ldx, double *Fo) -> int {
+        if (ns <= 1024)
+            hipLaunchKernelGGL(td_apply<1024>, dim3((unsigned)m), dim3(256), 0, s, lat->ndim, dims[0], dims[1],
+                               dims[2], X, ldx, Uf, Df, mu, Fo, n);
+        else
+            hipLaunchKernelGGL(td_apply<4096>, dim3((unsigned)m), dim3(256), 0, s, lat->ndim, dims[0], dims[1],
+                               dims[2], X, ldx, Uf, Df, mu, Fo, n);
+        BDG_CHECK_LAUNCH();
+        return 0;
+    };
+
+    int64_t count = 0, head = 0;  // valid history entries, ring slot of f_k
+    if (p->resume) {
+        int64_t h[2];
+        BDG_HIP(hipMemcpyAsync(h, hdr, sizeof(h), hipMemcpyDeviceToHost, s));
+        BDG_HIP(hipStreamSynchronize(s));
+        count = h[0];
+        head = h[1];
+        if (count < 1 || count > 5 || head < 0 || head > 4) {
+            set_error("bdg_td_evolve: resume requested but the workspace holds no history");
+            return BDG_ERR_WORKSPACE;
+        }
+    }
+    auto slot = [&](int back) { return hist[((head - back) % 5 + 5) % 5]; };  // f_{k - back}
+    if (count == 0) {
+        // f_0 = f(phi_0), with the fields of phi_0 when they follow the states
+        if (sc) {
+            const double *X[1] = {Phi};
+            const int64_t ld[1] = {ldphi};
+            const double c[1] = {1.0};
+            BDG_TRY(combine(1, X, ld, c, nullptr, 0, true));
+        }
+        head = 0;
+        BDG_TRY(apply(Phi, ldphi, hist[0]));
+        count = 1;
+    }
+    for (int64_t step = 0; step < nsteps; ++step) {
+        const double *f0 = slot(0);
+        if (count < 5) {
+            // classical RK4: k1 = f_k;  acc = k1 + 2 k2 + 2 k3 (+ k4 folded into the update)
+            {
+                const double *X[2] = {Phi, f0};
+                const int64_t ld[2] = {ldphi, n};
+                const double c[2] = {1.0, 0.5 * dt};
+                BDG_TRY(combine(2, X, ld, c, tmp, n, true));
+                BDG_TRY(apply(tmp, n, kb));  // k2
+            }
+            {
+                const double *X[2] = {f0, kb};
+                const int64_t ld[2] = {n, n};
+                const double c[2] = {1.0, 2.0};
+                BDG_TRY(combine(2, X, ld, c, acc, n, false));
+            }
+            {
+                const double *X[2] = {Phi, kb};
+                const int64_t ld[2] = {ldphi, n};
+                const double c[2] = {1.0, 0.5 * dt};
+                BDG_TRY(combine(2, X, ld, c, tmp, n, true));
+                BDG_TRY(apply(tmp, n, kb));  // k3
+            }
+            {
+                const double *X[2] = {acc, kb};
+                const int64_t ld[2] = {n, n};
+                const double c[2] = {1.0, 2.0};
+                BDG_TRY(combine(2, X, ld, c, acc, n, false));
+            }
+            {
+                const double *X[2] = {Phi, kb};
+                const int64_t ld[2] = {ldphi, n};
+                const double c[2] = {1.0, dt};
+                BDG_TRY(combine(2, X, ld, c, tmp, n, true));
+                BDG_TRY(apply(tmp, n, kb));  // k4
+            }
+            {
+                const double *X[3] = {Phi, acc, kb};
+                const int64_t ld[3] = {ldphi, n, n};
+                const double c[3] = {1.0, dt / 6.0, dt / 6.0};
+                BDG_TRY(combine(3, X, ld, c, Phi, ldphi, true));
+            }
+        } else {
+            // predictor, evaluation, corrector
+            static const double ab[5] = {1901.0 / 720.0, -2774.0 / 720.0, 2616.0 / 720.0, -1274.0 / 720.0,
+                                         251.0 / 720.0};
+            static const double am[5] = {251.0 / 720.0, 646.0 / 720.0, -264.0 / 720.0, 106.0 / 720.0,
+                                         -19.0 / 720.0};
+            {
+                const double *X[6] = {Phi, slot(0), slot(1), slot(2), slot(3), slot(4)};
+                const int64_t ld[6] = {ldphi, n, n, n, n, n};
+                double c[6] = {1.0};
+                for (int i = 0; i < 5; ++i) c[i + 1] = dt * ab[i];
+                BDG_TRY(combine(6, X, ld, c, tmp, n, true));
+                BDG_TRY(apply(tmp, n, kb));  // f(phi*)
+            }
+            {
+                const double *X[6] = {Phi, kb, slot(0), slot(1), slot(2), slot(3)};
+                const int64_t ld[6] = {ldphi, n, n, n, n, n};
+                double c[6] = {1.0};
+                for (int i = 0; i < 5; ++i) c[i + 1] = dt * am[i];
+                BDG_TRY(combine(6, X, ld, c, Phi, ldphi, true));
+            }
+        }
+        // f_{k+1} = f(phi_{k+1}) into the ring (over f_{k-4} once the ring is full)
+        head = (head + 1) % 5;
+        BDG_TRY(apply(Phi, ldphi, hist[head]));
+        if (count < 5) ++count;
+    }
+    hipLaunchKernelGGL(td_set_header, dim3(1), dim3(64), 0, s, hdr, count, head);
+    BDG_CHECK_LAUNCH();
+    return 0;
+}
+
+}  // namespace bdg

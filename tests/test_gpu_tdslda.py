@@ -1,0 +1,123 @@
+"""bdg_td_evolve (TDSLDA evolution, fifth-order ABM after RK4 start) against
+the oracle's evolution of the same states, element by element."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import tdslda as td
+from paper_2310_03341_amd import inputs
+from tests.gpu_util import need_gpu, to_dev_colmajor
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return need_gpu()
+
+
+def _states(dims, seed, m):
+    """m orthonormal states: eigenvectors of a random-field BdG matrix."""
+    w = inputs.random_field(dims, 4, 1.0, lambda d: inputs.vortex_2d(d, 0.3, 2.0) if len(d) == 2 else
+                            np.full(int(np.prod(d)), 0.2 + 0.1j), seed, "td_states")
+    H = oracle.assemble_workload(w)
+    W, Z = np.linalg.eigh(H)
+    pick = np.argsort(np.abs(W - 0.5))[:m]
+    return Z[:, np.sort(pick)]
+
+
+def _run(dev, dims, Phi0, dt, steps, sc, B=0.0, g=0.0, Vext=None, U0=None, D0=None, ld=None, splits=(None,)):
+    import torch
+    from paper_2310_03341_amd import api
+    n, m = Phi0.shape
+    P = to_dev_colmajor(Phi0, dev, ld=ld)
+    t = lambda a: torch.from_numpy(a).to(dev) if a is not None else None  # noqa: E731
+    ev = api.TdEvolver(dims, m, 1.0, B, g, Vext=t(Vext), U0=t(U0),
+                       D0=t(np.ascontiguousarray(D0).view(np.float64)) if D0 is not None else None,
+                       self_consistent=sc, device=dev)
+    done = 0
+    for k in splits:
+        k = steps - done if k is None else k
+        ev.evolve(P, dt, k)
+        done += k
+    torch.cuda.synchronize()
+    return P.cpu().numpy()
+
+
+@pytest.mark.parametrize("dims", [(8, 8), (16,), (6, 6, 4)])
+def test_frozen_fields_match_oracle(dev, dims):
+    rng = np.random.default_rng(len(dims))
+    ns = int(np.prod(dims))
+    Phi0 = _states(dims, 11 + len(dims), 6)
+    U0 = 0.3 * rng.standard_normal(ns)
+    D0 = 0.2 * (rng.standard_normal(ns) + 1j * rng.standard_normal(ns))
+    dt, steps = 0.01, 12  # four RK4 steps, then eight ABM steps
+    print("frozen %s" % (dims,), flush=True)
+    got = _run(dev, dims, Phi0, dt, steps, False, U0=U0, D0=D0)
+    ref = td.evolve(dims, np.zeros(ns), 1.0, td.TdParams(self_consistent=False), Phi0, dt, steps, U0=U0, D0=D0)
+    assert np.abs(got - ref).max() < 1e-12
+
+
+@pytest.mark.parametrize("instance", [0, 5])
+def test_self_consistent_evolution_matches_oracle(dev, instance):
+    """16x16 trap: states of the window 0 < E < Ec of a trial H, evolved with
+    the fields of eq. (densities2) recomputed at every evaluation."""
+    inst = inputs.scf_instance(instance, dims=(16, 16))
+    p = inputs.ScfParams()
+    ns = inst.Vext.size
+    H = oracle.assemble(inst.dims, inst.Vext, 0.3 * np.exp(1j * inst.theta), inst.mu)
+    W, Z = oracle.eigh(H, np.nextafter(0.0, 1.0), p.Ec)
+    Vq = inst.Vext * 1.1  # a quench of the trap starts the motion
+    dt, steps = 0.004, 20
+    print("self-consistent instance %d, %d states" % (instance, Z.shape[1]), flush=True)
+    got = _run(dev, inst.dims, Z, dt, steps, True, B=p.B, g=p.g, Vext=Vq)
+    ref = td.evolve(inst.dims, Vq, inst.mu, td.TdParams(B=p.B, g=p.g), Z, dt, steps)
+    assert np.abs(got - ref).max() < 1e-11
+    assert np.abs(ref - Z).max() > 1e-4  # the states did move
+    # unitarity of the evolution on the GPU result
+    assert np.abs(got.conj().T @ got - np.eye(Z.shape[1])).max() < 1e-10
+
+
+def test_resume_continues_the_history_exactly(dev):
+    """Twelve steps in one call equal 5 + 7 steps in two calls (same kernels
+    in the same order: bit for bit), with a leading dimension above n."""
+    dims = (8, 8)
+    rng = np.random.default_rng(2)
+    ns = 64
+    Phi0 = _states(dims, 17, 5)
+    Vext = 0.2 * rng.standard_normal(ns)
+    a = _run(dev, dims, Phi0, 0.01, 12, True, B=-0.3, g=2.0, Vext=Vext)
+    b = _run(dev, dims, Phi0, 0.01, 12, True, B=-0.3, g=2.0, Vext=Vext, ld=2 * ns + 6, splits=(5, 7))
+    assert np.array_equal(a, b)
+    ref = td.evolve(dims, Vext, 1.0, td.TdParams(B=-0.3, g=2.0), Phi0, 0.01, 12)
+    assert np.abs(a - ref).max() < 1e-12
+
+
+def test_largest_lattice_matches_oracle(dev):
+    """64 x 64 sites (the LDS limit: u and v of a state take 128 KB)."""
+    dims = (64, 64)
+    rng = np.random.default_rng(9)
+    ns = 4096
+    m = 24
+    A = rng.standard_normal((2 * ns, m)) + 1j * rng.standard_normal((2 * ns, m))
+    Phi0, _ = np.linalg.qr(A)
+    Vext = 0.1 * rng.standard_normal(ns)
+    print("64x64, %d states" % m, flush=True)
+    got = _run(dev, dims, Phi0, 0.004, 8, True, B=-0.3, g=2.0, Vext=Vext)
+    ref = td.evolve(dims, Vext, 1.0, td.TdParams(B=-0.3, g=2.0), Phi0, 0.004, 8)
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_lattice_beyond_lds_is_refused(dev):
+    import torch
+    from paper_2310_03341_amd import api
+    dims = (16, 16, 18)  # 4608 sites
+    ns = 16 * 16 * 18
+    ev = api.TdEvolver(dims, 2, 1.0, self_consistent=True,
+                       Vext=torch.zeros(ns, dtype=torch.float64, device=dev), device=dev)
+    P = api.colmajor(2 * ns, 2, torch.complex128, dev)
+    with pytest.raises(api.BdgError) as e:
+        ev.evolve(P, 0.01, 1)
+    assert e.value.code == 5
