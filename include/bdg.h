@@ -170,6 +170,36 @@ int bdg_eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double
              void *work, size_t work_bytes, bdg_err_report *report, bdg_stream_t stream);
 
 /*
+ * bdg_eigh1_workspace -- device workspace (bytes) of bdg_eigh1 for order n,
+ * element type `real` (1 = real symmetric, 0 = complex Hermitian) and zcols
+ * columns of Z.
+ */
+int bdg_eigh1_workspace(int64_t n, int32_t real, int64_t zcols, size_t *bytes);
+
+/*
+ * bdg_eigh1 -- one-stage FP64 eigensolver: blocked Householder reduction of
+ * the dense matrix straight to real tridiagonal form (panels of 64 columns,
+ * delayed two-sided updates; the trailing matrix is read once per column by a
+ * Hermitian matrix-vector product, the memory-bound half of the work), the
+ * same tridiagonal divide and conquer as bdg_eigh, and one back-
+ * transformation in compact-WY blocks.  This is the solver family the paper
+ * benchmarks (ELPA one-stage, real symmetric; complex Hermitian "about twice
+ * as long", sec. "Performance of the Matrix Diagonalization Algorithm"), next
+ * to the two-stage bdg_eigh.
+ *   real   1: A and Z hold real f64 (symmetric A); 0: complex128 (Hermitian).
+ *   A      [lda x n], lower triangle read; DESTROYED (the reflectors).
+ *   W, Z, zcols, m   as for bdg_eigh (window [emin, emax], ascending).
+ *   report optional: stage_ms[0] tridiagonalisation, [2] divide and
+ *          conquer, [4] back-transformation, [6] window, [7] total.
+ * Synchronises `stream` to read the eigenvalues that decide the window and
+ * returns after all its work has finished.  No particle-hole mirror, no
+ * mixed precision.
+ */
+int bdg_eigh1(int64_t n, int32_t real, double *A, int64_t lda, double emin, double emax, double *W,
+              double *Z, int64_t ldz, int64_t zcols, int64_t *m, void *work, size_t work_bytes,
+              bdg_err_report *report, bdg_stream_t stream);
+
+/*
  * bdg_refine_workspace -- device workspace (bytes) of bdg_refine for order n
  * and m refined columns.
  */

@@ -187,6 +187,31 @@ def eigh(A: torch.Tensor, emin: float = -math.inf, emax: float = math.inf,
     return Solver(A.shape[0], opts, A.device)(A, emin, emax)
 
 
+def eigh1(A: torch.Tensor, emin: float = -math.inf, emax: float = math.inf, W=None, Z=None):
+    """bdg_eigh1, the one-stage solver: real symmetric (float64 A) or complex
+    Hermitian (complex128 A) column-major A, destroyed.  Returns (W, Z, report)."""
+    L = lib()
+    P, I64, D, S = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    L.bdg_eigh1_workspace.argtypes = [I64, ctypes.c_int32, I64, ctypes.POINTER(ctypes.c_size_t)]
+    L.bdg_eigh1.argtypes = [I64, ctypes.c_int32, P, I64, D, D, P, P, I64, I64, ctypes.POINTER(I64), P,
+                            ctypes.c_size_t, ctypes.POINTER(Report), S]
+    n = A.shape[0]
+    real = 1 if A.dtype == torch.float64 else 0
+    if not real and A.dtype != torch.complex128:
+        raise ValueError("A must be float64 (symmetric) or complex128 (Hermitian)")
+    W = W if W is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+    Z = Z if Z is not None else colmajor(n, n, A.dtype, A.device)
+    nb = ctypes.c_size_t(0)
+    _call("bdg_eigh1_workspace", n, real, Z.shape[1], ctypes.byref(nb))
+    work = torch.empty(int(nb.value), dtype=torch.uint8, device=A.device)
+    rep = Report()
+    m = ctypes.c_int64(0)
+    _call("bdg_eigh1", n, real, _dev(A), _ld(A), float(emin), float(emax), _dev(W), _dev(Z), _ld(Z), Z.shape[1],
+          ctypes.byref(m), _dev(work), work.numel(), ctypes.byref(rep), _stream(A.device))
+    k = int(m.value)
+    return W[:k], Z[:, :k], rep
+
+
 def refine_workspace(n: int, m: int) -> int:
     nb = ctypes.c_size_t(0)
     _call("bdg_refine_workspace", int(n), int(m), ctypes.byref(nb))

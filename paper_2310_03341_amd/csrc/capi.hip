@@ -172,6 +172,36 @@ int bdg_eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double
                      (hipStream_t)stream);
 }
 
+int bdg_eigh1_workspace(int64_t n, int32_t real, int64_t zcols, size_t *bytes) {
+    if (n < 1) return -1;
+    if (real != 0 && real != 1) return -2;
+    if (zcols < 0) return -3;
+    if (!bytes) return -4;
+    *bytes = bdg::eigh1_workspace(n, real == 0, zcols);
+    return 0;
+}
+
+int bdg_eigh1(int64_t n, int32_t real, double *A, int64_t lda, double emin, double emax, double *W,
+              double *Z, int64_t ldz, int64_t zcols, int64_t *m, void *work, size_t work_bytes,
+              bdg_err_report *report, bdg_stream_t stream) {
+    if (n < 1) return -1;
+    if (real != 0 && real != 1) return -2;
+    if (!A) return -3;
+    if (lda < n) return -4;
+    if (!(emin <= emax)) return -5;
+    if (!W) return -7;
+    if (!Z) return -8;
+    if (ldz < n) return -9;
+    if (zcols < 0) return -10;
+    if (!m) return -11;
+    if (!work || work_bytes < bdg::eigh1_workspace(n, real == 0, zcols)) {
+        set_error("bdg_eigh1: workspace too small");
+        return BDG_ERR_WORKSPACE;
+    }
+    return bdg::eigh1(n, real == 0, A, lda, emin, emax, W, Z, ldz, zcols, m, work, report,
+                      (hipStream_t)stream);
+}
+
 int bdg_refine_workspace(int64_t n, int64_t m, size_t *bytes) {
     if (n < 1) { set_error("bdg_refine_workspace: n must be >= 1"); return -1; }
     if (m < 0 || m > n) { set_error("bdg_refine_workspace: m must be in [0, n]"); return -2; }

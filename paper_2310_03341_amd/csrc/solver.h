@@ -19,6 +19,9 @@ int eigh_workspace(int64_t n, const bdg_opts *opts, size_t *bytes);
 int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W, double *Z,
          int64_t ldz, int64_t zcols, int64_t *m, const bdg_opts *opts, void *work,
          size_t work_bytes, bdg_err_report *report, hipStream_t s);
+size_t eigh1_workspace(int64_t n, bool cx, int64_t zcols);
+int eigh1(int64_t n, bool cx, double *A, int64_t lda, double emin, double emax, double *W, double *Z,
+          int64_t ldz, int64_t zcols, int64_t *m_out, void *work, bdg_err_report *report, hipStream_t s);
 int refine_pairs(int64_t n, const double *H, int64_t ldh, const double *lam, double *X, int64_t ldx,
                  int64_t i0, int64_t m, double *W, const bdg_opts *opts, void *work,
                  bdg_err_report *report, hipStream_t s);

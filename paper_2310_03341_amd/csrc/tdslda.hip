@@ -107,15 +107,18 @@ __global__ void td_fields(int64_t ns, int ndim, const double *__restrict__ part,
 }
 
 // F[:, j] = -i H X[:, j]; one workgroup per state, u and v of the state in LDS.
-// Sites are taken in 2 x 2 blocks (x, y) (2 x 1 on a 1-D lattice).
-template <int MAXS>
-__global__ __launch_bounds__(256) void td_apply(int ndim, int Nx, int Ny, int Nz, const double *__restrict__ X,
-                                                int64_t ldx, const double *__restrict__ U,
-                                                const double *__restrict__ D, double mu, double *__restrict__ F,
-                                                int64_t ldf) {
+// Sites are taken in BY x 2 blocks (y, x): BY = 2 on 2-D and 3-D lattices, 1
+// on a 1-D one (a compile-time constant, so the accumulators stay in
+// registers).  Circulant coefficients t(x - k) are walked down the table as k
+// goes up (t(-1) = t(N - 1)).
+template <int MAXS, int BY, int NT>
+__global__ __launch_bounds__(NT) void td_apply(int ndim, int Nx, int Ny, int Nz, const double *__restrict__ X,
+                                               int64_t ldx, const double *__restrict__ U,
+                                               const double *__restrict__ D, double mu, double *__restrict__ F,
+                                               int64_t ldf) {
     __shared__ double2 sh[2 * MAXS];  // u: [0, ns), v: [ns, 2 ns); the launcher checks ns <= MAXS
     __shared__ double tab[3][64];
-    const int64_t ns = (int64_t)Nx * Ny * Nz;
+    const int ns = Nx * Ny * Nz;
     const int64_t j = blockIdx.x;
     for (int d = 0; d < 3; ++d) {
         const int Nd = d == 0 ? Nx : (d == 1 ? Ny : Nz);
@@ -132,88 +135,95 @@ __global__ __launch_bounds__(256) void td_apply(int ndim, int Nx, int Ny, int Nz
         }
     }
     const double2 *col = (const double2 *)(X + 2 * j * ldx);
-    for (int64_t i = threadIdx.x; i < 2 * ns; i += blockDim.x) sh[i] = col[i];
+    for (int i = threadIdx.x; i < 2 * ns; i += NT) sh[i] = col[i];
     __syncthreads();
-    const int BY = ndim > 1 ? 2 : 1;
     const int bx = Nx / 2, by = Ny / BY;
-    const int64_t nb = (int64_t)bx * by * Nz;
+    const int nb = bx * by * Nz;
     double2 *fcol = (double2 *)(F + 2 * j * ldf);
-    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x) {
-        const int x0 = 2 * (int)(b % bx);
-        const int y0 = BY * (int)((b / bx) % by);
-        const int z = (int)(b / ((int64_t)bx * by));
-        double2 acc[2][2][2];  // [component u/v][yy][xx]
+    for (int b = threadIdx.x; b < nb; b += NT) {
+        const int x0 = 2 * (b % bx);
+        const int y0 = BY * ((b / bx) % by);
+        const int z = b / (bx * by);
+        double ar[2][BY][2], ai[2][BY][2];  // [component u/v][yy][xx]
 #pragma unroll
         for (int c = 0; c < 2; ++c)
 #pragma unroll
-            for (int yy = 0; yy < 2; ++yy)
+            for (int yy = 0; yy < BY; ++yy)
 #pragma unroll
-                for (int xx = 0; xx < 2; ++xx) acc[c][yy][xx] = make_double2(0.0, 0.0);
+                for (int xx = 0; xx < 2; ++xx) ar[c][yy][xx] = ai[c][yy][xx] = 0.0;
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
             const double2 *s = sh + c * ns;
             // along x: out(x0 + xx, y0 + yy) += t(x0 + xx - k) s(k, y0 + yy)
-            for (int k = 0; k < Nx; ++k) {
-                const int d0 = x0 - k < 0 ? x0 - k + Nx : x0 - k;
-                const int d1 = d0 + 1 == Nx ? 0 : d0 + 1;
-                const double t0 = tab[0][d0], t1 = tab[0][d1];
-                for (int yy = 0; yy < BY; ++yy) {
-                    const double2 a = s[k + (int64_t)Nx * (y0 + yy + (int64_t)Ny * z)];
-                    acc[c][yy][0].x += t0 * a.x;
-                    acc[c][yy][0].y += t0 * a.y;
-                    acc[c][yy][1].x += t1 * a.x;
-                    acc[c][yy][1].y += t1 * a.y;
+            {
+                const double2 *line = s + Nx * (y0 + Ny * z);
+                int d0 = x0;  // (x0 - k) mod Nx at k = 0
+                for (int k = 0; k < Nx; ++k) {
+                    const int d1 = d0 + 1 == Nx ? 0 : d0 + 1;
+                    const double t0 = tab[0][d0], t1 = tab[0][d1];
+#pragma unroll
+                    for (int yy = 0; yy < BY; ++yy) {
+                        const double2 a = line[k + Nx * yy];
+                        ar[c][yy][0] += t0 * a.x;
+                        ai[c][yy][0] += t0 * a.y;
+                        ar[c][yy][1] += t1 * a.x;
+                        ai[c][yy][1] += t1 * a.y;
+                    }
+                    d0 = d0 == 0 ? Nx - 1 : d0 - 1;
                 }
             }
-            if (ndim > 1) {
+            if (BY == 2) {
                 // along y: out(x0 + xx, y0 + yy) += t(y0 + yy - k) s(x0 + xx, k)
+                const double2 *plane = s + Nx * Ny * z + x0;
+                int d0 = y0;
                 for (int k = 0; k < Ny; ++k) {
-                    const int d0 = y0 - k < 0 ? y0 - k + Ny : y0 - k;
                     const int d1 = d0 + 1 == Ny ? 0 : d0 + 1;
                     const double t0 = tab[1][d0], t1 = tab[1][d1];
-                    const double2 *row = s + (int64_t)Nx * (k + (int64_t)Ny * z) + x0;
-                    const double2 a0 = row[0], a1 = row[1];
-                    acc[c][0][0].x += t0 * a0.x;
-                    acc[c][0][0].y += t0 * a0.y;
-                    acc[c][0][1].x += t0 * a1.x;
-                    acc[c][0][1].y += t0 * a1.y;
-                    acc[c][1][0].x += t1 * a0.x;
-                    acc[c][1][0].y += t1 * a0.y;
-                    acc[c][1][1].x += t1 * a1.x;
-                    acc[c][1][1].y += t1 * a1.y;
+                    const double2 a0 = plane[Nx * k], a1 = plane[Nx * k + 1];
+                    ar[c][0][0] += t0 * a0.x;
+                    ai[c][0][0] += t0 * a0.y;
+                    ar[c][0][1] += t0 * a1.x;
+                    ai[c][0][1] += t0 * a1.y;
+                    ar[c][BY - 1][0] += t1 * a0.x;
+                    ai[c][BY - 1][0] += t1 * a0.y;
+                    ar[c][BY - 1][1] += t1 * a1.x;
+                    ai[c][BY - 1][1] += t1 * a1.y;
+                    d0 = d0 == 0 ? Ny - 1 : d0 - 1;
                 }
             }
             if (ndim > 2) {
                 // along z: out(x, y, z) += t(z - k) s(x, y, k)
+                const double2 *colz = s + x0 + Nx * y0;
+                int d0 = z;
                 for (int k = 0; k < Nz; ++k) {
-                    const int d0 = z - k < 0 ? z - k + Nz : z - k;
                     const double t0 = tab[2][d0];
+#pragma unroll
                     for (int yy = 0; yy < BY; ++yy) {
-                        const double2 *row = s + (int64_t)Nx * (y0 + yy + (int64_t)Ny * k) + x0;
-                        const double2 a0 = row[0], a1 = row[1];
-                        acc[c][yy][0].x += t0 * a0.x;
-                        acc[c][yy][0].y += t0 * a0.y;
-                        acc[c][yy][1].x += t0 * a1.x;
-                        acc[c][yy][1].y += t0 * a1.y;
+                        const double2 a0 = colz[Nx * (yy + Ny * k)], a1 = colz[Nx * (yy + Ny * k) + 1];
+                        ar[c][yy][0] += t0 * a0.x;
+                        ai[c][yy][0] += t0 * a0.y;
+                        ar[c][yy][1] += t0 * a1.x;
+                        ai[c][yy][1] += t0 * a1.y;
                     }
+                    d0 = d0 == 0 ? Nz - 1 : d0 - 1;
                 }
             }
         }
+#pragma unroll
         for (int yy = 0; yy < BY; ++yy) {
 #pragma unroll
             for (int xx = 0; xx < 2; ++xx) {
-                const int64_t r = x0 + xx + (int64_t)Nx * (y0 + yy + (int64_t)Ny * z);
+                const int r = x0 + xx + Nx * (y0 + yy + Ny * z);
                 const double2 u = sh[r], v = sh[ns + r];
                 const double w = U[r] - mu;
                 const double2 dl = *(const double2 *)(D + 2 * r);
-                const double2 tu = acc[0][yy][xx], tv = acc[1][yy][xx];
                 // top = T u + (U - mu) u + Delta v;  bottom = Delta^* u - T v - (U - mu) v
-                const double ar = tu.x + w * u.x + (dl.x * v.x - dl.y * v.y);
-                const double ai = tu.y + w * u.y + (dl.x * v.y + dl.y * v.x);
-                const double br = (dl.x * u.x + dl.y * u.y) - tv.x - w * v.x;
-                const double bi = (dl.x * u.y - dl.y * u.x) - tv.y - w * v.y;
+                const double tr = ar[0][yy][xx] + w * u.x + (dl.x * v.x - dl.y * v.y);
+                const double ti = ai[0][yy][xx] + w * u.y + (dl.x * v.y + dl.y * v.x);
+                const double br = (dl.x * u.x + dl.y * u.y) - ar[1][yy][xx] - w * v.x;
+                const double bi = (dl.x * u.y - dl.y * u.x) - ai[1][yy][xx] - w * v.y;
                 // f = -i (a + i b) = b - i a
-                fcol[r] = make_double2(ai, -ar);
+                fcol[r] = make_double2(ti, -tr);
                 fcol[ns + r] = make_double2(bi, -br);
             }
         }
@@ -302,12 +312,19 @@ int td_evolve(const bdg_lattice *lat, const double *Vext, double mu, const bdg_t
         return 0;
     };
     auto apply = [&](const double *X, int64_t ldx, double *Fo) -> int {
-        if (ns <= 1024)
-            hipLaunchKernelGGL(td_apply<1024>, dim3((unsigned)m), dim3(256), 0, s, lat->ndim, dims[0], dims[1],
-                               dims[2], X, ldx, Uf, Df, mu, Fo, n);
-        else
-            hipLaunchKernelGGL(td_apply<4096>, dim3((unsigned)m), dim3(256), 0, s, lat->ndim, dims[0], dims[1],
-                               dims[2], X, ldx, Uf, Df, mu, Fo, n);
+#define BDG_TD_APPLY(MS, BYV, NTV)                                                                       \
+    hipLaunchKernelGGL((td_apply<MS, BYV, NTV>), dim3((unsigned)m), dim3(NTV), 0, s, lat->ndim, dims[0], dims[1], \
+                       dims[2], X, ldx, Uf, Df, mu, Fo, n)
+        // LDS sized for the lattice; 1024 threads (16 waves) hide the LDS
+        // latency when one state fills the CU's LDS
+        if (lat->ndim == 1) {
+            if (ns <= 1024) BDG_TD_APPLY(1024, 1, 256);
+            else BDG_TD_APPLY(4096, 1, 1024);
+        } else {
+            if (ns <= 1024) BDG_TD_APPLY(1024, 2, 256);
+            else BDG_TD_APPLY(4096, 2, 1024);
+        }
+#undef BDG_TD_APPLY
         BDG_CHECK_LAUNCH();
         return 0;
     };

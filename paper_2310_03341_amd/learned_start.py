@@ -71,14 +71,36 @@ def generate(indices: List[int], dims, p, dev, log=None):
     return out
 
 
-def _batch(data, idx, dev):
-    Vext = torch.from_numpy(np.stack([data[i]["inst"].Vext for i in idx])).to(dev)
-    theta = torch.from_numpy(np.stack([data[i]["inst"].theta for i in idx])).to(dev)
-    tgt = np.stack([np.stack([data[i]["U"] - data[i]["inst"].Vext, data[i]["D"]]) for i in idx])
-    return Vext, theta, torch.from_numpy(tgt.astype(np.float32)).to(dev)
+def _d4(a, dims, k, flip):
+    """A field [ny*nx] (x fastest) under a symmetry of the square periodic
+    lattice: k quarter turns, then a reflection of x.  Every lattice symmetry
+    maps a trap to another valid trap and its self-consistent fields to the
+    fields of that trap (the spectral kinetic term is invariant), so the
+    transformed pairs are exact training data."""
+    g = a.reshape(dims[1], dims[0])
+    g = np.rot90(g, k)
+    if flip:
+        g = g[:, ::-1]
+    return np.ascontiguousarray(g).ravel()
 
 
-def train(data, dims, dev, channels=32, batch=8, steps=2000, lr=2e-3, seed=0, log=None):
+def _batch(data, idx, dev, rng=None, dims=None):
+    Vs, ths, tgts = [], [], []
+    for i in idx:
+        V, th = data[i]["inst"].Vext, data[i]["inst"].theta
+        tU, tD = data[i]["U"] - V, data[i]["D"]
+        if rng is not None and dims[0] == dims[1]:
+            k, f = int(rng.integers(0, 4)), bool(rng.integers(0, 2))
+            V, th, tU, tD = (_d4(a, dims, k, f) for a in (V, th, tU, tD))
+        Vs.append(V)
+        ths.append(th)
+        tgts.append(np.stack([tU, tD]))
+    Vext = torch.from_numpy(np.stack(Vs)).to(dev)
+    theta = torch.from_numpy(np.stack(ths)).to(dev)
+    return Vext, theta, torch.from_numpy(np.stack(tgts).astype(np.float32)).to(dev)
+
+
+def train(data, dims, dev, channels=32, batch=8, steps=2000, lr=2e-3, seed=0, log=None, augment=True):
     """Train the start-field network on converged fields; returns the StartNet."""
     from math import sqrt
     Nx, Ny = dims
@@ -96,7 +118,7 @@ def train(data, dims, dev, channels=32, batch=8, steps=2000, lr=2e-3, seed=0, lo
     n = len(data)
     for step in range(steps):
         idx = rng.choice(n, size=batch, replace=n < batch)
-        Vext, theta, tgt = _batch(data, idx, dev)
+        Vext, theta, tgt = _batch(data, idx, dev, rng if augment else None, dims)
         loss = net.backward(Vext, theta, mu, tgt)
         net.adam(lr * (0.1 if step > 0.75 * steps else 1.0))
         if log and (step % 500 == 0 or step == steps - 1):
