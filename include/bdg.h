@@ -462,6 +462,29 @@ int bdg_dgemm(char opA, char opB, int64_t M, int64_t N, int64_t K, double alpha,
               double *C, int64_t ldc, bdg_stream_t stream);
 
 /*
+ * bdg_gemm_int8 -- C = alpha op(A) op(B) + beta C in FP64 (real) or complex128
+ * (cplx = 1), emulated on the INT8 matrix cores: every row of op(A) and
+ * column of op(B) is scaled by a power of two, rounded to 7 slices bits and
+ * cut into `slices` int8 digit slices; the slice products are exact int32
+ * MFMA sums, added in FP64 with their weights (Ozaki, Ogita, Oishi & Rump,
+ * Numer. Algorithms 59 (2012); integer form of Ootomo, Ozaki & Yokota, IJHPCA
+ * 2024).  Error bound per entry: 2^(e_r + e_c) K (128^-S + (S+1) 65^2
+ * 128^-(S+2)) with max|row r of op(A)| < 2^(e_r - 1), max|column c of op(B)|
+ * < 2^(e_c - 1) (complex: real and imaginary parts) -- about 2^-56 2^(e_r +
+ * e_c) K at S = 8.  Complex products use the real embedding (four real
+ * products of M x K x N).
+ *   slices  3 .. 8.   op 'N' or 'C' ('T' for real only).
+ *   alpha, beta host scalars ((re, im) pairs when cplx).
+ *   work    device workspace of bdg_gemm_int8_workspace bytes.
+ * Asynchronous.
+ */
+int bdg_gemm_int8_workspace(int32_t cplx, int64_t M, int64_t N, int64_t K, int32_t slices, size_t *bytes);
+int bdg_gemm_int8(int32_t cplx, int32_t slices, char opA, char opB, int64_t M, int64_t N, int64_t K,
+                  const double *alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                  const double *beta, double *C, int64_t ldc, void *work, size_t work_bytes,
+                  bdg_stream_t stream);
+
+/*
  * Stage hooks (same kernels as bdg_eigh; for tests and per-stage timing).
  * Workspace sizes come from bdg_stage_workspace(stage, n, band):
  * stage 1 = he2hb, 2 = hb2st (none), 3 = stedc, 4 = bt2, 5 = bt1 (per column: m).

@@ -187,6 +187,29 @@ def eigh(A: torch.Tensor, emin: float = -math.inf, emax: float = math.inf,
     return Solver(A.shape[0], opts, A.device)(A, emin, emax)
 
 
+def gemm_int8(opA, opB, A, B, C, alpha=1.0, beta=0.0, slices: int = 8):
+    """bdg_gemm_int8: C = alpha op(A) op(B) + beta C emulated in FP64 on the INT8
+    matrix cores (float64 or complex128 column-major operands)."""
+    L = lib()
+    P, I64, S = ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p
+    L.bdg_gemm_int8_workspace.argtypes = [ctypes.c_int32, I64, I64, I64, ctypes.c_int32,
+                                          ctypes.POINTER(ctypes.c_size_t)]
+    L.bdg_gemm_int8.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_char, ctypes.c_char, I64, I64, I64, P, P,
+                                I64, P, I64, P, P, I64, P, ctypes.c_size_t, S]
+    cplx = 1 if C.dtype == torch.complex128 else 0
+    M, N = C.shape
+    K = A.shape[0] if opA.upper() in ("C", "T") else A.shape[1]
+    nb = ctypes.c_size_t(0)
+    _call("bdg_gemm_int8_workspace", cplx, M, N, K, int(slices), ctypes.byref(nb))
+    work = torch.empty(int(nb.value), dtype=torch.uint8, device=C.device)
+    al = (ctypes.c_double * 2)(complex(alpha).real, complex(alpha).imag)
+    be = (ctypes.c_double * 2)(complex(beta).real, complex(beta).imag)
+    _call("bdg_gemm_int8", cplx, int(slices), opA.encode(), opB.encode(), M, N, K,
+          ctypes.cast(al, ctypes.c_void_p), _dev(A), _ld(A), _dev(B), _ld(B), ctypes.cast(be, ctypes.c_void_p),
+          _dev(C), _ld(C), _dev(work), work.numel(), _stream(C.device))
+    return C
+
+
 def eigh1(A: torch.Tensor, emin: float = -math.inf, emax: float = math.inf, W=None, Z=None):
     """bdg_eigh1, the one-stage solver: real symmetric (float64 A) or complex
     Hermitian (complex128 A) column-major A, destroyed.  Returns (W, Z, report)."""

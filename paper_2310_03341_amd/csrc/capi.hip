@@ -172,6 +172,35 @@ int bdg_eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double
                      (hipStream_t)stream);
 }
 
+int bdg_gemm_int8_workspace(int32_t cplx, int64_t M, int64_t N, int64_t K, int32_t slices, size_t *bytes) {
+    if (cplx != 0 && cplx != 1) return -1;
+    if (M < 0 || N < 0 || K < 0) return -2;
+    if (slices < 3 || slices > 8) return -5;
+    if (!bytes) return -6;
+    *bytes = bdg::ozaki_workspace(cplx == 1, M, N, K, slices);
+    return 0;
+}
+
+int bdg_gemm_int8(int32_t cplx, int32_t slices, char opA, char opB, int64_t M, int64_t N, int64_t K,
+                  const double *alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                  const double *beta, double *C, int64_t ldc, void *work, size_t work_bytes,
+                  bdg_stream_t stream) {
+    if (cplx != 0 && cplx != 1) return -1;
+    if (slices < 3 || slices > 8) {
+        set_error("bdg_gemm_int8: slices must be 3..8");
+        return -2;
+    }
+    BDG_TRY(check_gemm_args(opA, opB, M, N, K, A, lda, B, ldb, C, ldc, cplx == 0));
+    if (!alpha || !beta) return -8;
+    if (M == 0 || N == 0) return 0;
+    if (!work || work_bytes < bdg::ozaki_workspace(cplx == 1, M, N, K, slices)) {
+        set_error("bdg_gemm_int8: workspace too small");
+        return BDG_ERR_WORKSPACE;
+    }
+    return bdg::ozaki_gemm(cplx == 1, slices, opA, opB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, work,
+                           (hipStream_t)stream);
+}
+
 int bdg_eigh1_workspace(int64_t n, int32_t real, int64_t zcols, size_t *bytes) {
     if (n < 1) return -1;
     if (real != 0 && real != 1) return -2;

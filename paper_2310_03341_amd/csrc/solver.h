@@ -19,6 +19,10 @@ int eigh_workspace(int64_t n, const bdg_opts *opts, size_t *bytes);
 int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W, double *Z,
          int64_t ldz, int64_t zcols, int64_t *m, const bdg_opts *opts, void *work,
          size_t work_bytes, bdg_err_report *report, hipStream_t s);
+size_t ozaki_workspace(bool cx, int64_t M, int64_t N, int64_t K, int S);
+int ozaki_gemm(bool cx, int S, char opA, char opB, int64_t M, int64_t N, int64_t K, const double *alpha,
+               const double *A, int64_t lda, const double *B, int64_t ldb, const double *beta, double *C,
+               int64_t ldc, void *work, hipStream_t s);
 size_t eigh1_workspace(int64_t n, bool cx, int64_t zcols);
 int eigh1(int64_t n, bool cx, double *A, int64_t lda, double emin, double emax, double *W, double *Z,
           int64_t ldz, int64_t zcols, int64_t *m_out, void *work, bdg_err_report *report, hipStream_t s);
