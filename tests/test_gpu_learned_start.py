@@ -1,8 +1,12 @@
 """The learned SCF start (network trained by the library's own kernels on
-converged SCF fields) against the uniform start, on small lattices.
+converged SCF fields) against the uniform start, on held-out traps.
 
-The fixed point does not depend on the start, so both starts must converge to
-the same fields; the learned start should need fewer diagonalisations.
+16x16 traps (harmonic + Gaussians, 0-4 vortices), linear mixing 0.9,
+tolerance 1e-6: 24 training traps, augmented by the eight symmetries of the
+square periodic lattice (exact: a symmetry maps a trap and its fixed point to
+another trap and its fixed point), and 8 held-out traps.  The fixed point
+does not depend on the start, so both starts must reach the same fields; the
+learned start must need fewer diagonalisations on the held-out traps.
 """
 import numpy as np
 import pytest
@@ -18,35 +22,28 @@ def dev():
     return need_gpu()
 
 
-def test_learned_start_converges_to_same_fields_in_fewer_iterations(dev):
+def test_learned_start_cuts_iterations_on_held_out_traps(dev):
     from paper_2310_03341_amd import learned_start as ls
-    dims = (12, 12)
-    # linear mixing 0.9: at 0.3 most of these small traps need more than 200
-    # iterations (the slow modes of the fixed-point map sit near 1)
-    p = inputs.ScfParams(tol=1e-6, alpha=0.9, max_iter=300)
+    dims = (16, 16)
+    p = inputs.ScfParams(tol=1e-6, alpha=0.9, max_iter=400)
     # a few traps end in a limit cycle (a level sitting on the window edge
     # flips in and out); only converged fields are training data or test cases
-    train = [d for d in ls.generate(list(range(16)), dims, p, dev) if d["ok"]]
-    test = [d for d in ls.generate(list(range(10000, 10006)), dims, p, dev) if d["ok"]]
-    assert len(train) >= 10 and len(test) >= 3, (len(train), len(test))
-    net = ls.train(train, dims, dev, channels=16, batch=8, steps=1500, lr=3e-3, log=print)
-    seen = ls.evaluate(net, train[:6], p, dev)
+    train = [d for d in ls.generate(list(range(24)), dims, p, dev, print) if d["ok"]]
+    test = [d for d in ls.generate(list(range(10000, 10008)), dims, p, dev, print) if d["ok"]]
+    assert len(train) >= 20 and len(test) >= 6, (len(train), len(test))
+    net = ls.train(train, dims, dev, channels=16, batch=8, steps=3000, lr=3e-3, augment=True)
     held = ls.evaluate(net, test, p, dev)
-    for tag, rows in (("train", seen), ("held-out", held)):
-        for r in rows:
-            print(tag, r)
-    for rows in (seen, held):
-        assert all(r["converged"] for r in rows)
-        # same fixed point from either start: both stop once a step changes the
-        # fields by <= 1e-6; with the slowest contraction near 0.97 per step the
-        # distance left to the fixed point can be ~30 times that
-        assert max(r["l2_dU"] for r in rows) < 1e-4
-        assert max(r["l2_dDelta"] for r in rows) < 1e-4
-    # where the network fits (its own training fields) the start saves
-    # diagonalisations; the held-out mean is reported, not asserted, at this
-    # size (a dozen training traps)
-    iu = np.mean([r["iters_uniform"] for r in seen])
-    il = np.mean([r["iters_learned"] for r in seen])
-    print("mean iterations: train uniform %.1f learned %.1f; held-out uniform %.1f learned %.1f" % (
-        iu, il, np.mean([r["iters_uniform"] for r in held]), np.mean([r["iters_learned"] for r in held])))
+    for r in held:
+        print("held-out", r, flush=True)
+    assert all(r["converged"] for r in held)
+    # same fixed point from either start: both stop once a step changes the
+    # fields by <= 1e-6; with the slowest contraction near 0.97 per step the
+    # distance left to the fixed point can be ~30 times that
+    assert max(r["l2_dU"] for r in held) < 1e-4
+    assert max(r["l2_dDelta"] for r in held) < 1e-4
+    iu = np.mean([r["iters_uniform"] for r in held])
+    il = np.mean([r["iters_learned"] for r in held])
+    better = sum(r["iters_learned"] < r["iters_uniform"] for r in held)
+    print("held-out mean iterations: uniform %.1f, learned %.1f; %d of %d traps improve" % (iu, il, better, len(held)))
     assert il < iu, (il, iu)
+    assert better > len(held) // 2
