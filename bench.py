@@ -90,7 +90,41 @@ def cpu_baseline(budget_s: float = 20.0):
         oracle.eigh_hqr(H, vectors=True)
         dt = time.perf_counter() - t0
     n_s = H.shape[0]
-    return dt, n_s, cores, "x".join(str(v) for v in w.dims)
+    # a second, half-size sample gives the measured exponent of the growth
+    w2 = inputs.line_3d(tuple(max(2, d // 2) if i == 0 else d for i, d in enumerate(w.dims)), instance=0, config=2)
+    H2 = oracle.assemble_workload(w2)
+    t0 = time.perf_counter()
+    oracle.eigh_hqr(H2, vectors=True)
+    dt2 = time.perf_counter() - t0
+    expo = math.log(dt / dt2) / math.log(n_s / H2.shape[0]) if dt2 > 0 else float("nan")
+    fit = "measured growth exponent %.2f between n=%d (%.2f s) and n=%d" % (expo, H2.shape[0], dt2, n_s)
+    return dt, n_s, cores, "x".join(str(v) for v in w.dims), fit
+
+
+def sample_pairs(W, Z, nsample=256, seed=0):
+    """Host copies of sampled eigenpairs (ends of the spectrum, around E = 0,
+    random columns) for the host certification."""
+    import numpy as np
+    import torch
+    n = Z.shape[1]
+    rng = np.random.default_rng(seed)
+    h = n // 2
+    idx = np.unique(np.r_[0, 1, n - 2, n - 1, max(h - 2, 0):min(h + 2, n), rng.choice(n, min(n, nsample), False)])
+    idx = idx[:nsample]
+    return W.cpu().numpy(), idx, Z[:, torch.from_numpy(idx).to(Z.device)].cpu().numpy()
+
+
+def certify_sampled(w, sample):
+    """max_j ||H z_j - w_j z_j|| / max|w| and max |(Z_s^H Z_s - I)| over the
+    sampled columns, in FP64 on the host with the oracle's matrix-free H."""
+    import numpy as np
+
+    import oracle
+    Wh, idx, Zs = sample
+    R = oracle.apply_h(w.dims, w.U, w.Delta, w.mu, Zs) - Zs * Wh[idx]
+    res = float(np.linalg.norm(R, axis=0).max() / np.abs(Wh).max())
+    gram = float(np.abs(Zs.conj().T @ Zs - np.eye(idx.size)).max())
+    return {"columns": int(idx.size), "max_resid": res, "gram_defect": gram}
 
 
 def check_blocked(api, torch, H, W, Z, block=8192):
@@ -213,6 +247,35 @@ def bench_onestage(api, inputs, torch, dev, progress, dims=(24, 24, 24)):
     return out
 
 
+def bench_int8_gemm(api, torch, dev, progress, M=8192, N=8192, K=8192, slices=8, reps=3):
+    """Complex C = A^H B emulated on the INT8 matrix cores (bdg_gemm_int8) next to
+    the FP64 MFMA ZGEMM (bdg_zgemm) on the same operands; rates count 8MNK."""
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+    torch.manual_seed(0)
+    A = api.colmajor(K, M, torch.complex128, dev)
+    A.copy_(torch.randn(K, M, dtype=torch.complex128, device=dev))
+    B = api.colmajor(K, N, torch.complex128, dev)
+    B.copy_(torch.randn(K, N, dtype=torch.complex128, device=dev))
+    C64 = api.colmajor(M, N, torch.complex128, dev)
+    C8 = api.colmajor(M, N, torch.complex128, dev)
+    progress("int8-emulated ZGEMM %dx%dx%d, %d slices" % (M, N, K, slices))
+    t64 = timed(lambda: api.zgemm("C", "N", A, B, C64))
+    t8 = timed(lambda: api.gemm_int8("C", "N", A, B, C8, slices=slices))
+    fl = 8.0 * M * N * K
+    return {"shape": [M, N, K], "slices": slices, "int8_s": round(t8, 4), "fp64_s": round(t64, 4),
+            "int8_tflops_equiv": round(fl / t8 / 1e12, 1), "fp64_tflops": round(fl / t64 / 1e12, 1),
+            "max_rel_diff": float((C8 - C64).abs().max() / C64.abs().max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,13 +289,17 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32+refinement arm")
     ap.add_argument("--window", type=float, nargs=2, default=None, metavar=("EMIN", "EMAX"),
                     help="eigenvalue window (default: all eigenpairs)")
+    ap.add_argument("--max-pairs", type=int, default=0,
+                    help="mixed arm: most eigenpairs the window may hold (sizes the refinement buffers; 0 = n)")
     ap.add_argument("--zcols", type=float, default=1.0,
                     help="columns of Z to allocate, as a fraction of n (a window needs fewer)")
-    ap.add_argument("--no-td", action="store_true", help="skip the TDSLDA evolution measurement")
+    ap.add_argument("--no-td", action="store_true", help="skip the TDSLDA and INT8-GEMM side measurements")
     ap.add_argument("--no-onestage", action="store_true", help="skip the one-stage (real and complex) solves")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy (read 1 GiB, write 1 GiB) before the solves, "
                          "as the reference point for HBM byte counters")
+    ap.add_argument("--only", choices=["tdslda", "onestage", "int8gemm"], default=None,
+                    help="run one side measurement alone and print its JSON (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver is single-GPU; run with --gpus 1",
@@ -247,6 +314,17 @@ def main():
 
     dev = torch.device("cuda:0")
     dims = tuple(args.dims)
+    if args.only:
+        def say(msg):
+            print("[bench] " + msg, file=sys.stderr, flush=True)
+        if args.only == "tdslda":
+            res = bench_tdslda(api, inputs, torch, dev, say)
+        elif args.only == "onestage":
+            res = bench_onestage(api, inputs, torch, dev, say, dims)
+        else:
+            res = bench_int8_gemm(api, torch, dev, say)
+        print(json.dumps({args.only: res}))
+        return
     if dims == (24, 24, 24):
         w = inputs.metric_3d()
     elif dims == (32, 32, 24):
@@ -301,6 +379,8 @@ def main():
         progress("timed step %.2f s" % (rep.stage_ms[7] / 1e3))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    sample64 = sample_pairs(Wk, Zk) if not args.no_cpu else None
+    sample_mixed = None
     m = Wk.numel()
     ms_step = 1e3 * wall / args.steps
     t_solve = sum(t_eigh) / len(t_eigh)
@@ -351,7 +431,7 @@ def main():
         W64 = Wk.clone()
         del solver
         torch.cuda.empty_cache()
-        mopts = api.make_opts(precision=api.BDG_FP32_REFINED, ph_mirror=ph)
+        mopts = api.make_opts(precision=api.BDG_FP32_REFINED, ph_mirror=ph, max_pairs=args.max_pairs)
         msolver = api.Solver(n, mopts, dev)
         api.assemble(w.dims, U, D, w.mu, out=H)
         torch.cuda.synchronize()
@@ -360,6 +440,8 @@ def main():
         torch.cuda.synchronize()
         tm = time.perf_counter() - t0
         rep = msolver.report
+        if not args.no_cpu:
+            sample_mixed = sample_pairs(Wm, Zm)
         mixed = {"time_s": round(rep.stage_ms[7] / 1e3, 4), "wall_s": round(tm, 3),
                  "refine_iters": rep.refine_iters, "refine_defect": rep.max_resid,
                  "close_pairs_step1": rep.refine_close_pairs, "clustered_cols_step1": rep.refine_cluster_cols,
@@ -378,6 +460,8 @@ def main():
         del msolver
     if not args.no_td:
         out["tdslda"] = bench_tdslda(api, inputs, torch, dev, progress)
+    if not args.no_td:
+        out["int8_gemm"] = bench_int8_gemm(api, torch, dev, progress)
     if not args.no_onestage:
         del H
         torch.cuda.empty_cache()
@@ -385,13 +469,19 @@ def main():
         out["one_stage"]["two_stage_complex_s"] = out["value"]
     if not args.no_cpu:
         progress("CPU oracle baseline")
-        dt, n_s, cores, sdims = cpu_baseline()
+        dt, n_s, cores, sdims, fit = cpu_baseline()
         scale = (n / n_s) ** 3
         out["cpu_baseline"] = {"value": round(dt * scale, 1), "unit": "s", "cores": cores,
                                "kind": "oracle",
                                "sample": "oracle Householder+QL, all eigenpairs, %s lattice "
-                                         "(n=%d) in %.1f s, scaled by (n/%d)^3" % (sdims, n_s, dt, n_s),
+                                         "(n=%d) in %.1f s, scaled by (n/%d)^3; %s" % (sdims, n_s, dt, n_s, fit),
                                "cpu": cpu_model()}
+        # FP64 certification of sampled eigenpairs of the timed solve on the
+        # host: residuals with the oracle's matrix-free H, Gram matrix in numpy
+        progress("host FP64 certification of sampled eigenpairs")
+        out["cpu_certification"] = {"fp64": certify_sampled(w, sample64)}
+        if sample_mixed is not None:
+            out["cpu_certification"]["mixed_refined"] = certify_sampled(w, sample_mixed)
     print(json.dumps(out))
 
 

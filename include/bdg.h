@@ -412,6 +412,11 @@ int bdg_net_forward_noalloc(const bdg_net_shape *shape, const float *params, con
 int bdg_net_backward(const bdg_net_shape *shape, const float *params, const double *Vext,
                      const double *theta, double mu, const float *target, float *grads,
                      float *loss, void *work, size_t work_bytes, bdg_stream_t stream);
+/* Start fields of the SCF from output sample `sample` of y (as bdg_net_forward
+ * writes it): U = Vext + y[sample][0], |Delta| = max(y[sample][1], 0), f64 on
+ * the lattice (Vext, U, absDelta [ny*nx] device). */
+int bdg_net_start_fields(const bdg_net_shape *shape, const float *y, int32_t sample, const double *Vext,
+                         double *U, double *absDelta, bdg_stream_t stream);
 /* Adam (Kingma & Ba) on the FP32 master weights; t is the 1-based step count. */
 int bdg_net_adam_step(int64_t nparams, float *params, const float *grads, float *m, float *v,
                       int32_t t, float lr, bdg_stream_t stream);

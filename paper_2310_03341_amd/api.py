@@ -526,6 +526,7 @@ def _net_sigs(L):
     L.bdg_net_forward_noalloc.argtypes = [SH, P, P, P, D, P, S]
     L.bdg_net_backward.argtypes = [SH, P, P, P, D, P, P, P, P, ctypes.c_size_t, S]
     L.bdg_net_adam_step.argtypes = [I64, P, P, P, P, ctypes.c_int32, ctypes.c_float, S]
+    L.bdg_net_start_fields.argtypes = [SH, P, ctypes.c_int32, P, P, P, S]
 
 
 class StartNet:
@@ -563,6 +564,14 @@ class StartNet:
         _call("bdg_net_forward_noalloc", ctypes.byref(self.shape), _dev(self.params), _dev(Vext), _dev(theta),
               float(mu), _dev(y), _stream(self.device))
         return y
+
+    def start_fields(self, y: torch.Tensor, sample: int, Vext: torch.Tensor):
+        """bdg_net_start_fields: (U, |Delta|) of output sample `sample` of y."""
+        U = torch.empty_like(Vext)
+        D = torch.empty_like(Vext)
+        _call("bdg_net_start_fields", ctypes.byref(self.shape), _dev(y), int(sample), _dev(Vext), _dev(U), _dev(D),
+              _stream(self.device))
+        return U, D
 
     def backward(self, Vext, theta, mu, target):
         _call("bdg_net_backward", ctypes.byref(self.shape), _dev(self.params), _dev(Vext), _dev(theta),

@@ -540,6 +540,17 @@ int bdg_net_backward(const bdg_net_shape *shape, const float *params, const doub
                              (hipStream_t)stream);
 }
 
+int bdg_net_start_fields(const bdg_net_shape *shape, const float *y, int32_t sample, const double *Vext,
+                         double *U, double *absDelta, bdg_stream_t stream) {
+    BDG_TRY(net_shape_ok(shape));
+    if (!y) return -2;
+    if (sample < 0 || sample >= shape->batch) return -3;
+    if (!Vext) return -4;
+    if (!U) return -5;
+    if (!absDelta) return -6;
+    return bdg::net_start_fields(shape, y, sample, Vext, U, absDelta, (hipStream_t)stream);
+}
+
 int bdg_net_adam_step(int64_t nparams, float *params, const float *grads, float *m, float *v,
                       int32_t t, float lr, bdg_stream_t stream) {
     if (nparams < 1) return -1;

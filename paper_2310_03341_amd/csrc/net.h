@@ -18,6 +18,8 @@ int net_forward_noalloc(const bdg_net_shape *sh, const float *params, const doub
 size_t net_scratch_capacity();
 int net_backward(const bdg_net_shape *sh, const float *params, const double *Vext, const double *theta,
                  double mu, const float *target, float *grads, float *loss, void *work, hipStream_t s);
+int net_start_fields(const bdg_net_shape *sh, const float *y, int sample, const double *Vext, double *U, double *D,
+                     hipStream_t s);
 int net_adam(int64_t np, float *params, const float *grads, float *m, float *v, int t, float lr,
              hipStream_t s);
 

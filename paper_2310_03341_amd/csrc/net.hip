@@ -221,6 +221,16 @@ __global__ void adam_kernel(int64_t np, float *__restrict__ p, const float *__re
     }
 }
 
+// start fields of the SCF from the network output of one sample:
+// U = Vext + y[0], |Delta| = max(y[1], 0)
+__global__ void start_fields_kernel(int64_t P, const float *__restrict__ y, const double *__restrict__ Vext,
+                                   double *__restrict__ U, double *__restrict__ D) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P; p += (int64_t)gridDim.x * blockDim.x) {
+        U[p] = Vext[p] + (double)y[p];
+        D[p] = fmax((double)y[P + p], 0.0);
+    }
+}
+
 unsigned blocks_for(int64_t total) {
     int64_t g = (total + 255) / 256;
     return (unsigned)(g > 2048 ? 2048 : (g < 1 ? 1 : g));
@@ -328,6 +338,15 @@ int net_backward(const bdg_net_shape *sh, const float *params, const double *Vex
         hipLaunchKernelGGL(relu_back, dim3(blocks_for((int64_t)B * L.cin[l] * P)), dim3(256), 0, s,
                            (int)(B * L.cin[l] * P), gx32, (const unsigned short *)(w + L.act[l]), g32, gbf);
     }
+    BDG_CHECK_LAUNCH();
+    return 0;
+}
+
+int net_start_fields(const bdg_net_shape *sh, const float *y, int sample, const double *Vext, double *U, double *D,
+                     hipStream_t s) {
+    const int64_t P = (int64_t)sh->ny * sh->nx;
+    hipLaunchKernelGGL(start_fields_kernel, dim3(blocks_for(P)), dim3(256), 0, s, P, y + (int64_t)sample * 2 * P, Vext,
+                       U, D);
     BDG_CHECK_LAUNCH();
     return 0;
 }

@@ -130,10 +130,8 @@ def predict_start(net: api.StartNet, inst, dev):
     B = net.shape.batch
     Vext = torch.from_numpy(np.stack([inst.Vext] * B)).to(dev)
     theta = torch.from_numpy(np.stack([inst.theta] * B)).to(dev)
-    y = net.forward(Vext, theta, inst.mu)[0].double()
-    U = torch.from_numpy(inst.Vext).to(dev) + y[0]
-    D = torch.clamp(y[1], min=0.0).contiguous()
-    return U.contiguous(), D
+    y = net.forward(Vext, theta, inst.mu)
+    return net.start_fields(y, 0, torch.from_numpy(inst.Vext).to(dev))
 
 
 def evaluate(net, test, p, dev, log=None):

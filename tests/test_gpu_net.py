@@ -186,3 +186,21 @@ def test_adam_matches_oracle_elementwise(dev):
         # each step moves a parameter by at most ~lr; FP32 rounding of p itself
         assert np.all(np.abs(gp - ref_p[0]) <= 2e-5 * lr * t + 2e-7 * np.abs(ref_p[0])), t
     del sn
+
+
+def test_start_fields_decode(dev):
+    """bdg_net_start_fields: U = Vext + y[0], |Delta| = max(y[1], 0) of one sample."""
+    import torch
+    from paper_2310_03341_amd import api
+    rng = np.random.default_rng(3)
+    C, ny, nx, B = 8, 10, 12, 3
+    sn = api.StartNet(C, ny, nx, B, dev)
+    y = torch.from_numpy(rng.standard_normal((B, 2, ny * nx)).astype(np.float32)).to(dev)
+    Vext = rng.uniform(0, 2, ny * nx)
+    U, D = sn.start_fields(y, 2, torch.from_numpy(Vext).to(dev))
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy().astype(np.float64)
+    assert np.array_equal(U.cpu().numpy(), Vext + yh[2, 0])
+    assert np.array_equal(D.cpu().numpy(), np.maximum(yh[2, 1], 0.0))
+    with pytest.raises(api.BdgError):
+        sn.start_fields(y, 3, torch.from_numpy(Vext).to(dev))
