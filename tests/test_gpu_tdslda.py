@@ -110,6 +110,22 @@ def test_largest_lattice_matches_oracle(dev):
     assert np.abs(got - ref).max() < 1e-12
 
 
+@pytest.mark.parametrize("dims", [(16, 8, 10), (12, 12, 12), (32, 36)])
+def test_large_lattices_match_oracle(dev, dims):
+    """Lattices above 1024 sites (the 4096-site LDS variant of the apply kernel)
+    with odd and unequal sides; self-consistent fields, RK4 start + ABM."""
+    rng = np.random.default_rng(sum(dims))
+    ns = int(np.prod(dims))
+    m = 12
+    A = rng.standard_normal((2 * ns, m)) + 1j * rng.standard_normal((2 * ns, m))
+    Phi0, _ = np.linalg.qr(A)
+    Vext = 0.1 * rng.standard_normal(ns)
+    print("large lattice %s, %d states" % (dims, m), flush=True)
+    got = _run(dev, dims, Phi0, 0.004, 7, True, B=-0.3, g=2.0, Vext=Vext)
+    ref = td.evolve(dims, Vext, 1.0, td.TdParams(B=-0.3, g=2.0), Phi0, 0.004, 7)
+    assert np.abs(got - ref).max() < 1e-12
+
+
 def test_lattice_beyond_lds_is_refused(dev):
     import torch
     from paper_2310_03341_amd import api
