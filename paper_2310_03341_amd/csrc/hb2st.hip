@@ -41,21 +41,38 @@ __host__ __device__ inline int64_t sweep_offset(int64_t n, int b, int64_t s) {
     return s + P(n - 2) - P(n - 2 - s);
 }
 
-// One task per workgroup; BT (16, 32 or 64) bounds the band width b so that
-// every loop has a fixed trip count.  All global loads are issued at once,
-// the reflector scalars are computed by every thread (no broadcast step), and
-// the task takes four block barriers.
-template <typename F, int BT>
-__global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restrict__ AB, int64_t ldab,
-                                                  F *__restrict__ V2, F *__restrict__ tau2, int64_t g,
-                                                  int64_t s_lo) {
+// Sum over each group of G consecutive lanes (G = 4, 8 or 16), to all of them.
+template <int G, typename T>
+__device__ inline T group_sum(T v) {
+    v = dpp_fold<0xB1, 0xf>(v);                   // quad_perm [1, 0, 3, 2]
+    v = dpp_fold<0x4E, 0xf>(v);                   // quad_perm [2, 3, 0, 1]
+    if (G >= 8) v = dpp_fold<0x141, 0xf>(v);      // row_half_mirror
+    if (G == 16) v = dpp_fold<0x140, 0xf>(v);     // row_mirror
+    return v;
+}
+
+// One task per workgroup of NT threads; BT (16, 32 or 64) bounds the band
+// width b so that every loop has a fixed trip count.  All global loads are
+// issued at once, the reflector scalars are computed by every thread (no
+// broadcast step), and the task takes four block barriers.  A task is a chain
+// of dependent latencies (loads, two matrix-vector products, the update and
+// its stores) that no other task can hide: at band 64, 512 threads (eight
+// elements each) take 10 % less time per step than 256, and 1024 threads
+// take 4 % more than 256.
+template <typename F, int BT, int NT>
+__global__ __launch_bounds__(NT) void hb2st_step(int64_t n, int b, F *__restrict__ AB, int64_t ldab,
+                                                 F *__restrict__ V2, F *__restrict__ tau2, int64_t g,
+                                                 int64_t s_lo) {
     typedef typename v2t<F>::type CV;
-    constexpr int NE = BT * BT / 256;  // matrix elements per thread
+    constexpr int NE = BT * BT / NT;  // matrix elements per thread
+    constexpr int NW = NT / 64;       // waves
+    constexpr int TPR = NT / 64;      // threads per row in the matrix-vector products
+    static_assert(NE >= 1 && BT % TPR == 0 && (TPR == 4 || TPR == 8 || TPR == 16), "hb2st: tile shape");
     constexpr int LD = BT + 1;
     __shared__ CV Bs[BT * LD];
     __shared__ CV Ds[BT * LD];
     __shared__ CV vp[BT], xv[BT], vn[BT], yv[BT], pv[BT], wb[BT];
-    __shared__ F red[4][4];
+    __shared__ F red[NW][4];
     const int64_t s = s_lo + blockIdx.x;
     const int64_t t = g - LAG * s;
     if (s > n - 3 || t < 0) return;
@@ -78,7 +95,7 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
         unsigned okb = 0, okd = 0;
 #pragma unroll
         for (int i = 0; i < NE; ++i) {
-            const int e = tid + 256 * i;
+            const int e = tid + NT * i;
             const int r = e % BT, c = e / BT;
             const bool ob = (t > 0) & (r < Lr) & (c < b);
             const bool od = (r < Lr) & (c < Lr);
@@ -96,7 +113,7 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
         const F tp0 = tau2[t > 0 ? ridx - 1 : 0];
 #pragma unroll
         for (int i = 0; i < NE; ++i) {
-            const int e = tid + 256 * i;
+            const int e = tid + NT * i;
             const int r = e % BT, c = e / BT;
             if (!((okb >> i) & 1u)) rb[i] = zero;
             if (!((okd >> i) & 1u)) rd[i] = zero;
@@ -114,21 +131,21 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
 
     // ---- phase 1: y = tp B vp and the first bulge column x = B[:, 0] - y
     // (vp_0 = 1) for t > 0; quads of threads per row.
-    const int qr = tid >> 2, q = tid & 3;
+    const int qr = tid / TPR, q = tid % TPR;
     CV yr = zero, xr = zero;
     {
         F sr = 0.0, si = 0.0;
         if (qr < BT) {
 #pragma unroll
-            for (int j = 0; j < BT / 4; ++j) {
-                const int c = q + 4 * j;
+            for (int j = 0; j < BT / TPR; ++j) {
+                const int c = q + TPR * j;
                 const CV a = Bs[qr + c * LD], v = vp[c];
                 sr += a.x * v.x - a.y * v.y;
                 si += a.x * v.y + a.y * v.x;
             }
         }
-        sr = quad_sum(sr);
-        si = quad_sum(si);
+        sr = group_sum<TPR>(sr);
+        si = group_sum<TPR>(si);
         F n2 = 0.0;
         if (qr < BT) {
             yr = mk2<F>(tp * sr, tp * si);
@@ -154,7 +171,9 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
     F tj, ur, ui;
     CV beta;
     {
-        const F tail2 = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+        F tail2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) tail2 += red[k][0];
         const CV x0 = xv[0];
         const F aa = sqrt(x0.x * x0.x + x0.y * x0.y);
         if (tail2 == 0.0) {
@@ -186,7 +205,7 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
         if (t > 0) {
 #pragma unroll
             for (int i = 0; i < NE; ++i) {
-                const int e = tid + 256 * i;
+                const int e = tid + NT * i;
                 const int r = e % BT, c = e / BT;
                 if (r >= Lr || c >= b) continue;
                 CV a = rb[i];
@@ -205,26 +224,26 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
         F pr = 0.0, pi = 0.0, wr = 0.0, wi = 0.0;
         if (qr < BT) {
 #pragma unroll
-            for (int j = 0; j < BT / 4; ++j) {
-                const int c = q + 4 * j;
+            for (int j = 0; j < BT / TPR; ++j) {
+                const int c = q + TPR * j;
                 const CV a = Ds[qr + c * LD], v = vn[c];
                 pr += a.x * v.x - a.y * v.y;
                 pi += a.x * v.y + a.y * v.x;
             }
             if (t > 0) {
 #pragma unroll
-                for (int j = 0; j < BT / 4; ++j) {
-                    const int r = q + 4 * j;
+                for (int j = 0; j < BT / TPR; ++j) {
+                    const int r = q + TPR * j;
                     const CV v = vn[r], a = Bs[r + qr * LD];
                     wr += v.x * a.x + v.y * a.y;
                     wi += v.x * a.y - v.y * a.x;
                 }
             }
         }
-        pr = quad_sum(pr);
-        pi = quad_sum(pi);
-        wr = quad_sum(wr);
-        wi = quad_sum(wi);
+        pr = group_sum<TPR>(pr);
+        pi = group_sum<TPR>(pi);
+        wr = group_sum<TPR>(wr);
+        wi = group_sum<TPR>(wi);
         F kr = 0.0, ki = 0.0, gr = 0.0, gi = 0.0;
         if (qr < BT && q == 0) {
             const CV p = mk2<F>(tj * pr, tj * pi);
@@ -245,14 +264,20 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
     __syncthreads();
 
     // ---- phase 4: write B (t > 0) or the removed column (t = 0), and D
-    const F Kr = 0.5 * tj * (red[0][0] + red[1][0] + red[2][0] + red[3][0]);
-    const F Ki = 0.5 * tj * (red[0][1] + red[1][1] + red[2][1] + red[3][1]);
-    const F gmr = red[0][2] + red[1][2] + red[2][2] + red[3][2];
-    const F gmi = red[0][3] + red[1][3] + red[2][3] + red[3][3];
+    F Kr = 0.0, Ki = 0.0, gmr = 0.0, gmi = 0.0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+        Kr += red[k][0];
+        Ki += red[k][1];
+        gmr += red[k][2];
+        gmi += red[k][3];
+    }
+    Kr *= 0.5 * tj;
+    Ki *= 0.5 * tj;
     if (t > 0) {
 #pragma unroll
         for (int i = 0; i < NE; ++i) {
-            const int e = tid + 256 * i;
+            const int e = tid + NT * i;
             const int r = e % BT, c = e / BT;
             if (r >= Lr || c >= b) continue;
             CV a;
@@ -279,7 +304,7 @@ __global__ __launch_bounds__(256) void hb2st_step(int64_t n, int b, F *__restric
     }
 #pragma unroll
     for (int i = 0; i < NE; ++i) {
-        const int e = tid + 256 * i;
+        const int e = tid + NT * i;
         const int r = e % BT, c = e / BT;
         if (r >= Lr || c >= Lr || r < c) continue;
         const CV vr = vn[r], vc = vn[c], pr = pv[r], pc = pv[c];
@@ -343,11 +368,11 @@ int hb2st_t(int64_t n, int b, F *AB, int64_t ldab, F *V2, F *tau2, double *d, do
             if (s_hi < s_lo) continue;
             const dim3 grid((unsigned)(s_hi - s_lo + 1));
             if (b <= 16)
-                hipLaunchKernelGGL((hb2st_step<F, 16>), grid, dim3(256), 0, s, n, b, AB, ldab, V2, tau2, g, s_lo);
+                hipLaunchKernelGGL((hb2st_step<F, 16, 256>), grid, dim3(256), 0, s, n, b, AB, ldab, V2, tau2, g, s_lo);
             else if (b <= 32)
-                hipLaunchKernelGGL((hb2st_step<F, 32>), grid, dim3(256), 0, s, n, b, AB, ldab, V2, tau2, g, s_lo);
+                hipLaunchKernelGGL((hb2st_step<F, 32, 256>), grid, dim3(256), 0, s, n, b, AB, ldab, V2, tau2, g, s_lo);
             else
-                hipLaunchKernelGGL((hb2st_step<F, 64>), grid, dim3(256), 0, s, n, b, AB, ldab, V2, tau2, g, s_lo);
+                hipLaunchKernelGGL((hb2st_step<F, 64, 512>), grid, dim3(512), 0, s, n, b, AB, ldab, V2, tau2, g, s_lo);
         }
         BDG_CHECK_LAUNCH();
     }

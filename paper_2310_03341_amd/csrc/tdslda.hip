@@ -26,7 +26,6 @@
 // A step moves 18 state arrays through HBM (predictor 6 in / 1 out, two
 // evaluations 1 in / 1 out each, corrector 6 in / 1 out).
 #include <math.h>
-#include <stdlib.h>
 
 #include "solver.h"
 
