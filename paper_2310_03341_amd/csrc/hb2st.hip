@@ -69,6 +69,12 @@ __global__ __launch_bounds__(NT) void hb2st_step(int64_t n, int b, F *__restrict
     constexpr int TPR = NT / 64;      // threads per row in the matrix-vector products
     static_assert(NE >= 1 && BT % TPR == 0 && (TPR == 4 || TPR == 8 || TPR == 16), "hb2st: tile shape");
     constexpr int LD = BT + 1;
+    // The Hermitian block D is handled through its stored lower triangle only:
+    // entry p of the triangle lies in column pair j = p / (BT + 1) (columns j
+    // and BT - 1 - j, BT + 1 entries together), so consecutive p are
+    // consecutive rows of one column.
+    constexpr int ND = BT / 2 * (BT + 1);
+    constexpr int NED = (ND + NT - 1) / NT;
     __shared__ CV Bs[BT * LD];
     __shared__ CV Ds[BT * LD];
     __shared__ CV vp[BT], xv[BT], vn[BT], yv[BT], pv[BT], wb[BT];
@@ -89,7 +95,17 @@ __global__ __launch_bounds__(NT) void hb2st_step(int64_t n, int b, F *__restrict
     // ---- phase 0: B = A[R, C] (t > 0), D = A[R, R] (full Hermitian), the
     // previous reflector (t > 0) or the column being removed (t = 0).
     // Unconditional loads (entry 0 outside the block), zeroed by select.
-    CV rb[NE], rd[NE];
+    CV rb[NE], rd[NED];
+    auto dpos = [](int p, int &r, int &c) {
+        const int j = p / (BT + 1), k = p - j * (BT + 1);
+        if (k < BT - j) {
+            c = j;
+            r = j + k;
+        } else {
+            c = BT - 1 - j;
+            r = c + (k - (BT - j));
+        }
+    };
     F tp = 0.0;
     {
         unsigned okb = 0, okd = 0;
@@ -98,12 +114,18 @@ __global__ __launch_bounds__(NT) void hb2st_step(int64_t n, int b, F *__restrict
             const int e = tid + NT * i;
             const int r = e % BT, c = e / BT;
             const bool ob = (t > 0) & (r < Lr) & (c < b);
-            const bool od = (r < Lr) & (c < Lr);
             const int64_t offb = ob ? 2 * ((b + r - c) + (c0 + c) * ldab) : 0;
-            const int64_t offd = od ? 2 * (r >= c ? (r - c) + (r0 + c) * ldab : (c - r) + (r0 + r) * ldab) : 0;
             rb[i] = ld2<F>(AB + offb);
-            rd[i] = ld2<F>(AB + offd);
             okb |= (unsigned)ob << i;
+        }
+#pragma unroll
+        for (int i = 0; i < NED; ++i) {
+            const int p = tid + NT * i;
+            int r, c;
+            dpos(p < ND ? p : 0, r, c);
+            const bool od = (p < ND) & (r < Lr);
+            const int64_t offd = od ? 2 * ((r - c) + (r0 + c) * ldab) : 0;
+            rd[i] = ld2<F>(AB + offd);
             okd |= (unsigned)od << i;
         }
         const bool ov = (t > 0) & (tid < b);
@@ -116,10 +138,17 @@ __global__ __launch_bounds__(NT) void hb2st_step(int64_t n, int b, F *__restrict
             const int e = tid + NT * i;
             const int r = e % BT, c = e / BT;
             if (!((okb >> i) & 1u)) rb[i] = zero;
-            if (!((okd >> i) & 1u)) rd[i] = zero;
-            else if (r < c) rd[i].y = -rd[i].y;  // upper entry: conj of the stored lower one
             Bs[r + c * LD] = rb[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NED; ++i) {
+            const int p = tid + NT * i;
+            if (p >= ND) break;
+            int r, c;
+            dpos(p, r, c);
+            if (!((okd >> i) & 1u)) rd[i] = zero;
             Ds[r + c * LD] = rd[i];
+            if (r > c) Ds[c + r * LD] = mk2<F>(rd[i].x, -rd[i].y);  // upper: conj of the lower entry
         }
         if (tid < BT) {
             vp[tid] = sel2(ov, pv0, zero);
@@ -303,10 +332,12 @@ __global__ __launch_bounds__(NT) void hb2st_step(int64_t n, int b, F *__restrict
         st2<F>(AB + 2 * ((1 + tid) + s * ldab), sel2(tid == 0, beta, zero));
     }
 #pragma unroll
-    for (int i = 0; i < NE; ++i) {
-        const int e = tid + NT * i;
-        const int r = e % BT, c = e / BT;
-        if (r >= Lr || c >= Lr || r < c) continue;
+    for (int i = 0; i < NED; ++i) {
+        const int p = tid + NT * i;
+        if (p >= ND) break;
+        int r, c;
+        dpos(p, r, c);
+        if (r >= Lr) continue;
         const CV vr = vn[r], vc = vn[c], pr = pv[r], pc = pv[c];
         const CV wr = mk2<F>(pr.x - (Kr * vr.x - Ki * vr.y), pr.y - (Kr * vr.y + Ki * vr.x));
         const CV wc = mk2<F>(pc.x - (Kr * vc.x - Ki * vc.y), pc.y - (Kr * vc.y + Ki * vc.x));
