@@ -300,6 +300,9 @@ def main():
                          "as the reference point for HBM byte counters")
     ap.add_argument("--only", choices=["tdslda", "onestage", "int8gemm"], default=None,
                     help="run one side measurement alone and print its JSON (for profiling)")
+    ap.add_argument("--jsonl", type=str, default="",
+                    help="also append the result line, with a UTC time stamp and the command line, "
+                         "to this JSON-lines log")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the solver is single-GPU; run with --gpus 1",
@@ -324,6 +327,7 @@ def main():
         else:
             res = bench_int8_gemm(api, torch, dev, say)
         print(json.dumps({args.only: res}))
+        append_log(args.jsonl, {args.only: res})
         return
     if dims == (24, 24, 24):
         w = inputs.metric_3d()
@@ -483,6 +487,19 @@ def main():
         if sample_mixed is not None:
             out["cpu_certification"]["mixed_refined"] = certify_sampled(w, sample_mixed)
     print(json.dumps(out))
+    append_log(args.jsonl, out)
+
+
+def append_log(path, rec):
+    """One JSON line per run appended to `path` (no-op for an empty path)."""
+    if not path:
+        return
+    import datetime
+    row = {"time_utc": datetime.datetime.now(datetime.timezone.utc).isoformat(timespec="seconds"),
+           "argv": sys.argv[1:]}
+    row.update(rec)
+    with open(path, "a") as f:
+        f.write(json.dumps(row) + "\n")
 
 
 if __name__ == "__main__":

@@ -16,13 +16,15 @@ import argparse
 import dataclasses
 import json
 import math
+import os
 import time
-from typing import List
+from typing import List, Optional
 
 import numpy as np
 import torch
 
 from . import api, inputs
+from . import checkpoint as ckpt
 
 UNIFORM_DELTA = 0.3
 
@@ -33,36 +35,79 @@ def uniform_start(inst: inputs.ScfInstance, dev):
     return U, D
 
 
-def run_scf(stepper: api.ScfStepper, U, D, p: inputs.ScfParams, max_iter=None):
-    """Iterate until the change is below p.tol; returns (iterations, converged, history)."""
+def run_scf(stepper: api.ScfStepper, U, D, p: inputs.ScfParams, max_iter=None,
+            checkpoint: Optional[str] = None, every: int = 10, fp: str = ""):
+    """Iterate until the change is below p.tol; returns (iterations, converged, history).
+
+    With `checkpoint`, the fields are written there every `every` iterations
+    and at the end, and an existing checkpoint of the same problem (`fp`, see
+    checkpoint.fingerprint) is continued: U and D are overwritten in place by
+    its fields and the count goes on from its iteration."""
     hist = []
     max_iter = max_iter or p.max_iter
-    for it in range(1, max_iter + 1):
+    it0 = 0
+    if checkpoint:
+        got = ckpt.load(checkpoint, fp)
+        if got is not None:
+            Uc, Dc, it0, hist = got
+            U.copy_(torch.from_numpy(Uc))
+            D.copy_(torch.from_numpy(Dc))
+            if hist and (not math.isfinite(hist[-1]) or hist[-1] <= p.tol):
+                return it0, math.isfinite(hist[-1]), hist
+
+    def keep(it):
+        if checkpoint:
+            ckpt.save(checkpoint, U.cpu().numpy(), D.cpu().numpy(), it, hist, fp)
+
+    for it in range(it0 + 1, max_iter + 1):
         change, m = stepper.step(U, D)
         hist.append(change)
         if not math.isfinite(change):
+            keep(it)
             return it, False, hist
         if change <= p.tol:
+            keep(it)
             return it, True, hist
+        if checkpoint and it % every == 0:
+            keep(it)
+    keep(max(it0, max_iter))
     return max_iter, False, hist
 
 
-def solve_instance(inst, p, dev, U=None, D=None):
+def solve_instance(inst, p, dev, U=None, D=None, checkpoint: Optional[str] = None, every: int = 10):
     st = api.ScfStepper(inst.dims, torch.from_numpy(inst.Vext).to(dev),
                         torch.from_numpy(inst.theta).to(dev), inst.mu, p)
     if U is None:
         U, D = uniform_start(inst, dev)
-    iters, ok, hist = run_scf(st, U, D, p)
+    fp = ckpt.fingerprint(inst.dims, inst.mu, p, inst.Vext, inst.theta) if checkpoint else ""
+    iters, ok, hist = run_scf(st, U, D, p, checkpoint=checkpoint, every=every, fp=fp)
     return iters, ok, U, D
 
 
-def generate(indices: List[int], dims, p, dev, log=None):
-    """Converged fields of the SCF instances (uniform start)."""
+def generate(indices: List[int], dims, p, dev, log=None, checkpoint_dir: Optional[str] = None):
+    """Converged fields of the SCF instances (uniform start).  With
+    `checkpoint_dir`, finished instances are kept there and not solved again,
+    and the instance in progress is checkpointed every ten iterations."""
     out = []
+    if checkpoint_dir:
+        os.makedirs(checkpoint_dir, exist_ok=True)
     for i in indices:
         inst = inputs.scf_instance(i, dims=dims)
         t0 = time.time()
-        iters, ok, U, D = solve_instance(inst, p, dev)
+        done = os.path.join(checkpoint_dir, "instance_%d_done.npz" % i) if checkpoint_dir else None
+        fp = ckpt.fingerprint(inst.dims, inst.mu, p, inst.Vext, inst.theta) if checkpoint_dir else ""
+        got = ckpt.load(done, fp) if done else None
+        if got is not None:
+            U, D, iters, hist = got
+            ok = bool(hist) and math.isfinite(hist[-1]) and hist[-1] <= p.tol
+            out.append({"index": i, "inst": inst, "iters": iters, "ok": ok, "U": U, "D": D})
+            if log:
+                log("instance %d: from %s" % (i, done))
+            continue
+        partial = os.path.join(checkpoint_dir, "instance_%d_scf.npz" % i) if checkpoint_dir else None
+        iters, ok, U, D = solve_instance(inst, p, dev, checkpoint=partial)
+        if done:
+            os.replace(partial, done)
         out.append({"index": i, "inst": inst, "iters": iters, "ok": ok,
                     "U": U.cpu().numpy(), "D": D.cpu().numpy()})
         if log:
@@ -163,6 +208,8 @@ def main():
     ap.add_argument("--alpha", type=float, default=0.9, help="linear mixing (same for both starts)")
     ap.add_argument("--max-iter", type=int, default=400)
     ap.add_argument("--out", type=str, default="")
+    ap.add_argument("--checkpoint-dir", type=str, default="",
+                    help="keep converged instances (and the one in progress) here; a rerun continues")
     args = ap.parse_args()
     dev = torch.device("cuda:0")
     p = dataclasses.replace(inputs.ScfParams(), alpha=args.alpha, max_iter=args.max_iter)
@@ -171,8 +218,9 @@ def main():
     t0 = time.time()
     # instances whose uniform-start iteration does not converge (limit cycles
     # of a level on the window edge) are left out of both sets
-    train_all = generate(list(range(args.train)), dims, p, dev, log)
-    test_all = generate(list(range(10000, 10000 + args.test)), dims, p, dev, log)
+    cdir = args.checkpoint_dir or None
+    train_all = generate(list(range(args.train)), dims, p, dev, log, checkpoint_dir=cdir)
+    test_all = generate(list(range(10000, 10000 + args.test)), dims, p, dev, log, checkpoint_dir=cdir)
     train_set = [d for d in train_all if d["ok"]]
     test_set = [d for d in test_all if d["ok"]]
     t1 = time.time()

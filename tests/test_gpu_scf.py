@@ -58,3 +58,23 @@ def test_scf_uniform_gas_fixed_point_on_gpu(dev):
     assert np.abs(d - d.mean()).max() < 1e-10
     _, nu = scf.uniform_densities(dims, 0.0, d.mean(), 1.0, p.Ec)
     assert abs(p.g * nu / d.mean() - 1.0) < 1e-9
+
+
+def test_scf_checkpoint_resume_on_gpu(dev, tmp_path):
+    """The SCF iteration on the GPU, interrupted after 7 steps and continued
+    from its checkpoint, reaches the iterate of an uninterrupted run of the
+    same length (the step is a function of the fields alone)."""
+    import torch
+    from paper_2310_03341_amd import learned_start as ls
+    inst = inputs.scf_instance(3, dims=(12, 12))
+    p = inputs.ScfParams(tol=0.0, max_iter=12)
+    it_a, _, Ua, Da = ls.solve_instance(inst, p, dev)
+    path = str(tmp_path / "scf.npz")
+    p7 = inputs.ScfParams(tol=0.0, max_iter=7)
+    it_b, ok_b, _, _ = ls.solve_instance(inst, p7, dev, checkpoint=path, every=3)
+    assert it_b == 7 and not ok_b
+    it_c, _, Uc, Dc = ls.solve_instance(inst, p, dev, checkpoint=path, every=3)
+    assert it_a == it_c == 12
+    print("max |U - U'| %.2e, max |D - D'| %.2e" % ((Ua - Uc).abs().max().item(), (Da - Dc).abs().max().item()))
+    assert torch.allclose(Ua, Uc, rtol=0, atol=1e-12)
+    assert torch.allclose(Da, Dc, rtol=0, atol=1e-12)
