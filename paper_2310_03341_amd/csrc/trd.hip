@@ -182,78 +182,79 @@ __global__ __launch_bounds__(CB) void panel_dots(int64_t n, int64_t c, int j, co
 // of them) of tile column J.  P1[J][row] += B_IJ v_J for the rows of tile I;
 // P2[J][q][col] = sum over its tiles of B_IJ^H v_I for the columns of tile J.
 // On the diagonal tile only the strictly lower part adds its adjoint and the
-// diagonal adds once.  Thread (r, cq): row r of the tile, columns 16 cq ..
+// diagonal adds once.  512 threads: lane r is row r of a tile (coalesced
+// column reads), wave cq holds columns 8 cq .. 8 cq + 7.  The tile loop has no
+// barrier: each thread keeps its part of the row sums of every tile in LDS
+// slots of its own, which one barrier at the end reduces over the eight
+// waves; the column sums are reduced over the lanes of each wave by DPP
+// moves.  With about 120 registers, two workgroups share a CU and hide the
+// latency of each other's loads.
+constexpr int HW = 8;           // waves of hemv_tiles
+constexpr int HC = HT / HW;     // columns per thread
 template <bool CX>
-__global__ __launch_bounds__(256) void hemv_tiles(int64_t mt, const double *__restrict__ B, int64_t ldb,
-                                                  const double *__restrict__ v, double *__restrict__ P1,
-                                                  double *__restrict__ P2, int maxq) {
+__global__ __launch_bounds__(64 * HW, 4) void hemv_tiles(int64_t mt, const double *__restrict__ B, int64_t ldb,
+                                                      const double *__restrict__ v, double *__restrict__ P1,
+                                                      double *__restrict__ P2, int maxq) {
     const int J = blockIdx.x, q = blockIdx.y;
     const int nt = (int)((mt + HT - 1) / HT);
     const int I0 = J + q * HCH;
     if (I0 >= nt) return;
     const int I1 = std::min(nt, I0 + HCH);
     const int r = threadIdx.x & 63, cq = threadIdx.x >> 6;
-    __shared__ double2 red[4][64];
-    zd vJ[16], acc2[16];
+    __shared__ double2 rs[HCH][HW][HT];  // row-sum partials: tile, wave, row
+    zd vJ[HC], acc2[HC];
+    const int64_t c0 = (int64_t)J * HT + cq * HC;
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        const int64_t col = (int64_t)J * HT + cq * 16 + s;
-        vJ[s] = col < mt ? eld<CX>(v, col) : mk(0.0, 0.0);
+    for (int s = 0; s < HC; ++s) {
+        vJ[s] = c0 + s < mt ? eld<CX>(v, c0 + s) : mk(0.0, 0.0);
         acc2[s] = mk(0.0, 0.0);
     }
-    for (int I = I0; I < I1; ++I) {
+#pragma unroll
+    for (int u = 0; u < HCH; ++u) {
+        const int I = I0 + u;
+        if (I >= I1) break;
         const int64_t row = (int64_t)I * HT + r;
         const bool rok = row < mt;
         const zd vI = rok ? eld<CX>(v, row) : mk(0.0, 0.0);
-        zd s1 = mk(0.0, 0.0);
-        zd bv[16];
+        zd bv[HC];
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int64_t col = (int64_t)J * HT + cq * 16 + s;
-            const bool ok = rok && col < mt && (I != J || row >= col);
+        for (int s = 0; s < HC; ++s) {
+            const int64_t col = c0 + s;
+            const bool ok = rok & (col < mt) & ((I != J) | (row >= col));
             // unconditional load from entry 0 outside, so the loads overlap
             const zd b = eld<CX>(B, ok ? row + col * ldb : 0);
             bv[s] = ok ? b : mk(0.0, 0.0);
         }
+        zd s1 = mk(0.0, 0.0);
 #pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int64_t col = (int64_t)J * HT + cq * 16 + s;
+        for (int s = 0; s < HC; ++s) {
+            const int64_t col = c0 + s;
             zd b = bv[s];
             if (I == J && row == col) b.im = 0.0;  // Hermitian diagonal is real
             s1 = cadd(s1, cmul(b, vJ[s]));
             if (I != J || row > col) acc2[s] = cadd(acc2[s], cjmul(b, vI));
         }
-        red[cq][r] = make_double2(s1.re, s1.im);
-        __syncthreads();
-        if (cq == 0 && rok) {
-            double xr = 0.0, xi = 0.0;
-            for (int k2 = 0; k2 < 4; ++k2) {
-                xr += red[k2][r].x;
-                xi += red[k2][r].y;
-            }
-            est<CX>(P1, (int64_t)J * mt + row, mk(xr, xi));
-        }
-        __syncthreads();
+        rs[u][cq][r] = make_double2(s1.re, s1.im);
     }
-    // column sums of acc2 over the 64 rows r: LDS transpose in four rounds
-    __shared__ double2 cs[64][17];
-    for (int g = 0; g < 4; ++g) {
-        if (cq == g) {
+    // column sums over the 64 rows (lanes) of this wave's columns
 #pragma unroll
-            for (int s = 0; s < 16; ++s) cs[r][s] = make_double2(acc2[s].re, acc2[s].im);
+    for (int s = 0; s < HC; ++s) {
+        const double xr = wave_sum_last(acc2[s].re), xi = wave_sum_last(acc2[s].im);
+        if (r == 63 && c0 + s < mt) est<CX>(P2, ((int64_t)J * maxq + q) * HT + cq * HC + s, mk(xr, xi));
+    }
+    __syncthreads();
+    // row sums: thread (u, r) of the first HCH x 64 adds the eight waves' parts
+    for (int e = threadIdx.x; e < HCH * HT; e += 64 * HW) {
+        const int u = e / HT, rr = e % HT;
+        const int64_t row = (int64_t)(I0 + u) * HT + rr;
+        if (I0 + u >= I1 || row >= mt) continue;
+        double xr = 0.0, xi = 0.0;
+#pragma unroll
+        for (int w = 0; w < HW; ++w) {
+            xr += rs[u][w][rr].x;
+            xi += rs[u][w][rr].y;
         }
-        __syncthreads();
-        if (threadIdx.x < 16) {
-            const int s = threadIdx.x;
-            double xr = 0.0, xi = 0.0;
-            for (int rr = 0; rr < 64; ++rr) {
-                xr += cs[rr][s].x;
-                xi += cs[rr][s].y;
-            }
-            const int64_t col = (int64_t)J * HT + g * 16 + s;
-            if (col < mt) est<CX>(P2, ((int64_t)J * maxq + q) * HT + g * 16 + s, mk(xr, xi));
-        }
-        __syncthreads();
+        est<CX>(P1, (int64_t)J * mt + row, mk(xr, xi));
     }
 }
 
@@ -444,7 +445,7 @@ int trd_t(int64_t n, double *A, int64_t lda, const L1 &L, char *base, hipStream_
             const int64_t mt = n - c - 1;
             const int nt = (int)((mt + HT - 1) / HT);
             const int maxq = (nt + HCH - 1) / HCH;
-            hipLaunchKernelGGL((hemv_tiles<CX>), dim3(nt, maxq), dim3(256), 0, s, mt,
+            hipLaunchKernelGGL((hemv_tiles<CX>), dim3(nt, maxq), dim3(64 * HW), 0, s, mt,
                                A + ew * ((c + 1) + (c + 1) * lda), lda, VW + ew * ((c + 1) + (int64_t)j * ldw),
                                P1, P2, maxq);
             const int nw = (int)((mt + CB - 1) / CB);
