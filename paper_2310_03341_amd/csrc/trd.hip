@@ -260,40 +260,51 @@ __global__ __launch_bounds__(64 * HW, 4) void hemv_tiles(int64_t mt, const doubl
 
 // w = tau (y - V u1 - W u2) over rows c+1 .. n-1, with y summed from the hemv
 // partials; partial sums of w^H v.  Rows <= c of W's column are zero.
+// Workgroup: the 64 rows of tile I (lane = row); its eight waves split the
+// terms of y (tile columns J, chunks q and delayed-update columns i, each
+// wave every eighth), then one barrier and wave 0 finishes the rows.
 template <bool CX>
-__global__ __launch_bounds__(CB) void finish_w(int64_t n, int64_t c, int j, const double *__restrict__ tau,
-                                               const double *__restrict__ u, double *VW, int64_t ldw,
-                                               const double *__restrict__ P1, const double *__restrict__ P2,
-                                               int maxq, double *__restrict__ part) {
-    __shared__ double red[4];
+__global__ __launch_bounds__(64 * HW) void finish_w(int64_t n, int64_t c, int j, const double *__restrict__ tau,
+                                                    const double *__restrict__ u, double *VW, int64_t ldw,
+                                                    const double *__restrict__ P1, const double *__restrict__ P2,
+                                                    int maxq, double *__restrict__ part) {
     __shared__ double2 us[2 * NB];
+    __shared__ double2 ys[HW][HT];
     for (int i = threadIdx.x; i < 2 * NB; i += blockDim.x) us[i] = make_double2(u[2 * i], u[2 * i + 1]);
     __syncthreads();
     const int64_t mt = n - c - 1;
-    const zd t = mk(tau[2 * c], tau[2 * c + 1]);
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // 0 .. mt-1
-    double pr = 0.0, pi = 0.0;
+    const int I = blockIdx.x, lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t idx = (int64_t)I * HT + lane;  // 0 .. mt-1
+    const int nt = (int)((mt + HT - 1) / HT);
+    zd y = mk(0.0, 0.0);
     if (idx < mt) {
         const int64_t r = c + 1 + idx;
-        const int I = (int)(idx / HT);
-        const int nt = (int)((mt + HT - 1) / HT);
-        zd y = mk(0.0, 0.0);
-        for (int J = 0; J <= I; ++J) y = cadd(y, eld<CX>(P1, (int64_t)J * mt + idx));
+        for (int J = wv; J <= I; J += HW) y = cadd(y, eld<CX>(P1, (int64_t)J * mt + idx));
         const int nq = (nt - I + HCH - 1) / HCH;
-        for (int q = 0; q < nq; ++q) y = cadd(y, eld<CX>(P2, ((int64_t)I * maxq + q) * HT + (idx % HT)));
-        for (int i = 0; i < j; ++i) {
+        for (int q = wv; q < nq; q += HW) y = cadd(y, eld<CX>(P2, ((int64_t)I * maxq + q) * HT + lane));
+        for (int i = wv; i < j; i += HW) {
             const zd v = eld<CX>(VW, r + (int64_t)i * ldw), w = eld<CX>(VW, r + (int64_t)(NB + i) * ldw);
             y = csub(y, cadd(cmul(v, mk(us[i].x, us[i].y)), cmul(w, mk(us[NB + i].x, us[NB + i].y))));
         }
-        const zd w = cmul(t, y);
+    }
+    ys[wv][lane] = make_double2(y.re, y.im);
+    __syncthreads();
+    if (wv != 0) return;
+    double pr = 0.0, pi = 0.0;
+    if (idx < mt) {
+        const int64_t r = c + 1 + idx;
+        zd ysum = mk(0.0, 0.0);
+#pragma unroll
+        for (int w = 0; w < HW; ++w) ysum = cadd(ysum, mk(ys[w][lane].x, ys[w][lane].y));
+        const zd w = cmul(mk(tau[2 * c], tau[2 * c + 1]), ysum);
         est<CX>(VW, r + (int64_t)(NB + j) * ldw, w);
         const zd p = cjmul(w, eld<CX>(VW, r + (int64_t)j * ldw));
         pr = p.re;
         pi = p.im;
     }
-    pr = block_sum(pr, red);
-    pi = block_sum(pi, red);
-    if (threadIdx.x == 0) {
+    pr = wave_sum_last(pr);
+    pi = wave_sum_last(pi);
+    if (lane == 63) {
         part[2 * blockIdx.x] = pr;
         part[2 * blockIdx.x + 1] = pi;
     }
@@ -385,7 +396,7 @@ L1 layout1(int64_t n, bool cx, int64_t zcols) {
     L.np = n >= 2 ? (n - 1 + NB - 1) / NB : 0;
     L.nt = (n + HT - 1) / HT;
     L.maxq = (L.nt + HCH - 1) / HCH;
-    L.nparts = (n + CB - 1) / CB + 1;
+    L.nparts = (n + HT - 1) / HT + 1;  // >= (n + CB - 1) / CB + 1 as well
     size_t o = 0;
     auto put = [&](size_t b) { size_t r = o; o += al256(b); return r; };
     L.off_d = put(8 * (size_t)n);
@@ -448,9 +459,9 @@ int trd_t(int64_t n, double *A, int64_t lda, const L1 &L, char *base, hipStream_
             hipLaunchKernelGGL((hemv_tiles<CX>), dim3(nt, maxq), dim3(64 * HW), 0, s, mt,
                                A + ew * ((c + 1) + (c + 1) * lda), lda, VW + ew * ((c + 1) + (int64_t)j * ldw),
                                P1, P2, maxq);
-            const int nw = (int)((mt + CB - 1) / CB);
-            hipLaunchKernelGGL((finish_w<CX>), dim3(nw), dim3(CB), 0, s, n, c, j, tau, u, VW, ldw, P1, P2, maxq,
-                               part);
+            const int nw = nt;  // one workgroup per 64-row tile
+            hipLaunchKernelGGL((finish_w<CX>), dim3(nw), dim3(64 * HW), 0, s, n, c, j, tau, u, VW, ldw, P1, P2,
+                               maxq, part);
             hipLaunchKernelGGL((fix_w<CX>), dim3(gs), dim3(CB), 0, s, n, c, k, j, tau, part, nw, VW, WV, ldw);
             BDG_CHECK_LAUNCH();
         }
