@@ -26,6 +26,7 @@
 // A step moves 18 state arrays through HBM (predictor 6 in / 1 out, two
 // evaluations 1 in / 1 out each, corrector 6 in / 1 out).
 #include <math.h>
+#include <stdlib.h>
 
 #include "solver.h"
 
@@ -135,7 +136,12 @@ __global__ __launch_bounds__(NT) void td_apply(int ndim, int Nx, int Ny, int Nz,
         }
     }
     const double2 *col = (const double2 *)(X + 2 * j * ldx);
-    for (int i = threadIdx.x; i < 2 * ns; i += NT) sh[i] = col[i];
+    // fixed trip count (2 ns <= 2 MAXS): every load is issued before the first store
+#pragma unroll
+    for (int it = 0; it < 2 * MAXS / NT; ++it) {
+        const int i = threadIdx.x + it * NT;
+        if (i < 2 * ns) sh[i] = col[i];
+    }
     __syncthreads();
     const int bx = Nx / 2, by = Ny / BY;
     const int nb = bx * by * Nz;
@@ -230,6 +236,139 @@ __global__ __launch_bounds__(NT) void td_apply(int ndim, int Nx, int Ny, int Nz,
     }
 }
 
+// The same F = -i H X with the kinetic term on the matrix cores, for 2-D
+// lattices whose sides are multiples of 16 and the 16 x 16 x 16 lattice.  The
+// circulant product along x and along y of one z plane is a 16 x 16 tile
+// product: D[x][y] = sum_x' t(x - x') s[x'][y] + sum_y' s[x][y'] t(y - y'),
+// i.e. T_x S and S T_y with T symmetric (v_mfma_f64_16x16x4, real tables,
+// real and imaginary parts of s as two products).  Along z the tile is
+// oriented [z][x] for one y: D[z][x] = sum_z' t(z - z') s[x][y][z'].  One
+// component (u, then v) at a time sits in LDS with the x stride padded by
+// one element (the tile operands then hit distinct banks); the x and y terms
+// go to an LDS result buffer, the z term is added into it, and the epilogue
+// adds the local terms with the other component read from global memory.
+// 1024 threads: the per-state chain of loads, products and stores is latency
+// bound, and more waves shorten it (0.31 ms per application at 16^3 against
+// 0.36 ms with 512 threads and 0.35 ms for the general kernel).
+constexpr int TD_MFMA_LDS = 4352;  // padded sites: (Nx + 1) Ny Nz <= 4352
+constexpr int TD_MFMA_NT = 1024;
+__global__ __launch_bounds__(TD_MFMA_NT) void td_apply_mfma(int ndim, int Nx, int Ny, int Nz,
+                                                            const double *__restrict__ X, int64_t ldx,
+                                                            const double *__restrict__ U,
+                                                            const double *__restrict__ D, double mu,
+                                                            double *__restrict__ F, int64_t ldf) {
+    constexpr int NTH = TD_MFMA_NT, NW = NTH / 64;
+    __shared__ double2 S[TD_MFMA_LDS];
+    __shared__ double2 O[TD_MFMA_LDS];
+    __shared__ double tab[3][64];
+    const int ns = Nx * Ny * Nz;
+    const int px = Nx + 1, pxy = (Nx + 1) * Ny;  // padded strides
+    const int64_t j = blockIdx.x;
+    for (int d = 0; d < 3; ++d) {
+        const int Nd = d == 0 ? Nx : (d == 1 ? Ny : Nz);
+        for (int k = threadIdx.x; k < Nd; k += blockDim.x) {
+            double v;
+            const double pn = M_PI / (double)Nd;
+            if (k == 0) {
+                v = M_PI * M_PI * ((double)Nd * Nd + 2.0) / (6.0 * (double)Nd * Nd);
+            } else {
+                const double sn = sin(pn * (double)k);
+                v = ((k & 1) ? -1.0 : 1.0) * pn * pn / (sn * sn);
+            }
+            tab[d][k] = (d < ndim) ? v : 0.0;
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const double2 *col = (const double2 *)(X + 2 * j * ldx);
+    double2 *fcol = (double2 *)(F + 2 * j * ldf);
+    const int txb = Nx / 16, tyb = Ny / 16;
+    for (int c = 0; c < 2; ++c) {
+        // fixed trip count (ns <= 4096): every load is issued before the first store
+#pragma unroll
+        for (int it = 0; it < 4096 / NTH; ++it) {
+            const int r = threadIdx.x + it * NTH;
+            if (r < ns) {
+                const int x = r % Nx, y = (r / Nx) % Ny, z = r / (Nx * Ny);
+                S[x + px * y + pxy * z] = col[c * ns + r];
+            }
+        }
+        __syncthreads();
+        // x and y terms, tiles [x][y] of one plane z
+        const int nA = txb * tyb * Nz;
+        for (int tile = wv; tile < nA; tile += NW) {
+            const int bx = tile % txb, by = (tile / txb) % tyb, z = tile / (txb * tyb);
+            d4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
+            const int xo = bx * 16 + lr, yo = by * 16 + lr;
+            for (int k0 = 0; k0 < Nx; k0 += 4) {
+                const int xp = k0 + lk;
+                const int dd = xo - xp < 0 ? xo - xp + Nx : xo - xp;
+                const double a = tab[0][dd];
+                const double2 b = S[xp + px * yo + pxy * z];
+                ar = mfma16(a, b.x, ar);
+                ai = mfma16(a, b.y, ai);
+            }
+            for (int k0 = 0; k0 < Ny; k0 += 4) {
+                const int yp = k0 + lk;
+                const int dd = yo - yp < 0 ? yo - yp + Ny : yo - yp;
+                const double bt = tab[1][dd];
+                const double2 a = S[xo + px * yp + pxy * z];
+                ar = mfma16(a.x, bt, ar);
+                ai = mfma16(a.y, bt, ai);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) O[(bx * 16 + lk + 4 * q) + px * yo + pxy * z] = make_double2(ar[q], ai[q]);
+        }
+        if (ndim == 3) {
+            __syncthreads();
+            // z term, tiles [z][x] of one y (Nz == 16)
+            const int nB = Ny * txb;
+            for (int tile = wv; tile < nB; tile += NW) {
+                const int bx = tile % txb, y = tile / txb;
+                d4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
+                const int xo = bx * 16 + lr;
+                for (int k0 = 0; k0 < Nz; k0 += 4) {
+                    const int zp = k0 + lk;
+                    const int dd = lr - zp < 0 ? lr - zp + Nz : lr - zp;
+                    const double a = tab[2][dd];
+                    const double2 b = S[xo + px * y + pxy * zp];
+                    ar = mfma16(a, b.x, ar);
+                    ai = mfma16(a, b.y, ai);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double2 &o = O[xo + px * y + pxy * (lk + 4 * q)];
+                    o.x += ar[q];
+                    o.y += ai[q];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < 4096 / NTH; ++it) {
+            const int r = threadIdx.x + it * NTH;
+            if (r >= ns) break;
+            const int x = r % Nx, y = (r / Nx) % Ny, z = r / (Nx * Ny);
+            const int li = x + px * y + pxy * z;
+            const double2 kin = O[li], self = S[li], other = col[(1 - c) * ns + r];
+            const double w = U[r] - mu;
+            const double2 dl = *(const double2 *)(D + 2 * r);
+            if (c == 0) {
+                // top = T u + (U - mu) u + Delta v;  f = -i top
+                const double tr = kin.x + w * self.x + (dl.x * other.x - dl.y * other.y);
+                const double ti = kin.y + w * self.y + (dl.x * other.y + dl.y * other.x);
+                fcol[r] = make_double2(ti, -tr);
+            } else {
+                // bottom = Delta^* u - T v - (U - mu) v
+                const double br = (dl.x * other.x + dl.y * other.y) - kin.x - w * self.x;
+                const double bi = (dl.x * other.y - dl.y * other.x) - kin.y - w * self.y;
+                fcol[ns + r] = make_double2(bi, -br);
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Resume state kept at the head of the workspace: [count of valid history
 // entries, ring position of f_k].
 __global__ void td_set_header(int64_t *hdr, int64_t count, int64_t head) {
@@ -311,13 +450,25 @@ int td_evolve(const bdg_lattice *lat, const double *Vext, double mu, const bdg_t
         BDG_CHECK_LAUNCH();
         return 0;
     };
+    // the matrix-core kinetic term: 2-D sides that are multiples of 16, or 16^3
+    static const bool mfma_env = [] {
+        const char *v = getenv("BDG_TD_MFMA");
+        return !(v && v[0] == '0');
+    }();
+    const bool mfma_ok = mfma_env && ((lat->ndim == 2 && dims[0] % 16 == 0 && dims[1] % 16 == 0 &&
+                                       (dims[0] + 1) * dims[1] <= TD_MFMA_LDS) ||
+                                      (lat->ndim == 3 && dims[0] == 16 && dims[1] == 16 && dims[2] == 16));
     auto apply = [&](const double *X, int64_t ldx, double *Fo) -> int {
 #define BDG_TD_APPLY(MS, BYV, NTV)                                                                       \
     hipLaunchKernelGGL((td_apply<MS, BYV, NTV>), dim3((unsigned)m), dim3(NTV), 0, s, lat->ndim, dims[0], dims[1], \
                        dims[2], X, ldx, Uf, Df, mu, Fo, n)
-        // LDS sized for the lattice; 1024 threads (16 waves) hide the LDS
-        // latency when one state fills the CU's LDS
-        if (lat->ndim == 1) {
+        // matrix-core form where the lattice allows it; otherwise LDS sized
+        // for the lattice, 1024 threads (16 waves) hiding the LDS latency
+        // when one state fills the CU's LDS
+        if (mfma_ok) {
+            hipLaunchKernelGGL(td_apply_mfma, dim3((unsigned)m), dim3(TD_MFMA_NT), 0, s, lat->ndim, dims[0], dims[1],
+                               dims[2], X, ldx, Uf, Df, mu, Fo, n);
+        } else if (lat->ndim == 1) {
             if (ns <= 1024) BDG_TD_APPLY(1024, 1, 256);
             else BDG_TD_APPLY(4096, 1, 1024);
         } else {

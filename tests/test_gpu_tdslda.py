@@ -110,10 +110,12 @@ def test_largest_lattice_matches_oracle(dev):
     assert np.abs(got - ref).max() < 1e-12
 
 
-@pytest.mark.parametrize("dims", [(16, 8, 10), (12, 12, 12), (32, 36)])
+@pytest.mark.parametrize("dims", [(16, 8, 10), (12, 12, 12), (32, 36), (16, 16, 16), (48, 16), (32, 64)])
 def test_large_lattices_match_oracle(dev, dims):
-    """Lattices above 1024 sites (the 4096-site LDS variant of the apply kernel)
-    with odd and unequal sides; self-consistent fields, RK4 start + ABM."""
+    """Lattices above 1024 sites with odd and unequal sides (the 4096-site LDS
+    variant of the apply kernel) and lattices whose kinetic term runs on the
+    matrix cores (16^3, 2-D sides that are multiples of 16); self-consistent
+    fields, RK4 start + ABM."""
     rng = np.random.default_rng(sum(dims))
     ns = int(np.prod(dims))
     m = 12
