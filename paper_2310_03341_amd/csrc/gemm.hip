@@ -2,6 +2,7 @@
 #include "gemm.h"
 
 #include <math.h>
+#include <stdlib.h>
 
 namespace bdg {
 namespace {
@@ -121,14 +122,56 @@ __device__ inline void store_tile(T *__restrict__ S, const typename v2t<T>::type
     }
 }
 
+// Direct global -> LDS operand tiles (complex FP64, 64 x 16 elements per
+// tile).  One wave instruction moves 64 elements of 16 bytes to 64
+// consecutive LDS slots (lane l to slot base + l, the slot base in M0; checked
+// on gfx950 by an in-bounds probe), so the tile never passes through vector
+// registers.  Layouts, in elements:
+//   i-fast operands (column i contiguous in memory: A 'N', B 'C'):
+//     (i, k) at k * 64 + i, one instruction per k row;
+//   k-fast operands (k contiguous: A 'C', B 'N'): (i, k) at i * 16 + (k ^ (i & 15)),
+//     one instruction per four i rows; the XOR places the 16 rows that one
+//     MFMA operand read touches at one k in 16 different bank groups.
+// Elements outside the matrix are loaded from row or column 0 (any valid
+// address): rows beyond M or N only reach outputs that are never stored,
+// and K beyond the end is masked when the tile is read.
+__device__ inline int dslot(bool kfast, int i, int k) { return kfast ? i * 16 + (k ^ (i & 15)) : k * 64 + i; }
+
+__device__ inline void direct_tile(const double *__restrict__ P, int64_t ld, int64_t r0, int64_t MN, int64_t k0,
+                                   int64_t K, bool kfast, double *lds_tile, int wave, int lane) {
+    const unsigned lbase = (unsigned)(size_t)(__attribute__((address_space(3))) void *)lds_tile;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int q = wave + 4 * u;  // instruction q of 16
+        int i, k;
+        if (kfast) {
+            i = 4 * q + (lane >> 4);
+            k = (lane & 15) ^ (i & 15);
+        } else {
+            i = lane;
+            k = q;
+        }
+        int64_t gi = r0 + i, gk = k0 + k;
+        gi = gi < MN ? gi : 0;
+        gk = gk < K ? gk : 0;
+        const double *src = P + 2 * (kfast ? gk + gi * ld : gi + gk * ld);
+        const unsigned m0v = __builtin_amdgcn_readfirstlane(lbase + 1024u * (unsigned)q);
+        asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off"
+                     :: "v"(src), "s"(m0v) : "memory", "m0");
+    }
+}
+
+__device__ inline void wait_vm_direct() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // opA: false = 'N', true = 'C'.  opB likewise.
-template <typename T, bool CPLX, bool CA, bool CB, int MODE, int WB>
+template <typename T, bool CPLX, bool CA, bool CB, int MODE, int WB, bool DIRECT>
 __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk) {
     typedef Cfg<T, CPLX, WB> C;
     typedef typename acc4<T>::type A4;
     constexpr int EW = C::EW;
     constexpr int BM = C::BM, BN = C::BM, WT = 16 * WB;  // tile, and each wave's share of it
     static_assert(WB == 2 || (WB == 4 && !CPLX && MODE == GEMM_FULL), "large tiles: real, full mode");
+    static_assert(!DIRECT || (sizeof(T) == 8 && CPLX && WB == 2 && MODE != GEMM_HEMM_L), "direct tiles: complex FP64");
     __shared__ T As[2][C::BK * C::LDS_LD * EW];
     __shared__ T Bs[2][C::BK * C::LDS_LD * EW];
 
@@ -210,74 +253,144 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
         else store_tile<T, CPLX, WB, true>(Bs[buf], rb, bok, bcj);
     };
 
-    if (kbeg < kend) {
-        loadA(kbeg);
-        loadB(kbeg);
-        storeA(0, kbeg);
-        storeB(0);
-        __syncthreads();
-        int buf = 0;
-        for (int64_t k0 = kbeg; k0 < kend; k0 += C::BK) {
-            const int64_t kn = k0 + C::BK;
-            const bool more = kn < kend;
-            if (more) {
-                loadA(kn);
-                loadB(kn);
-            }
-            const T *as = As[buf];
-            const T *bs = Bs[buf];
+    if constexpr (DIRECT) {
+        // operand layouts: A 'C' and B 'N' are k-fast
+        constexpr bool kfA = CA, kfB = !CB;
+        auto compute_direct = [&](int buf, int64_t k0, bool tail) {
+            const double2 *as = (const double2 *)As[buf];
+            const double2 *bs = (const double2 *)Bs[buf];
 #pragma unroll
             for (int kk = 0; kk < C::BK; kk += 4) {
                 const int kr = kk + (lane >> 4);
+                const bool kin = !tail || (k0 + kr < kend);
                 T are[WB], aim[WB], bre[WB], bim[WB];
 #pragma unroll
                 for (int a = 0; a < WB; ++a) {
-                    const int idx = kr * C::LDS_LD + wm * WT + a * 16 + (lane & 15);
-                    if (CPLX) {
-                        are[a] = as[2 * idx];
-                        aim[a] = as[2 * idx + 1];
-                    } else {
-                        are[a] = as[idx];
-                        aim[a] = 0;
-                    }
+                    const double2 v = as[dslot(kfA, wm * WT + a * 16 + (lane & 15), kr)];
+                    are[a] = kin ? v.x : 0.0;
+                    aim[a] = kin ? (CA ? -v.y : v.y) : 0.0;
                 }
 #pragma unroll
                 for (int b = 0; b < WB; ++b) {
-                    const int idx = kr * C::LDS_LD + wn * WT + b * 16 + (lane & 15);
-                    if (CPLX) {
-                        bre[b] = bs[2 * idx];
-                        bim[b] = bs[2 * idx + 1];
-                    } else {
-                        bre[b] = bs[idx];
-                        bim[b] = 0;
-                    }
+                    const double2 v = bs[dslot(kfB, wn * WT + b * 16 + (lane & 15), kr)];
+                    bre[b] = kin ? v.x : 0.0;
+                    bim[b] = kin ? (CB ? -v.y : v.y) : 0.0;
                 }
+                T as2[WB], bs2[WB];
+#pragma unroll
+                for (int a = 0; a < WB; ++a) as2[a] = are[a] + aim[a];
+#pragma unroll
+                for (int b = 0; b < WB; ++b) bs2[b] = bre[b] + bim[b];
 #pragma unroll
                 for (int a = 0; a < WB; ++a)
 #pragma unroll
                     for (int b = 0; b < WB; ++b) accR[a][b] = mfma16(are[a], bre[b], accR[a][b]);
-                if (CPLX) {
-                    T as2[WB], bs2[WB];
 #pragma unroll
-                    for (int a = 0; a < WB; ++a) as2[a] = are[a] + aim[a];
+                for (int a = 0; a < WB; ++a)
 #pragma unroll
-                    for (int b = 0; b < WB; ++b) bs2[b] = bre[b] + bim[b];
+                    for (int b = 0; b < WB; ++b)
+                        accI[CPLX ? a : 0][CPLX ? b : 0] = mfma16(aim[a], bim[b], accI[CPLX ? a : 0][CPLX ? b : 0]);
 #pragma unroll
-                    for (int a = 0; a < (CPLX ? WB : 1); ++a)
+                for (int a = 0; a < WB; ++a)
 #pragma unroll
-                        for (int b = 0; b < (CPLX ? WB : 1); ++b) accI[a][b] = mfma16(aim[a], bim[b], accI[a][b]);
-#pragma unroll
-                    for (int a = 0; a < (CPLX ? WB : 1); ++a)
-#pragma unroll
-                        for (int b = 0; b < (CPLX ? WB : 1); ++b) acc3[a][b] = mfma16(as2[a], bs2[b], acc3[a][b]);
-                }
+                    for (int b = 0; b < WB; ++b)
+                        acc3[CPLX ? a : 0][CPLX ? b : 0] = mfma16(as2[a], bs2[b], acc3[CPLX ? a : 0][CPLX ? b : 0]);
             }
-            if (more) {
-                storeA(buf ^ 1, kn);
-                storeB(buf ^ 1);
-            }
+        };
+        auto issue = [&](int buf, int64_t k0) {
+            direct_tile((const double *)A, g.lda, m0, g.M, k0, kend, kfA, (double *)As[buf], wave, lane);
+            direct_tile((const double *)B, g.ldb, n0, g.N, k0, kend, kfB, (double *)Bs[buf], wave, lane);
+        };
+        if (kbeg < kend) {
+            // full K tiles in the loop, a partial last tile after it
+            const int64_t kfull = kbeg + (kend - kbeg) / C::BK * C::BK;
+            issue(0, kbeg);
+            wait_vm_direct();
             __syncthreads();
-            buf ^= 1;
+            int buf = 0;
+            int64_t k0 = kbeg;
+            for (; k0 < kfull; k0 += C::BK) {
+                const int64_t kn = k0 + C::BK;
+                const bool more = kn < kend;
+                // the other buffer was last read before the barrier that ended the previous step
+                if (more) issue(buf ^ 1, kn);
+                compute_direct(buf, k0, false);
+                if (more) wait_vm_direct();
+                __syncthreads();
+                buf ^= 1;
+            }
+            if (k0 < kend) compute_direct(buf, k0, true);
+        }
+    } else {
+        if (kbeg < kend) {
+            loadA(kbeg);
+            loadB(kbeg);
+            storeA(0, kbeg);
+            storeB(0);
+            __syncthreads();
+            int buf = 0;
+            for (int64_t k0 = kbeg; k0 < kend; k0 += C::BK) {
+                const int64_t kn = k0 + C::BK;
+                const bool more = kn < kend;
+                if (more) {
+                    loadA(kn);
+                    loadB(kn);
+                }
+                const T *as = As[buf];
+                const T *bs = Bs[buf];
+    #pragma unroll
+                for (int kk = 0; kk < C::BK; kk += 4) {
+                    const int kr = kk + (lane >> 4);
+                    T are[WB], aim[WB], bre[WB], bim[WB];
+    #pragma unroll
+                    for (int a = 0; a < WB; ++a) {
+                        const int idx = kr * C::LDS_LD + wm * WT + a * 16 + (lane & 15);
+                        if (CPLX) {
+                            are[a] = as[2 * idx];
+                            aim[a] = as[2 * idx + 1];
+                        } else {
+                            are[a] = as[idx];
+                            aim[a] = 0;
+                        }
+                    }
+    #pragma unroll
+                    for (int b = 0; b < WB; ++b) {
+                        const int idx = kr * C::LDS_LD + wn * WT + b * 16 + (lane & 15);
+                        if (CPLX) {
+                            bre[b] = bs[2 * idx];
+                            bim[b] = bs[2 * idx + 1];
+                        } else {
+                            bre[b] = bs[idx];
+                            bim[b] = 0;
+                        }
+                    }
+    #pragma unroll
+                    for (int a = 0; a < WB; ++a)
+    #pragma unroll
+                        for (int b = 0; b < WB; ++b) accR[a][b] = mfma16(are[a], bre[b], accR[a][b]);
+                    if (CPLX) {
+                        T as2[WB], bs2[WB];
+    #pragma unroll
+                        for (int a = 0; a < WB; ++a) as2[a] = are[a] + aim[a];
+    #pragma unroll
+                        for (int b = 0; b < WB; ++b) bs2[b] = bre[b] + bim[b];
+    #pragma unroll
+                        for (int a = 0; a < (CPLX ? WB : 1); ++a)
+    #pragma unroll
+                            for (int b = 0; b < (CPLX ? WB : 1); ++b) accI[a][b] = mfma16(aim[a], bim[b], accI[a][b]);
+    #pragma unroll
+                        for (int a = 0; a < (CPLX ? WB : 1); ++a)
+    #pragma unroll
+                            for (int b = 0; b < (CPLX ? WB : 1); ++b) acc3[a][b] = mfma16(as2[a], bs2[b], acc3[a][b]);
+                    }
+                }
+                if (more) {
+                    storeA(buf ^ 1, kn);
+                    storeB(buf ^ 1);
+                }
+                __syncthreads();
+                buf ^= 1;
+            }
         }
     }
 
@@ -428,7 +541,16 @@ int launch(const GemmArgs &g, hipStream_t s) {
         grid = dim3((unsigned)tm, (unsigned)tn, splitk);
     }
     if (tm <= 0 || tn <= 0) return 0;
-    hipLaunchKernelGGL((gemm_kernel<T, CPLX, CA, CB, MODE, WB>), grid, dim3(NT), 0, s, h, kchunk);
+    // complex FP64 tiles without index maps load straight into LDS
+    constexpr bool DIRECT_OK = sizeof(T) == 8 && CPLX && WB == 2 && MODE != GEMM_HEMM_L;
+    static const bool direct_env = [] {
+        const char *v = getenv("BDG_GEMM_DIRECT");
+        return !(v && v[0] == '0');
+    }();
+    if (DIRECT_OK && direct_env && !g.acol && !g.brow)
+        hipLaunchKernelGGL((gemm_kernel<T, CPLX, CA, CB, MODE, WB, DIRECT_OK>), grid, dim3(NT), 0, s, h, kchunk);
+    else
+        hipLaunchKernelGGL((gemm_kernel<T, CPLX, CA, CB, MODE, WB, false>), grid, dim3(NT), 0, s, h, kchunk);
     BDG_CHECK_LAUNCH();
     if (splitk > 1) {
         const int64_t total = g.M * g.N;
