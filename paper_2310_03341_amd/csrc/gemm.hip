@@ -171,7 +171,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
     constexpr int EW = C::EW;
     constexpr int BM = C::BM, BN = C::BM, WT = 16 * WB;  // tile, and each wave's share of it
     static_assert(WB == 2 || (WB == 4 && !CPLX && MODE == GEMM_FULL), "large tiles: real, full mode");
-    static_assert(!DIRECT || (sizeof(T) == 8 && CPLX && WB == 2 && MODE != GEMM_HEMM_L), "direct tiles: complex FP64");
+    static_assert(!DIRECT || (sizeof(T) == 8 && CPLX && WB == 2), "direct tiles: complex FP64");
     __shared__ T As[2][C::BK * C::LDS_LD * EW];
     __shared__ T Bs[2][C::BK * C::LDS_LD * EW];
 
@@ -254,9 +254,24 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
     };
 
     if constexpr (DIRECT) {
-        // operand layouts: A 'C' and B 'N' are k-fast
-        constexpr bool kfA = CA, kfB = !CB;
+        // operand layouts: A 'C' and B 'N' are k-fast.  HEMM_L: A tiles below
+        // the diagonal block are i-fast, above it k-fast and conjugated (the
+        // stored lower triangle read transposed); the four tiles of the
+        // diagonal block go through registers (load_tile picks each element
+        // from the stored triangle) and are stored i-fast, conjugation done.
+        constexpr bool kfB = !CB;
+        auto a_layout = [&](int64_t k0, bool &kf, bool &cj) {
+            if (MODE == GEMM_HEMM_L) {
+                kf = k0 >= m0 + BM;
+                cj = kf;
+            } else {
+                kf = CA;
+                cj = CA;
+            }
+        };
         auto compute_direct = [&](int buf, int64_t k0, bool tail) {
+            bool kfA, cjA;
+            a_layout(k0, kfA, cjA);
             const double2 *as = (const double2 *)As[buf];
             const double2 *bs = (const double2 *)Bs[buf];
 #pragma unroll
@@ -268,7 +283,7 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
                 for (int a = 0; a < WB; ++a) {
                     const double2 v = as[dslot(kfA, wm * WT + a * 16 + (lane & 15), kr)];
                     are[a] = kin ? v.x : 0.0;
-                    aim[a] = kin ? (CA ? -v.y : v.y) : 0.0;
+                    aim[a] = kin ? (cjA ? -v.y : v.y) : 0.0;
                 }
 #pragma unroll
                 for (int b = 0; b < WB; ++b) {
@@ -297,14 +312,35 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
                         acc3[CPLX ? a : 0][CPLX ? b : 0] = mfma16(as2[a], bs2[b], acc3[CPLX ? a : 0][CPLX ? b : 0]);
             }
         };
+        bool stagedA = false;  // a diagonal-block A tile waits in ra for its LDS store
         auto issue = [&](int buf, int64_t k0) {
-            direct_tile((const double *)A, g.lda, m0, g.M, k0, kend, kfA, (double *)As[buf], wave, lane);
+            if (MODE == GEMM_HEMM_L && k0 + C::BK > m0 && k0 < m0 + BM) {
+                load_tile<T, CPLX, WB, false, false>(A, g.lda, m0, k0, g.M, kend, ra, aok, acj, true);
+                stagedA = true;
+            } else {
+                bool kfA, cjA;
+                a_layout(k0, kfA, cjA);
+                direct_tile((const double *)A, g.lda, m0, g.M, k0, kend, kfA, (double *)As[buf], wave, lane);
+            }
             direct_tile((const double *)B, g.ldb, n0, g.N, k0, kend, kfB, (double *)Bs[buf], wave, lane);
+        };
+        auto store_staged = [&](int buf) {
+            if (MODE != GEMM_HEMM_L || !stagedA) return;
+            stagedA = false;
+            double2 *dst = (double2 *)As[buf];
+            const int t = threadIdx.x;
+#pragma unroll
+            for (int j = 0; j < C::PER_THREAD; ++j) {
+                const int i = t % C::BM, k = t / C::BM + (NT / C::BM) * j;  // load_tile's i-fast assignment
+                const bool ok = (aok >> j) & 1u, cj = (acj >> j) & 1u;
+                dst[k * 64 + i] = make_double2(ok ? ra[j].x : 0.0, ok ? (cj ? -ra[j].y : ra[j].y) : 0.0);
+            }
         };
         if (kbeg < kend) {
             // full K tiles in the loop, a partial last tile after it
             const int64_t kfull = kbeg + (kend - kbeg) / C::BK * C::BK;
             issue(0, kbeg);
+            store_staged(0);
             wait_vm_direct();
             __syncthreads();
             int buf = 0;
@@ -315,7 +351,10 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
                 // the other buffer was last read before the barrier that ended the previous step
                 if (more) issue(buf ^ 1, kn);
                 compute_direct(buf, k0, false);
-                if (more) wait_vm_direct();
+                if (more) {
+                    store_staged(buf ^ 1);
+                    wait_vm_direct();
+                }
                 __syncthreads();
                 buf ^= 1;
             }
@@ -542,7 +581,7 @@ int launch(const GemmArgs &g, hipStream_t s) {
     }
     if (tm <= 0 || tn <= 0) return 0;
     // complex FP64 tiles without index maps load straight into LDS
-    constexpr bool DIRECT_OK = sizeof(T) == 8 && CPLX && WB == 2 && MODE != GEMM_HEMM_L;
+    constexpr bool DIRECT_OK = sizeof(T) == 8 && CPLX && WB == 2;
     static const bool direct_env = [] {
         const char *v = getenv("BDG_GEMM_DIRECT");
         return !(v && v[0] == '0');
