@@ -448,22 +448,33 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
         wave_copy_to_lds<F>(TF + 2 * ((S * tmax + t) * NBK * NBK + wave * TQ), &Ts[bufn][wave * TQ], TQ, lane);
     };
     // complex offset of Z entry (row, this lane's column)
-    auto zoff = [&](int64_t row) -> int64_t { return RM ? row * ldz + col : row + col * ldz; };
-    // raw loads of one Z tile; ok bits for its 4 entries in zmask
+    // Z entry (row, this lane's column) = zl[row * rstr]: zl holds the lane's
+    // column, rstr is the row stride; the four rows a lane holds in a tile
+    // differ by per-lane constants, so an address costs one add of a uniform
+    // row offset (no 64-bit multiply per element).
+    const int64_t rstr = RM ? ldz : 1;
+    const F *zl = Z + 2 * (RM ? col : col * ldz);
+    int64_t lrow[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) lrow[q] = 2 * (int64_t)mfma_row((F)0, lane, q) * rstr;
+    // raw loads of one Z tile (rows outside the matrix read the lane's row 0 of
+    // the tile block and are zeroed later); ok bits for its 4 entries in zmask
     auto fetch_tile = [&](int64_t rs1, int rtl, int h1, CV *raw, unsigned &zmask, int bit0) {
+        const F *base = zl + 2 * (rs1 + rtl * 16) * rstr;  // uniform part
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int row = rtl * 16 + mfma_row((F)0, lane, q);
             const bool ok = (row < h1) & colok;
-            raw[q] = ld2<F>(Z + (int64_t)ok * (2 * zoff(rs1 + row)));
+            raw[q] = ld2<F>(ok ? base + lrow[q] : Z);
             zmask |= (unsigned)ok << (bit0 + q);
         }
     };
     auto put_tile = [&](int64_t rs1, int rtl, int h1, const A4 &tr, const A4 &ti) {
+        F *base = (F *)zl + 2 * (rs1 + rtl * 16) * rstr;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int row = rtl * 16 + mfma_row((F)0, lane, q);
-            if (row < h1 && colok) st2<F>(Z + 2 * zoff(rs1 + row), mk2<F>(tr[q], ti[q]));
+            if (row < h1 && colok) st2<F>(base + lrow[q], mk2<F>(tr[q], ti[q]));
         }
     };
     for (int64_t S = nsb - 1; S >= 0; --S) {
