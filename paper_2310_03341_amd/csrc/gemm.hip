@@ -253,6 +253,17 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
         else store_tile<T, CPLX, WB, true>(Bs[buf], rb, bok, bcj);
     };
 
+    // C entry (row block a, column block b, element q) of this lane: offset and
+    // whether it lies inside the matrix (split-K partials excluded)
+    auto c_off = [&](int a, int b, int q, bool &ok) -> int64_t {
+        const int64_t col = n0 + wn * WT + b * 16 + (lane & 15);
+        const int64_t row = m0 + wm * WT + a * 16 + mfma_row((T)0, lane, q);
+        ok = (row < g.M) & (col < g.N);
+        return ok ? row + (g.ccol ? (int64_t)g.ccol[col] : col) * g.ldc : 0;
+    };
+    constexpr bool CEARLY = DIRECT && MODE != GEMM_HEMM_L;  // HEMM tiles have no registers to spare
+    const bool c_early = CEARLY && g.splitk <= 1 && !((T)g.beta_re == (T)0 && (T)g.beta_im == (T)0);
+    typename v2t<T>::type preC[CEARLY ? WB : 1][CEARLY ? WB : 1][4];
     if constexpr (DIRECT) {
         // operand layouts: A 'C' and B 'N' are k-fast.  HEMM_L: A tiles below
         // the diagonal block are i-fast, above it k-fast and conjugated (the
@@ -343,6 +354,19 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
             store_staged(0);
             wait_vm_direct();
             __syncthreads();
+            // C (beta != 0) is read now, so that its latency passes behind the first K tile
+            if (c_early) {
+#pragma unroll
+                for (int a = 0; a < WB; ++a)
+#pragma unroll
+                    for (int b = 0; b < WB; ++b)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            bool ok;
+                            const int64_t off = c_off(a, b, q, ok);
+                            preC[CEARLY ? a : 0][CEARLY ? b : 0][q] = ld2<T>(Cm + 2 * off);
+                        }
+            }
             int buf = 0;
             int64_t k0 = kbeg;
             for (; k0 < kfull; k0 += C::BK) {
@@ -466,7 +490,15 @@ __global__ __launch_bounds__(NT, 2) void gemm_kernel(GemmArgs g, int64_t kchunk)
             }
         }
         T oldr[WB][4], oldi[WB][4];
-        if (!to_part && !beta0) {
+        if (CEARLY && c_early) {
+#pragma unroll
+            for (int b = 0; b < WB; ++b)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    oldr[b][q] = preC[CEARLY ? a : 0][CEARLY ? b : 0][q].x;
+                    oldi[b][q] = preC[CEARLY ? a : 0][CEARLY ? b : 0][q].y;
+                }
+        } else if (!to_part && !beta0) {
 #pragma unroll
             for (int b = 0; b < WB; ++b)
 #pragma unroll
