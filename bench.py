@@ -276,6 +276,35 @@ def bench_int8_gemm(api, torch, dev, progress, M=8192, N=8192, K=8192, slices=8,
             "max_rel_diff": float((C8 - C64).abs().max() / C64.abs().max())}
 
 
+def bench_bt2_alone(api, torch, dev, progress, n=27648, m=13824, band=64):
+    """The back-transformation 2 alone at the solver's shape (n = 27648, the
+    13824 back-transformed columns of the particle-hole mirror), for counter
+    runs that must not go through stage 2's launch loop.  Reflectors are
+    synthetic with tau = 0: the apply kernel's loads, products and stores do
+    not depend on the values, and Z stays finite.  One call of the stage."""
+    import numpy as np
+    torch.manual_seed(0)
+    T = (n - 2 - np.arange(n - 2, dtype=np.int64)) // band + 1
+    voff_h = np.zeros(n + 1, dtype=np.int64)
+    voff_h[1:n - 2] = np.cumsum(T)[:-1]
+    nrefl = int(T.sum())
+    voff = torch.from_numpy(voff_h).to(dev)
+    V2 = (torch.randn((nrefl + 1) * band, dtype=torch.complex128, device=dev) * 0.02)
+    tau2 = torch.zeros(nrefl + 1, dtype=torch.float64, device=dev)
+    e = torch.randn(n, dtype=torch.complex128, device=dev)
+    Y = api.colmajor(n, n, torch.float64, dev)
+    Y.copy_(torch.randn(n, n, dtype=torch.float64, device=dev))
+    torch.cuda.synchronize()
+    progress("back-transformation 2 alone, n=%d, %d columns" % (n, m))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    Z = api.stage_bt2(e, Y, n - m, m, V2, tau2, voff, band, rowmajor=True)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) / 1e3
+    return {"n": n, "m_bt": m, "band": band, "stage_s": round(t, 4), "finite": bool(torch.isfinite(Z).all())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,7 +327,7 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy (read 1 GiB, write 1 GiB) before the solves, "
                          "as the reference point for HBM byte counters")
-    ap.add_argument("--only", choices=["tdslda", "onestage", "int8gemm"], default=None,
+    ap.add_argument("--only", choices=["tdslda", "onestage", "int8gemm", "bt2"], default=None,
                     help="run one side measurement alone and print its JSON (for profiling)")
     ap.add_argument("--jsonl", type=str, default="",
                     help="also append the result line, with a UTC time stamp and the command line, "
@@ -317,6 +346,12 @@ def main():
 
     dev = torch.device("cuda:0")
     dims = tuple(args.dims)
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)  # one elementwise kernel: 1 GiB read, 1 GiB written
+        torch.cuda.synchronize()
+        del src, dst
     if args.only:
         def say(msg):
             print("[bench] " + msg, file=sys.stderr, flush=True)
@@ -324,6 +359,8 @@ def main():
             res = bench_tdslda(api, inputs, torch, dev, say)
         elif args.only == "onestage":
             res = bench_onestage(api, inputs, torch, dev, say, dims)
+        elif args.only == "bt2":
+            res = bench_bt2_alone(api, torch, dev, say)
         else:
             res = bench_int8_gemm(api, torch, dev, say)
         print(json.dumps({args.only: res}))
@@ -352,13 +389,6 @@ def main():
     def step():
         api.assemble(w.dims, U, D, w.mu, out=H)
         return solver(H, lo, hi, W, Z)
-
-    if args.calib_copy:
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.neg(src, out=dst)  # one elementwise kernel: 1 GiB read, 1 GiB written
-        torch.cuda.synchronize()
-        del src, dst
 
     def progress(msg):
         print("[bench] " + msg, file=sys.stderr, flush=True)
