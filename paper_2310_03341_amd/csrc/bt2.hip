@@ -28,7 +28,15 @@ constexpr int HT = 6;       // 16-row tiles covering HMAX (<= 96 rows)
 constexpr int VLD = 97;     // LDS leading dimension of V (padding avoids bank conflicts)
 constexpr int SLAB = 64;    // columns of Z per workgroup (16 per wave)
 
-// Phase vector: ph_0 = 1, ph_{i+1} = ph_i e_i / |e_i| (renormalised); |e| out.
+// |e_i| of the complex sub-diagonal, one thread per entry (the same hypot as
+// the phase scan).
+__global__ void abs_kernel(int64_t n, const double *__restrict__ e_cplx, double *__restrict__ e_abs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i + 1 < n) e_abs[i] = hypot(e_cplx[2 * i], e_cplx[2 * i + 1]);
+}
+
+// Phase vector: ph_0 = 1, ph_{i+1} = ph_i e_i / |e_i| (renormalised); |e| out
+// unless e_abs is null.
 __global__ void phases_kernel(int64_t n, const double *__restrict__ e_cplx, double *__restrict__ ph,
                               double *__restrict__ e_abs) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
@@ -38,7 +46,7 @@ __global__ void phases_kernel(int64_t n, const double *__restrict__ e_cplx, doub
     for (int64_t i = 0; i + 1 < n; ++i) {
         const double er = e_cplx[2 * i], ei = e_cplx[2 * i + 1];
         const double a = hypot(er, ei);
-        e_abs[i] = a;
+        if (e_abs) e_abs[i] = a;
         if (a > 0.0) {
             const double ur = er / a, ui = ei / a;
             const double nr = pr * ur - pi * ui, ni = pr * ui + pi * ur;
@@ -728,6 +736,19 @@ size_t bt2_workspace(int64_t n, int b) { return 16 * (size_t)bt2_nblocks(n, b) *
 
 int phases(int64_t n, const double *e_cplx, double *ph, double *e_abs, hipStream_t s) {
     hipLaunchKernelGGL(phases_kernel, dim3(1), dim3(64), 0, s, n, e_cplx, ph, e_abs);
+    BDG_CHECK_LAUNCH();
+    return 0;
+}
+
+int phase_abs(int64_t n, const double *e_cplx, double *e_abs, hipStream_t s) {
+    if (n < 2) return 0;
+    hipLaunchKernelGGL(abs_kernel, dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s, n, e_cplx, e_abs);
+    BDG_CHECK_LAUNCH();
+    return 0;
+}
+
+int phase_scan(int64_t n, const double *e_cplx, double *ph, hipStream_t s) {
+    hipLaunchKernelGGL(phases_kernel, dim3(1), dim3(64), 0, s, n, e_cplx, ph, (double *)nullptr);
     BDG_CHECK_LAUNCH();
     return 0;
 }

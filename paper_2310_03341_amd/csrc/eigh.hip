@@ -72,6 +72,37 @@ __global__ void nonfinite_lower(int64_t n, const double *__restrict__ A, int64_t
     if (bad) atomicOr(flag, 1);
 }
 
+// The phase scan (one thread, sequential over the sub-diagonal) runs on the
+// side stream beside the divide and conquer: it reads the complex sub-diagonal
+// and writes the phase vector, which only the phase scaling after the D&C
+// reads; the D&C itself needs |e| only (phase_abs, on the caller's stream).
+struct SideScan {
+    hipEvent_t ready = nullptr, done = nullptr;
+    ~SideScan() {
+        if (ready) (void)hipEventDestroy(ready);
+        if (done) (void)hipEventDestroy(done);
+    }
+    int start(int64_t n, const double *ec, double *ph, hipStream_t s) {
+        hipStream_t s2 = side_stream();
+        if (!s2 || hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
+            if (done) (void)hipEventDestroy(done);
+            done = nullptr;
+            return phase_scan(n, ec, ph, s);  // in order on the caller's stream
+        }
+        BDG_HIP(hipEventRecord(ready, s));
+        BDG_HIP(hipStreamWaitEvent(s2, ready, 0));
+        BDG_TRY(phase_scan(n, ec, ph, s2));
+        BDG_HIP(hipEventRecord(done, s2));
+        return 0;
+    }
+    // the caller's stream waits for the scan
+    int join(hipStream_t s) {
+        if (done) BDG_HIP(hipStreamWaitEvent(s, done, 0));
+        return 0;
+    }
+};
+
 struct Timer {
     hipStream_t s;
     hipEvent_t ev[12];
@@ -270,9 +301,15 @@ int eigh_mixed(int64_t n, double *A, int64_t lda, double emin, double emax, doub
         BDG_HIP(hipStreamSynchronize(s));
     }
     BDG_TRY(hb2st(n, b, AB, L.ldab, V2, tau2, d, ec, s));
-    BDG_TRY(phases(n, ec, ph, ea, s));
+    BDG_TRY(phase_abs(n, ec, ea, s));
+    SideScan scan;
+    BDG_TRY(scan.start(n, ec, ph, s));
     tm.mark(3, "hb2st");
-    BDG_TRY(stedc(n, d, ea, W2, Y, n, scratch, s, leaf));
+    {
+        const int rc = stedc(n, d, ea, W2, Y, n, scratch, s, leaf);
+        BDG_TRY(scan.join(s));
+        BDG_TRY(rc);
+    }
     tm.mark(4, "stedc");
     // FP32 basis: all columns, or the E >= 0 half and its particle-hole partners
     const int64_t c0 = ph_mirror ? n / 2 : 0;
@@ -452,10 +489,16 @@ int eigh(int64_t n, double *A, int64_t lda, double emin, double emax, double *W,
         BDG_HIP(hipStreamSynchronize(s));  // vh goes out of scope
     }
     BDG_TRY(hb2st(n, b, AB, L.ldab, V2, tau2, d, ec, s));
-    BDG_TRY(phases(n, ec, ph, ea, s));
+    BDG_TRY(phase_abs(n, ec, ea, s));
+    SideScan scan;
+    BDG_TRY(scan.start(n, ec, ph, s));
     tm.mark(3, "hb2st");
     // ---- tridiagonal divide and conquer
-    BDG_TRY(stedc(n, d, ea, W2, Y, n, scratch, s, leaf));
+    {
+        const int rc = stedc(n, d, ea, W2, Y, n, scratch, s, leaf);
+        BDG_TRY(scan.join(s));
+        BDG_TRY(rc);
+    }
     tm.mark(4, "stedc");
     // ---- window
     std::vector<double> wh((size_t)n);

@@ -20,12 +20,10 @@
 #include "stages.h"
 
 namespace bdg {
-namespace {
 
-constexpr int PQ_ROWS = 256;  // rows per workgroup in the panel kernels
-
-// One non-blocking side stream per device for the look-ahead panel (default
-// priority), created on first use and kept for the life of the process.
+// One non-blocking side stream per device (default priority), created on first
+// use and kept for the life of the process: stage 1's look-ahead panels, and
+// the phase scan that runs beside the divide and conquer.
 hipStream_t side_stream() {
     static std::mutex mu;
     static hipStream_t st[64] = {};
@@ -35,6 +33,10 @@ hipStream_t side_stream() {
     if (!st[dev] && hipStreamCreateWithFlags(&st[dev], hipStreamNonBlocking) != hipSuccess) st[dev] = nullptr;
     return st[dev];
 }
+
+namespace {
+
+constexpr int PQ_ROWS = 256;  // rows per workgroup in the panel kernels
 
 struct Events {
     hipEvent_t upd = nullptr, panel = nullptr;

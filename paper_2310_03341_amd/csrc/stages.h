@@ -38,8 +38,15 @@ size_t stedc_workspace(int64_t n);
 int stedc(int64_t n, const double *d, const double *e, double *lam_out, double *Q_out, int64_t ldq,
           void *work, hipStream_t s, int leaf);
 
+// The library's side stream on the current device (nullptr if it cannot be created).
+hipStream_t side_stream();
+
 // Phase scaling of the complex sub-diagonal and back-transformation 2.
+// phases = phase_abs (|e|, what the divide and conquer needs) + phase_scan
+// (the phase vector, needed only by the scaling after it).
 int phases(int64_t n, const double *e_cplx, double *ph, double *e_abs, hipStream_t s);
+int phase_abs(int64_t n, const double *e_cplx, double *e_abs, hipStream_t s);
+int phase_scan(int64_t n, const double *e_cplx, double *ph, hipStream_t s);
 int phase_scale(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, double *Z,
                 int64_t ldz, hipStream_t s);
 int phase_scale(int64_t n, int64_t m, const double *Y, int64_t i0, const double *ph, float *Z,
