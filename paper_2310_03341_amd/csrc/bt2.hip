@@ -485,6 +485,31 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
             if (row < h1 && colok) st2<F>(base + lrow[q], mk2<F>(tr[q], ti[q]));
         }
     };
+    // Tiles that lie wholly inside the matrix (every window but the last of
+    // each sweep block, when the workgroup's 64 columns exist): a wave-uniform
+    // base address plus this lane's 32-bit byte offset, so each load or store
+    // costs one instruction with a scalar base and no bounds selects.  The
+    // offsets stay below 2^32 for every n the workspace can hold.
+    const bool cols_full = j0 + SLAB <= m;
+    uint32_t lofs[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        lofs[q] = (uint32_t)sizeof(CV) *
+                  (uint32_t)(RM ? (int64_t)mfma_row((F)0, lane, q) * ldz + (wave * 16 + li)
+                                : (int64_t)mfma_row((F)0, lane, q) + (int64_t)(wave * 16 + li) * ldz);
+    auto tile_base = [&](int64_t row0) {
+        return (char *)Z + sizeof(CV) * (RM ? row0 * ldz + j0 : row0 + j0 * ldz);
+    };
+    auto fetch_tile_full = [&](int64_t rs1, int rtl, CV *raw) {
+        const char *base = tile_base(rs1 + rtl * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) raw[q] = ld2<F>((const F *)(base + lofs[q]));
+    };
+    auto put_tile_full = [&](int64_t rs1, int rtl, const A4 &tr, const A4 &ti) {
+        char *base = tile_base(rs1 + rtl * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st2<F>((F *)(base + lofs[q]), mk2<F>(tr[q], ti[q]));
+    };
     for (int64_t S = nsb - 1; S >= 0; --S) {
         const int64_t s0 = S * NBK;
         const int64_t T0 = (n - 2 - s0) / b + 1;
@@ -586,10 +611,16 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
             // now, behind this block's W = V^H Z: issued at the start of the
             // block, right after the previous block's stores and beside the
             // V/T loads, the same loads made the launch 2.7 % slower.
+            const bool nfull = cols_full && n - (rs + b) >= HT * 16;  // window of block t + 1 inside
             if (more) {
-                const int h1 = (int)min((int64_t)(HT * 16), n - (rs + b));
+                if (nfull) {
 #pragma unroll
-                for (int k = 0; k < SHIFT; ++k) fetch_tile(rs + b, HT - SHIFT + k, h1, zraw[k], zmask, 4 * k);
+                    for (int k = 0; k < SHIFT; ++k) fetch_tile_full(rs + b, HT - SHIFT + k, zraw[k]);
+                } else {
+                    const int h1 = (int)min((int64_t)(HT * 16), n - (rs + b));
+#pragma unroll
+                    for (int k = 0; k < SHIFT; ++k) fetch_tile(rs + b, HT - SHIFT + k, h1, zraw[k], zmask, 4 * k);
+                }
             }
             // W2 = T W (T upper triangular), stored negated:
             // Re = Q1 - Q2, Im = Q3 - Q1 - Q2, Q1 = sum tr wr, Q2 = sum ti wi,
@@ -695,7 +726,7 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
                 for (int k = 0; k < SHIFT; ++k) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
-                        const bool ok = (zmask >> (4 * k + q)) & 1u;
+                        const bool ok = nfull || ((zmask >> (4 * k + q)) & 1u);
                         F a = ok ? zraw[k][q].x : (F)0, c = ok ? zraw[k][q].y : (F)0;
                         // pins the selects (and the wait for the loads) here
                         asm volatile("" : "+v"(a), "+v"(c)::"memory");
@@ -704,8 +735,13 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
                     }
                 }
                 wait_vm_all();  // the direct LDS loads of block t + 1 (nothing else is pending)
+                if (cols_full && h == HT * 16) {
 #pragma unroll
-                for (int k = 0; k < SHIFT; ++k) put_tile(rs, k, h, zr[k], zi[k]);
+                    for (int k = 0; k < SHIFT; ++k) put_tile_full(rs, k, zr[k], zi[k]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < SHIFT; ++k) put_tile(rs, k, h, zr[k], zi[k]);
+                }
 #pragma unroll
                 for (int k = 0; k + SHIFT < HT; ++k) {
                     zr[k] = zr[k + SHIFT];
