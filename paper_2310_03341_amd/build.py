@@ -27,6 +27,11 @@ HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
 # combine them with vector arithmetic, which AGPRs would need copies for.
 EXTRA_FLAGS = {name: ["-mllvm", "-amdgpu-mfma-vgpr-form"]
                for name in ("bt2.hip", "gemm.hip", "he2hb.hip", "refine.hip")}
+# The back-transformation-2 ring kernel unrolls its block loop by three; its
+# product loops must still unroll fully (their tile and accumulator indices
+# become constants, which keeps those arrays in registers), which needs a
+# larger size limit for pragma-requested unrolling than the default.
+EXTRA_FLAGS["bt2.hip"] = EXTRA_FLAGS["bt2.hip"] + ["-mllvm", "-pragma-unroll-threshold=1000000"]
 
 
 def _compile(src: str) -> str:

@@ -16,6 +16,8 @@
 // G(S, 1), ... in that order.  Columns of Z are independent: each workgroup
 // owns a slab of columns and streams all blocks through LDS.
 #include "gemm.h"
+#include <stdlib.h>
+#include <type_traits>
 #include "stages.h"
 
 namespace bdg {
@@ -762,6 +764,312 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
     }
 }
 
+// Sixteen zero bytes that Z entries outside the matrix are loaded from, and a
+// sink their stores go to, so a tile load or store is always the same four
+// instructions (no branch, no select).
+__device__ __align__(16) double kZeroPad[2] = {0.0, 0.0};
+__device__ __align__(16) double kSinkPad[2];
+
+// Band width 64 (SHIFT = 4) variant of the pipelined kernel.  The window's
+// six 16-row tiles live in a ring of six register slots: logical tile i of
+// block t is slot (4 t + i) mod 6, so the four tiles a block hands back are
+// the slots that receive the four tiles the next block adds.  Each outgoing
+// tile is stored right after its last update and its slot is refilled at
+// once with the next window's tile, straight from memory: no registers hold
+// prefetched tiles, and nothing is copied at the end of a block step.  The
+// slot map repeats every three blocks, so the block loop is unrolled by three
+// with the map as a compile-time constant.  The window is kept as complex
+// pairs, the layout a 16-byte load delivers.
+//
+// Counter discipline: the V/T fetch for block t + 1 is issued after the
+// block's W product, and it is followed by exactly 32 vector memory
+// instructions (four tiles stored and four loaded, four instructions each,
+// whichever path a tile takes), so waiting until at most 32 are outstanding
+// waits for the fetch alone; the next block's first reads of the refilled
+// slots are ordered by the compiler's own counts, which see no later access
+// it does not know about.
+template <typename F, bool RM>
+__global__ __launch_bounds__(256, 1) void bt2_apply_ring(int64_t n, int64_t m, const F *__restrict__ V2,
+                                                         const int64_t *__restrict__ voff, int64_t nsb,
+                                                         int64_t tmax, const F *__restrict__ TF,
+                                                         F *__restrict__ Z, int64_t ldz) {
+    typedef typename v2t<F>::type CV;
+    typedef typename acc4<F>::type A4;
+    constexpr int SHIFT = 4, b = 64;
+    static_assert(HT == 6 && HT * 16 >= b + NBK - 1, "a ring of six tiles covers the window");
+    __shared__ CV Vs[2][VLD * NBK];
+    __shared__ CV Ts[2][NBK * NBK];
+    __shared__ int64_t vb[NBK];
+    __shared__ int64_t vt[NBK];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15;
+    const int64_t j0 = (int64_t)blockIdx.x * SLAB;
+    const int64_t col = j0 + wave * 16 + li;
+    const bool colok = col < m;
+    const int64_t nsw = n - 2;
+    const CV zero = mk2<F>(0.0, 0.0);
+    for (int i = tid; i < 2 * VLD * NBK; i += 256) (&Vs[0][0])[i] = zero;
+    auto fetch = [&](int64_t S, int64_t t, int bufn) {
+#pragma unroll
+        for (int k = 0; k < NBK / 4; ++k) {
+            const int j = wave + 4 * k;
+            CV *dst = &Vs[bufn][j + j * VLD];
+            if (t < vt[j]) wave_copy_to_lds<F>(V2 + 2 * (vb[j] + t) * b, dst, b, lane);
+            else if (lane < b) dst[lane] = zero;  // no such reflector
+        }
+        constexpr int TQ = NBK * NBK / 4;
+        wave_copy_to_lds<F>(TF + 2 * ((S * tmax + t) * NBK * NBK + wave * TQ), &Ts[bufn][wave * TQ], TQ, lane);
+    };
+    // tile addresses: inside the matrix, a wave-uniform base plus this lane's
+    // 32-bit byte offset; otherwise per element, with the zero pad and the sink
+    const int64_t rstr = RM ? ldz : 1;
+    const F *zl = Z + 2 * (RM ? col : col * ldz);
+    int64_t lrow[4];
+    uint32_t lofs[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        lrow[q] = 2 * (int64_t)mfma_row((F)0, lane, q) * rstr;
+        lofs[q] = (uint32_t)sizeof(CV) *
+                  (uint32_t)(RM ? (int64_t)mfma_row((F)0, lane, q) * ldz + (wave * 16 + li)
+                                : (int64_t)mfma_row((F)0, lane, q) + (int64_t)(wave * 16 + li) * ldz);
+    }
+    const bool cols_full = j0 + SLAB <= m;
+    auto tile_base = [&](int64_t row0) {
+        return (char *)Z + sizeof(CV) * (RM ? row0 * ldz + j0 : row0 + j0 * ldz);
+    };
+    // the ring: logical tile i of block t in slot (4 t + i) mod 6, entry q of a
+    // lane's column as (real, imaginary) scalars
+    F zx[HT][4], zy[HT][4];
+    auto load_tile = [&](int64_t rs1, int rtl, int h1, bool full, int slot) __attribute__((always_inline)) {
+        if (full) {
+            const char *base = tile_base(rs1 + rtl * 16);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const CV v = ld2<F>((const F *)(base + lofs[q]));
+                zx[slot][q] = v.x;
+                zy[slot][q] = v.y;
+            }
+        } else {
+            const F *base = zl + 2 * (rs1 + rtl * 16) * rstr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = rtl * 16 + mfma_row((F)0, lane, q);
+                const bool ok = (row < h1) & colok;
+                const CV v = ld2<F>(ok ? base + lrow[q] : (const F *)kZeroPad);
+                zx[slot][q] = v.x;
+                zy[slot][q] = v.y;
+            }
+        }
+    };
+    auto store_tile = [&](int64_t rs1, int rtl, int h1, bool full, int slot) __attribute__((always_inline)) {
+        if (full) {
+            char *base = tile_base(rs1 + rtl * 16);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) st2<F>((F *)(base + lofs[q]), mk2<F>(zx[slot][q], zy[slot][q]));
+        } else {
+            F *base = (F *)zl + 2 * (rs1 + rtl * 16) * rstr;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = rtl * 16 + mfma_row((F)0, lane, q);
+                const bool ok = (row < h1) & colok;
+                st2<F>(ok ? base + lrow[q] : (F *)kSinkPad, mk2<F>(zx[slot][q], zy[slot][q]));
+            }
+        }
+    };
+    auto wvalid = [](int kt, int it) { return !(16 * kt + 15 < 16 * it || 16 * kt > 16 * it + 14 + b); };
+    for (int64_t S = nsb - 1; S >= 0; --S) {
+        const int64_t s0 = S * NBK;
+        const int64_t T0 = (n - 2 - s0) / b + 1;
+        if (s0 + 1 >= n) continue;
+        __syncthreads();
+        if (tid < NBK) {
+            const int64_t sw = s0 + tid;
+            vb[tid] = sw < nsw ? voff[sw] : 0;
+            vt[tid] = sw < nsw ? (n - 2 - sw) / b + 1 : 0;
+        }
+        __syncthreads();
+        {
+            const int h0 = (int)min((int64_t)(HT * 16), n - (s0 + 1));
+            fetch(S, 0, 0);
+#pragma unroll
+            for (int i = 0; i < HT; ++i) load_tile(s0 + 1, i, h0, cols_full && h0 == HT * 16, i);
+            wait_vm_all();
+        }
+        __syncthreads();
+        // one block step with the slot map of phase P; false after the last block
+        // (inlined: the ring must stay in registers)
+        auto block = [&](int64_t t, auto Pc) __attribute__((always_inline)) -> bool {
+            constexpr int P = decltype(Pc)::value;
+            auto sl = [](int i) { return (4 * P + i) % HT; };
+            const int64_t rs = s0 + 1 + t * b;
+            const int h = (int)min((int64_t)(HT * 16), n - rs);
+            const int buf = (int)(t & 1);
+            const bool more = t + 1 < T0 && rs + b < n;
+            const bool full = cols_full && h == HT * 16;
+            const bool nfull = cols_full && n - (rs + b) >= HT * 16;
+            const int h1 = (int)min((int64_t)(HT * 16), n - (rs + b));
+            const CV *V = Vs[buf];
+            const CV *T = Ts[buf];
+            // W = V^H Z in Gauss' three-product form (as in the kernel above)
+            A4 wr[2], wi[2];
+            {
+                A4 p1[2], p2[2], p3[2];
+#pragma unroll
+                for (int it = 0; it < 2; ++it) {
+                    p1[it] = A4{0, 0, 0, 0};
+                    p2[it] = A4{0, 0, 0, 0};
+                    p3[it] = A4{0, 0, 0, 0};
+                }
+                constexpr int NS = HT * 4;
+                CV vc[2], vn[2];
+                auto wload = [&](int st, CV *dst) {
+                    const int kt = st >> 2, q = st & 3;
+#pragma unroll
+                    for (int it = 0; it < 2; ++it)
+                        if (wvalid(kt, it)) dst[it] = V[(16 * kt + mfma_row((F)0, lane, q)) + (16 * it + li) * VLD];
+                };
+                wload(0, vc);
+#pragma unroll
+                for (int st = 0; st < NS; ++st) {
+                    if (st + 1 < NS) wload(st + 1, vn);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int kt = st >> 2, q = st & 3;
+                    const F zre = zx[sl(kt)][q], zim = zy[sl(kt)][q];
+                    const F d = zim - zre;
+#pragma unroll
+                    for (int it = 0; it < 2; ++it) {
+                        if (!wvalid(kt, it)) continue;
+                        p1[it] = mfma16(vc[it].x, zre, p1[it]);
+                        p2[it] = mfma16(vc[it].y, zim, p2[it]);
+                        p3[it] = mfma16(vc[it].x + vc[it].y, d, p3[it]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    vc[0] = vn[0];
+                    vc[1] = vn[1];
+                }
+#pragma unroll
+                for (int it = 0; it < 2; ++it) {
+                    wr[it] = p1[it] + p2[it];
+                    wi[it] = p3[it] + p1[it] - p2[it];
+                }
+            }
+            // V and T of block t + 1 into the other buffer (last read in block
+            // t - 1, before the barrier that closed it)
+            if (more) fetch(S, t + 1, buf ^ 1);
+            // W2 = T W, stored negated
+            A4 ur[2], ui[2];
+            {
+                A4 sw[2];
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt) sw[kt] = wr[kt] + wi[kt];
+                A4 q1[2], q2[2], q3[2];
+#pragma unroll
+                for (int it = 0; it < 2; ++it) {
+                    q1[it] = A4{0, 0, 0, 0};
+                    q2[it] = A4{0, 0, 0, 0};
+                    q3[it] = A4{0, 0, 0, 0};
+                }
+                auto tload = [&](int st) {
+                    const int it = st >= 8 ? 1 : 0, kt = st >= 4 ? 1 : 0, q = st & 3;
+                    return T[(16 * it + li) + (16 * kt + mfma_row((F)0, lane, q)) * NBK];
+                };
+                CV tc = tload(0), tn;
+#pragma unroll
+                for (int st = 0; st < 12; ++st) {
+                    if (st + 1 < 12) tn = tload(st + 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int it = st >= 8 ? 1 : 0, kt = st >= 4 ? 1 : 0, q = st & 3;
+                    q1[it] = mfma16(tc.x, wr[kt][q], q1[it]);
+                    q2[it] = mfma16(tc.y, wi[kt][q], q2[it]);
+                    q3[it] = mfma16(tc.x + tc.y, sw[kt][q], q3[it]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    tc = tn;
+                }
+#pragma unroll
+                for (int it = 0; it < 2; ++it) {
+                    ur[it] = q2[it] - q1[it];
+                    ui[it] = q1[it] + q2[it] - q3[it];
+                }
+            }
+            // Z += V (-W2); each outgoing tile is stored after its last fold
+            // and its slot refilled with the next window's tile
+            {
+                A4 su[2];
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt) su[kt] = ur[kt] + ui[kt];
+                constexpr int NS = HT * 8;
+                auto uvalid = [&](int st) { return wvalid(st >> 3, (st >> 2) & 1); };
+                auto nextv = [&](int st) {
+                    int x = st + 1;
+                    while (x < NS && !uvalid(x)) ++x;
+                    return x;
+                };
+                auto uload = [&](int st) {
+                    const int rtl = st >> 3, kt = (st >> 2) & 1, q = st & 3;
+                    return V[(16 * rtl + li) + (16 * kt + mfma_row((F)0, lane, q)) * VLD];
+                };
+                A4 acc[2][3];
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[p][c] = A4{0, 0, 0, 0};
+                auto fold = [&](int rtl) __attribute__((always_inline)) {
+                    A4 *a = acc[rtl & 1];
+                    const int slot = sl(rtl);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        zx[slot][q] += a[0][q] - a[1][q];
+                        zy[slot][q] += a[2][q] - a[0][q] - a[1][q];
+                    }
+                    a[0] = A4{0, 0, 0, 0};
+                    a[1] = A4{0, 0, 0, 0};
+                    a[2] = A4{0, 0, 0, 0};
+                    if (rtl < SHIFT) {
+                        store_tile(rs, rtl, h, full, slot);
+                        if (more) load_tile(rs + b, rtl + HT - SHIFT, h1, nfull, slot);
+                    }
+                };
+                CV uc = uload(nextv(-1)), un;
+                int last_rtl = -1;
+#pragma unroll
+                for (int st = 0; st < NS; ++st) {
+                    if (!uvalid(st)) continue;
+                    const int nx = nextv(st);
+                    if (nx < NS) un = uload(nx);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int rtl = st >> 3, kt = (st >> 2) & 1, q = st & 3;
+                    A4 *a = acc[rtl & 1];
+                    a[0] = mfma16(uc.x, ur[kt][q], a[0]);
+                    a[1] = mfma16(uc.y, ui[kt][q], a[1]);
+                    a[2] = mfma16(uc.x + uc.y, su[kt][q], a[2]);
+                    if (rtl != last_rtl) {  // first step of row tile rtl
+                        if (last_rtl >= 0) fold(last_rtl);
+                        last_rtl = rtl;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    uc = un;
+                }
+                fold(last_rtl);
+            }
+            if (more) {
+                // the V/T fetch is older than the 32 tile accesses after it
+                asm volatile("s_waitcnt vmcnt(32)" ::: "memory");
+                __syncthreads();
+                return true;
+            }
+#pragma unroll
+            for (int i = SHIFT; i < HT; ++i) store_tile(rs, i, h, full, sl(i));
+            return false;
+        };
+        for (int64_t t = 0;; t += 3) {
+            if (!block(t, std::integral_constant<int, 0>{})) break;
+            if (!block(t + 1, std::integral_constant<int, 1>{})) break;
+            if (!block(t + 2, std::integral_constant<int, 2>{})) break;
+        }
+    }
+}
+
 }  // namespace
 
 bool bt2_rowmajor_ok(int b) { return b >= 16 && b <= BMAX && b % 16 == 0; }
@@ -862,11 +1170,24 @@ int bt2_apply_t(int64_t n, int b, int64_t m, const F *V2, const int64_t *voff, F
                                tmax, TFw, Z, ldz);                                                           \
     else hipLaunchKernelGGL((bt2_apply_pipe<F, SH, false>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb,   \
                             tmax, TFw, Z, ldz);
+    // band 64: the ring-window kernel (BDG_BT2_RING=0 selects the pipelined one)
+    static const bool ring_env = [] {
+        const char *v = getenv("BDG_BT2_RING");
+        return !(v && v[0] == '0');
+    }();
     switch (b % 16 == 0 ? b / 16 : 0) {
         case 1: BDG_BT2_PIPE(1) break;
         case 2: BDG_BT2_PIPE(2) break;
         case 3: BDG_BT2_PIPE(3) break;
-        case 4: BDG_BT2_PIPE(4) break;
+        case 4:
+            if (!ring_env) {
+                BDG_BT2_PIPE(4)
+            } else if (rm) {
+                hipLaunchKernelGGL((bt2_apply_ring<F, true>), grid, dim3(256), 0, s, n, m, V2, voff, nsb, tmax, TFw, Z, ldz);
+            } else {
+                hipLaunchKernelGGL((bt2_apply_ring<F, false>), grid, dim3(256), 0, s, n, m, V2, voff, nsb, tmax, TFw, Z, ldz);
+            }
+            break;
         default: hipLaunchKernelGGL((bt2_apply<F, 0, 2>), grid, dim3(256), 0, s, n, b, m, V2, voff, nsb, tmax, TFw, Z, ldz); break;
     }
 #undef BDG_BT2_PIPE
