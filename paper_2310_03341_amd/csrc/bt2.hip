@@ -781,13 +781,13 @@ __device__ __align__(16) double kSinkPad[2];
 // with the map as a compile-time constant.  The window is kept as complex
 // pairs, the layout a 16-byte load delivers.
 //
-// Counter discipline: the V/T fetch for block t + 1 is issued after the
-// block's W product, and it is followed by exactly 32 vector memory
-// instructions (four tiles stored and four loaded, four instructions each,
-// whichever path a tile takes), so waiting until at most 32 are outstanding
-// waits for the fetch alone; the next block's first reads of the refilled
-// slots are ordered by the compiler's own counts, which see no later access
-// it does not know about.
+// Counter discipline: the V/T fetch for block t + 1 is issued at the start
+// of block t and followed by exactly 32 vector memory instructions (four
+// tiles stored and four loaded, four instructions each, whichever path a tile
+// takes), so waiting until at most 32 are outstanding waits for the fetch
+// alone.  The next block's first reads of the refilled slots are counted by
+// the compiler, which does not see the fetch issued after them; its counts
+// then wait for a few more of the older accesses, never for the fetch.
 template <typename F, bool RM>
 __global__ __launch_bounds__(256, 1) void bt2_apply_ring(int64_t n, int64_t m, const F *__restrict__ V2,
                                                          const int64_t *__restrict__ voff, int64_t nsb,
@@ -911,6 +911,9 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_ring(int64_t n, int64_t m, c
             const int h1 = (int)min((int64_t)(HT * 16), n - (rs + b));
             const CV *V = Vs[buf];
             const CV *T = Ts[buf];
+            // V and T of block t + 1 into the other buffer (last read in block
+            // t - 1, before the barrier that closed it)
+            if (more) fetch(S, t + 1, buf ^ 1);
             // W = V^H Z in Gauss' three-product form (as in the kernel above)
             A4 wr[2], wi[2];
             {
@@ -954,9 +957,6 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_ring(int64_t n, int64_t m, c
                     wi[it] = p3[it] + p1[it] - p2[it];
                 }
             }
-            // V and T of block t + 1 into the other buffer (last read in block
-            // t - 1, before the barrier that closed it)
-            if (more) fetch(S, t + 1, buf ^ 1);
             // W2 = T W, stored negated
             A4 ur[2], ui[2];
             {
