@@ -32,8 +32,8 @@ PEAK_HBM = 8.0e12
 # 1 GiB device copy in the same run.  Valid only for the kernel source it was
 # measured on (sha256 of csrc/bt2.hip) and the same workload; otherwise the
 # bench reports null.
-BT2_TRAFFIC = {"sha256": "b84c137f71fb65e4d9ad793c602688f2e8f8d033a52282fae7298d60496f667d",
-               "n": 27648, "m_bt": 13824, "fetch_bytes": 4223217647989.7, "write_bytes": 2644664468736.0}
+BT2_TRAFFIC = {"sha256": "021c4ca7c0a1d7d1e73860284fe7fdd89b7e6bea531b1098ccdfad55b34cf410",
+               "n": 27648, "m_bt": 13824, "fetch_bytes": 2729697403969.1, "write_bytes": 2644665591520.0}
 
 
 def _bt2_source_sha() -> str:
