@@ -764,6 +764,28 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_pipe(int64_t n, int b_rt, in
     }
 }
 
+// Steps (row tile rt, column tile kt, k slice q) of the update product
+// Z += V (-W2) that meet the V parallelogram of band width B, and for each step
+// the next such step: next[st + 1] for st = -1 .. HT * 8 - 1 (HT * 8 when none
+// is left).  Built at compile time: a search loop in the unrolled product
+// stays a run-time loop of scalar compares and branches.
+template <int B>
+struct UpdSteps {
+    static constexpr int NS = HT * 8;
+    int next[NS + 1];
+    static constexpr bool valid(int st) {
+        const int rt = st >> 3, kt = (st >> 2) & 1;
+        return !(16 * rt + 15 < 16 * kt || 16 * rt > 16 * kt + 14 + B);
+    }
+    constexpr UpdSteps() : next{} {
+        int nx = NS;
+        for (int st = NS - 1; st >= -1; --st) {
+            next[st + 1] = nx;
+            if (st >= 0 && valid(st)) nx = st;
+        }
+    }
+};
+
 // Sixteen zero bytes that Z entries outside the matrix are loaded from, and a
 // sink their stores go to, so a tile load or store is always the same four
 // instructions (no branch, no select).
@@ -1000,11 +1022,8 @@ __global__ __launch_bounds__(256, 1) void bt2_apply_ring(int64_t n, int64_t m, c
                 for (int kt = 0; kt < 2; ++kt) su[kt] = ur[kt] + ui[kt];
                 constexpr int NS = HT * 8;
                 auto uvalid = [&](int st) { return wvalid(st >> 3, (st >> 2) & 1); };
-                auto nextv = [&](int st) {
-                    int x = st + 1;
-                    while (x < NS && !uvalid(x)) ++x;
-                    return x;
-                };
+                constexpr UpdSteps<b> usteps{};
+                auto nextv = [&](int st) { return usteps.next[st + 1]; };
                 auto uload = [&](int st) {
                     const int rtl = st >> 3, kt = (st >> 2) & 1, q = st & 3;
                     return V[(16 * rtl + li) + (16 * kt + mfma_row((F)0, lane, q)) * VLD];
