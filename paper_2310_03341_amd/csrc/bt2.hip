@@ -800,8 +800,10 @@ __device__ __align__(16) double kSinkPad[2];
 // once with the next window's tile, straight from memory: no registers hold
 // prefetched tiles, and nothing is copied at the end of a block step.  The
 // slot map repeats every three blocks, so the block loop is unrolled by three
-// with the map as a compile-time constant.  The window is kept as complex
-// pairs, the layout a 16-byte load delivers.
+// with the map as a compile-time constant.  The window is kept as (real,
+// imaginary) scalars, which the two halves of a 16-byte load fill in place.
+// Lane offsets within a tile are 32-bit: the launcher uses this kernel only
+// when 16 rows and 64 columns of Z span less than 2^31 bytes.
 //
 // Counter discipline: the V/T fetch for block t + 1 is issued at the start
 // of block t and followed by exactly 32 vector memory instructions (four
@@ -1199,7 +1201,7 @@ int bt2_apply_t(int64_t n, int b, int64_t m, const F *V2, const int64_t *voff, F
         case 2: BDG_BT2_PIPE(2) break;
         case 3: BDG_BT2_PIPE(3) break;
         case 4:
-            if (!ring_env) {
+            if (!ring_env || (int64_t)sizeof(F) * 2 * (16 + SLAB * ldz) >= ((int64_t)1 << 31)) {
                 BDG_BT2_PIPE(4)
             } else if (rm) {
                 hipLaunchKernelGGL((bt2_apply_ring<F, true>), grid, dim3(256), 0, s, n, m, V2, voff, nsb, tmax, TFw, Z, ldz);
