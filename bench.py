@@ -32,8 +32,8 @@ PEAK_HBM = 8.0e12
 # 1 GiB device copy in the same run.  Valid only for the kernel source it was
 # measured on (sha256 of csrc/bt2.hip) and the same workload; otherwise the
 # bench reports null.
-BT2_TRAFFIC = {"sha256": "4075a3774228f9bd4cbe1a9b5c24a73789d54bd30bc352e3d484cc7c436cf6cb",
-               "n": 27648, "m_bt": 13824, "fetch_bytes": 2752906622831.6, "write_bytes": 2644665735072.0}
+BT2_TRAFFIC = {"sha256": "261b228058abb244f85f7984d0fdc73869bf35f5faa24088de71b1f9b2bedba0",
+               "n": 27648, "m_bt": 13824, "fetch_bytes": 2726300789783.9, "write_bytes": 2644665558752.0}
 
 
 def _bt2_source_sha() -> str:
