@@ -158,3 +158,53 @@ def test_hb2st_and_bt2(dev, n, band):
         assert np.abs(Zh.conj().T @ Zh - np.eye(n)).max() < 1e-12, rowmajor
         Zs.append(Zh)
     assert np.abs(Zs[0] - Zs[1]).max() < 1e-12
+
+
+_CHILD_BT2 = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, sys.argv[2])
+from paper_2310_03341_amd import api
+d = sys.argv[1]
+dev = torch.device("cuda:0")
+ld = lambda k: torch.from_numpy(np.load(d + "/" + k + ".npy")).to(dev)
+e, Y, V2, tau2, voff = ld("e"), ld("Y"), ld("V2"), ld("tau2"), ld("voff")
+Yc = api.colmajor(Y.shape[0], Y.shape[1], torch.float64, dev)
+Yc.copy_(Y)
+n = Y.shape[0]
+for rm in (True, False):
+    Z = api.stage_bt2(e, Yc, 0, n, V2, tau2, voff, 64, rowmajor=rm)
+    torch.cuda.synchronize()
+    np.save(d + "/Z%d.npy" % int(rm), Z.cpu().numpy())
+"""
+
+
+def test_bt2_band64_pipelined_kernel_matches_ring(dev, tmp_path):
+    """Band 64 has two back-transformation-2 kernels: the ring-window one (the
+    default) and the pipelined one, selected by BDG_BT2_RING=0 (read once per
+    process, hence the child process).  Both apply the same block reflectors
+    in the same order; their outputs agree to rounding, on both Z routes."""
+    import os
+    import subprocess
+    import sys
+    import torch
+    from paper_2310_03341_amd import api
+    n, band = 301, 64
+    ABh = random_band(n, band, seed=7)
+    AB = torch.from_numpy(ABh).to(dev)
+    d, e, V2, tau2, voff = api.stage_hb2st(AB, band)
+    torch.cuda.synchronize()
+    ea = torch.from_numpy(np.abs(e.cpu().numpy()[: n - 1]).copy()).to(dev)
+    W, Y = api.stage_stedc(d, ea)
+    torch.cuda.synchronize()
+    for k, v in (("e", e), ("Y", Y), ("V2", V2), ("tau2", tau2), ("voff", voff)):
+        np.save(str(tmp_path / (k + ".npy")), v.cpu().numpy())
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, BDG_BT2_RING="0")
+    r = subprocess.run([sys.executable, "-c", _CHILD_BT2, str(tmp_path), root], env=env,
+                       capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0, r.stderr[-2000:]
+    for rm in (True, False):
+        Zr = api.stage_bt2(e, Y, 0, n, V2, tau2, voff, band, rowmajor=rm)
+        torch.cuda.synchronize()
+        Zp = np.load(str(tmp_path / ("Z%d.npy" % int(rm))))
+        assert np.abs(Zr.cpu().numpy() - Zp).max() < 1e-12, rm
